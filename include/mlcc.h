@@ -1,0 +1,236 @@
+/*
+ * libmlcc -- multilevel CC2 / CCSD (MLCC2, MLCCSD with CCS/CCSD levels) on
+ * Cholesky-decomposed electron-repulsion integrals, for AMD MI355X (gfx950).
+ *
+ * Method: Folkestad, Kjonstad, Goletto, Koch, "Multilevel CC2 and CCSD in
+ * reduced orbital spaces" (arXiv 2006.05226).  Section numbers below refer to
+ * that paper: Sec. 2.1 (the MLCC2 and MLCCSD models, their ground-state
+ * equations and Jacobians) and Appendix A (the equations in terms of the
+ * Cholesky vectors: X1 basis, Fock matrix, energy, Omega vectors, Jacobian
+ * transformations).
+ *
+ * ---------------------------------------------------------------------------
+ * Conventions shared by every call
+ * ---------------------------------------------------------------------------
+ * Orbitals.  n = n_occ + n_vir molecular orbitals, occupied first.  Inside each
+ *   block the active orbitals come first: active occupied 0..n_occ_act-1,
+ *   active virtual n_occ..n_occ+n_vir_act-1.  The active-active Fock blocks are
+ *   diagonal (semicanonical basis, Sec. 2.1); the library takes the MO Fock
+ *   matrix to be diag(eps) and the one-electron integrals to be
+ *   h = diag(eps) - G(D_HF), so that the reference is a canonical
+ *   Hartree-Fock state of the Hamiltonian defined by (h, L).
+ * Cholesky vectors.  L[J][p][q], row major, J < n_chol, L[J][p][q] == L[J][q][p],
+ *   g_pqrs = sum_J L[J][p][q] L[J][r][s] (Appendix A).
+ * Singles.  t1 / omega1 / c1 / sigma1 are [n_vir][n_occ] (all orbitals).
+ * Doubles.  Active space only, M = n_occ_act * n_vir_act pairs with pair index
+ *   ai = a * n_occ_act + i.  A doubles array is the full symmetric M x M matrix
+ *   x[ai][bj] == x[bj][ai] with X2 = 1/2 sum x_aibj E_ai E_bj, projected with
+ *   the biorthonormal basis <mu_aibj|E_ck E_dl|HF> = d(ai,ck)d(bj,dl) +
+ *   d(ai,dl)d(bj,ck).
+ * Excitation vectors.  dim = n_vir*n_occ (+ M*M for MLCC2/MLCCSD in the full
+ *   space): singles block followed by the doubles block.  Several vectors are
+ *   stored back to back, [n_vec][dim].
+ * Pointers.  Every array argument may be host memory or device memory on the
+ *   context's GPU; the library tells them apart with hipPointerGetAttributes.
+ *   The caller owns every pointer it passes; inputs are copied before a call
+ *   returns, outputs are written only into the caller's buffers and only when
+ *   the call returns MLCC_OK (MLCC_E_NOCONV also fills best-so-far values).
+ * Streams.  All device work of a context is ordered on the stream given at
+ *   context creation; every call except mlcc_submit/mlcc_poll has completed
+ *   its device work when it returns.
+ * Threading.  One host thread at a time per context (and its problems);
+ *   mlcc_submit / mlcc_poll are thread safe.
+ * Units.  Hartree.
+ * Errors.  No exception or abort crosses this interface; a negative status is
+ *   returned and mlcc_last_error() describes it.
+ */
+#ifndef MLCC_H
+#define MLCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mlcc_status;
+#define MLCC_OK 0
+#define MLCC_PENDING 1       /* mlcc_poll: request not finished yet */
+#define MLCC_E_ARG (-1)      /* invalid argument (dimensions, NULL, flags) */
+#define MLCC_E_OOM (-2)      /* device memory or the HBM budget exhausted */
+#define MLCC_E_NOCONV (-3)   /* iteration limit reached */
+#define MLCC_E_NUMERIC (-4)  /* NaN/Inf in inputs or iterates */
+#define MLCC_E_DEVICE (-5)   /* HIP runtime error */
+#define MLCC_E_BUSY (-6)     /* server queue full */
+#define MLCC_E_STATE (-7)    /* call out of order (e.g. no amplitudes yet) */
+
+/* Models (Sec. 2.1). */
+#define MLCC_CCS 0     /* X = X1 */
+#define MLCC_MLCC2 1   /* X = X1 + S2, S2 in the active space, perturbative */
+#define MLCC_MLCCSD 2  /* CCS/CCSD: X = X1 + T2, T2 in the active space */
+
+/* Arithmetic of the Cholesky-index contractions (the MFMA GEMMs).  Amplitude
+ * and denominator updates, DIIS, Davidson and energies are FP64 always. */
+#define MLCC_FP64 0
+#define MLCC_FP32 1
+
+typedef struct mlcc_context mlcc_context;
+typedef struct mlcc_problem mlcc_problem;
+typedef struct mlcc_server mlcc_server;
+
+typedef struct {
+  int32_t n_occ, n_vir, n_chol;   /* N_o, N_v, N_J */
+  int32_t n_occ_act, n_vir_act;   /* active prefixes (ignored for MLCC_CCS) */
+  int32_t model;                  /* MLCC_CCS | MLCC_MLCC2 | MLCC_MLCCSD */
+  int32_t precision;              /* MLCC_FP64 | MLCC_FP32 */
+  const double *L;                /* [n_chol][n][n], symmetric in the last two */
+  const double *eps;              /* [n] orbital energies in the order above */
+} mlcc_problem_desc;
+
+typedef struct {
+  double tol;             /* ground state: ||Omega||_2; Davidson: residual norm */
+  int32_t max_iter;       /* iteration limit */
+  int32_t diis_dim;       /* DIIS history length (ground state), 0 -> 8 */
+  int32_t max_subspace;   /* Davidson subspace before collapse, 0 -> 20*n_roots */
+  int32_t n_guess;        /* Davidson start vectors, 0 -> n_roots + 2 */
+  int32_t effective;      /* MLCC2 Davidson on the singles space with the
+                             omega-dependent effective Jacobian (Sec. 2.1: the
+                             doubles-doubles block is diagonal) */
+} mlcc_solver_opts;
+
+typedef struct {
+  int32_t iterations;
+  int32_t converged;      /* 1 if every quantity met opts.tol */
+  double residual;        /* final ||Omega|| or max root residual */
+  double energy;          /* correlation energy at the final amplitudes */
+  int32_t complex_roots;  /* number of returned roots that had a complex pair */
+  int32_t transforms;     /* Jacobian transformations performed */
+} mlcc_info;
+
+/* ---- context -------------------------------------------------------------
+ * device: HIP ordinal.  hip_stream: a hipStream_t of that device (NULL = the
+ * library creates its own).  hbm_budget: bytes the context may allocate on
+ * the device (0 = no limit beyond the device's free memory). */
+mlcc_status mlcc_context_create(int device, void *hip_stream, uint64_t hbm_budget,
+                                mlcc_context **ctx);
+mlcc_status mlcc_context_destroy(mlcc_context *ctx);
+/* Message of the last error on this context (or of the last failed create when
+ * ctx is NULL).  Valid until the next call on the context. */
+const char *mlcc_last_error(mlcc_context *ctx);
+/* Device bytes currently allocated by the context. */
+uint64_t mlcc_context_bytes(mlcc_context *ctx);
+
+/* ---- problems --------------------------------------------------------------
+ * Copies L and eps to the device, forms h (see Conventions) and prepares the
+ * packed blocks of L the model needs.  Errors: MLCC_E_ARG (dimensions < 1,
+ * active > total, NULL pointers), MLCC_E_NUMERIC (NaN/Inf in eps),
+ * MLCC_E_OOM. */
+mlcc_status mlcc_problem_create(mlcc_context *ctx, const mlcc_problem_desc *desc,
+                                mlcc_problem **prob);
+mlcc_status mlcc_problem_destroy(mlcc_problem *prob);
+/* dims[0..7] = n_occ, n_vir, n_chol, n_occ_act, n_vir_act, M, singles dim,
+ * full-space excitation dim. */
+mlcc_status mlcc_problem_dims(const mlcc_problem *prob, int64_t dims[8]);
+
+/* Set the amplitudes at which mlcc_residual / mlcc_jacobian_transform are
+ * evaluated.  t1 [n_vir][n_occ]; x2 [M][M] symmetric: the MLCCSD t2, or an
+ * independent MLCC2 s2 (NULL for MLCC2 = use the analytic s2 of t1). */
+mlcc_status mlcc_set_amplitudes(mlcc_problem *prob, const double *t1, const double *x2);
+
+/* Omega vector (Sec. 2.1 eqs. mlcc2_1/2, mlccsd_1/2; Appendix A.1) at the
+ * current amplitudes.  omega1 [n_vir][n_occ]; omega2 [M][M] or NULL; x2_out
+ * [M][M] or NULL receives the doubles used (analytic s2 for MLCC2 when no s2
+ * was set); e_corr (or NULL) receives the correlation energy (Appendix A.1).
+ * MLCC_E_STATE if no amplitudes were set. */
+mlcc_status mlcc_residual(mlcc_problem *prob, double *omega1, double *omega2,
+                          double *x2_out, double *e_corr);
+
+/* Ground state: DIIS-accelerated quasi-Newton on Omega = 0 (Sec. 2.1); MLCC2
+ * re-solves s2 analytically each iteration.  Starts from the current t1 (zero
+ * if none was set) and leaves the converged amplitudes set.  t1_out may be
+ * NULL.  MLCC_E_NOCONV after opts.max_iter iterations (outputs filled). */
+mlcc_status mlcc_ground_state(mlcc_problem *prob, const mlcc_solver_opts *opts,
+                              double *t1_out, double *e_corr, mlcc_info *info);
+
+/* sigma = A c for n_vec vectors [n_vec][dim] (full space, Appendix A.2) at the
+ * current amplitudes.  The transformation is the derivative of the Omega
+ * vector; for MLCC2 the doubles-doubles block is eps_aibj (Sec. 2.1). */
+mlcc_status mlcc_jacobian_transform(mlcc_problem *prob, int32_t n_vec, const double *c,
+                                    double *sigma);
+
+/* MLCC2 effective singles transformation at frequency omega:
+ * s1 = A11 c1 + A12 (omega - eps)^-1 A21 c1   (A22 is diagonal, Sec. 2.1).
+ * c1, s1: [n_vec][n_vir*n_occ]. */
+mlcc_status mlcc_jacobian_transform_eff(mlcc_problem *prob, double omega, int32_t n_vec,
+                                        const double *c1, double *s1);
+
+/* Lowest n_roots excitation energies (eigenvalues of the Jacobian, Sec. 2.1)
+ * by a nonsymmetric Davidson method at the current amplitudes.  omega
+ * [n_roots]; r1 [n_roots][n_vir*n_occ] (singles part of the unit-norm right
+ * eigenvectors) or NULL. */
+mlcc_status mlcc_davidson_solve(mlcc_problem *prob, int32_t n_roots,
+                                const mlcc_solver_opts *opts, double *omega, double *r1,
+                                mlcc_info *info);
+
+/* ---- serving: continuous batching of excitation solves ---------------------
+ * A server owns a scheduler thread on the context's device.  Requests are
+ * admitted when their estimated HBM footprint fits in the budget left and a
+ * slot is free; admitted requests advance together, one solver step each per
+ * scheduler round, so the work of requests of different sizes overlaps on the
+ * GPU.  Each request runs ground state then Davidson. */
+typedef struct {
+  int32_t max_slots;        /* requests on the device at once (0 -> 8) */
+  int32_t max_queue;        /* waiting requests before MLCC_E_BUSY (0 -> 1024) */
+  uint64_t hbm_budget;      /* bytes for admitted requests (0 -> context budget) */
+} mlcc_server_opts;
+
+typedef struct {
+  mlcc_status status;       /* MLCC_OK, MLCC_E_NOCONV, ... of the finished solve */
+  int32_t n_roots;
+  double omega[16];         /* first min(n_roots, 16) excitation energies */
+  double e_corr;
+  double t_submit, t_admit, t_done;  /* seconds on the server's clock */
+  int32_t gs_iterations, es_iterations;
+} mlcc_result;
+
+mlcc_status mlcc_server_create(mlcc_context *ctx, const mlcc_server_opts *opts,
+                               mlcc_server **srv);
+/* Drains admitted work, cancels waiting requests, joins the thread. */
+mlcc_status mlcc_server_destroy(mlcc_server *srv);
+/* Copies the request's inputs (host or device) and queues it.  MLCC_E_BUSY if
+ * the queue is full; MLCC_E_OOM if its footprint exceeds the server budget
+ * (it could never be admitted); MLCC_E_ARG for invalid descriptors. */
+mlcc_status mlcc_submit(mlcc_server *srv, const mlcc_problem_desc *desc, int32_t n_roots,
+                        const mlcc_solver_opts *gs_opts, const mlcc_solver_opts *es_opts,
+                        uint64_t *ticket);
+/* MLCC_PENDING until the request is done, then MLCC_OK and *out filled (the
+ * ticket is released).  MLCC_E_ARG for an unknown ticket. */
+mlcc_status mlcc_poll(mlcc_server *srv, uint64_t ticket, mlcc_result *out);
+/* Estimated device bytes of one request (admission uses this). */
+uint64_t mlcc_request_footprint(const mlcc_problem_desc *desc, int32_t n_roots,
+                                const mlcc_solver_opts *es_opts);
+
+/* ---- kernel-level entry points (used by the kernel unit tests) -------------
+ * Batched, batch-reduced strided GEMM on the device, the engine every
+ * Cholesky-index contraction runs on:
+ *   C_z[m][n] = alpha * sum_{r<R} sum_{k<K} A_zr[m][k] B_zr[k][n] + beta * C_z[m][n]
+ * with A_zr[m][k] at A + z*sA[3] + r*sA[2] + m*sA[0] + k*sA[1] and likewise
+ * B (sB = {k, n, r, z}) and C (sC = {m, n, z}).  Device pointers only.
+ * prec: MLCC_FP64 (FP64 MFMA) or MLCC_FP32 (A, B, C float; FP32 MFMA). */
+mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int64_t K,
+                      int64_t R, int64_t Z, double alpha, const void *A, const int64_t sA[4],
+                      const void *B, const int64_t sB[4], double beta, void *C,
+                      const int64_t sC[3]);
+
+/* Internal intermediates for step-by-step parity tests.  which: 0 = F~ [n][n],
+ * 1 = L~ [n_chol][n][n] (FP64 copy), 2 = g~_aibj [M][M], 3 = t1 [n_vir][n_occ],
+ * 4 = doubles [M][M].  out is host memory of the stated size.  The values are
+ * those of the last mlcc_residual / transform call. */
+mlcc_status mlcc_debug_get(mlcc_problem *prob, int32_t which, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLCC_H */

@@ -1,0 +1,469 @@
+// Element-wise and reduction kernels of the MLCC path: packing of Cholesky
+// blocks, the orbital-energy denominator updates of the doubles (Sec. 2.1: the
+// MLCC2 doubles equation has the analytic solution s = -g~/eps in the
+// semicanonical basis), the u = 2x - x(i<->j) combinations, symmetrisation of
+// the doubles part of the Jacobian transformation, quasi-Newton steps, the
+// Davidson preconditioner and FP64 dot products.
+//
+// These are HBM-bound: grid-stride loops with consecutive lanes on consecutive
+// addresses; reductions are two-pass with a fixed order (deterministic).
+#include "mlcc_internal.h"
+
+namespace mlcc {
+namespace k {
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned blocks_for(int64_t n, int64_t cap = 16384) {
+  int64_t b = (n + TPB - 1) / TPB;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (unsigned)b;
+}
+
+#define GRID_STRIDE(i, n)                                                   \
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (n); \
+       i += (int64_t)gridDim.x * blockDim.x)
+
+template <typename TD, typename TS>
+__global__ void k_pack2d(TD *dst, const TS *src, int64_t Z, int64_t sz, int64_t rows,
+                         int64_t cols, int64_t ld) {
+  const int64_t per = rows * cols;
+  GRID_STRIDE(t, Z * per) {
+    const int64_t z = t / per, rem = t - z * per;
+    const int64_t r = rem / cols, c = rem - r * cols;
+    dst[t] = (TD)src[z * sz + r * ld + c];
+  }
+}
+
+// transposing pack through a 32x32 LDS tile per (z, tile)
+template <typename TD, typename TS>
+__global__ void k_pack2d_t(TD *dst, const TS *src, int64_t sz, int64_t rows, int64_t cols,
+                           int64_t ld) {
+  __shared__ TD tile[32][33];
+  const int64_t z = blockIdx.z;
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + y, c = c0 + tx;
+    if (r < rows && c < cols) tile[y][tx] = (TD)src[z * sz + r * ld + c];
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t c = c0 + y, r = r0 + tx;
+    if (r < rows && c < cols) dst[z * rows * cols + c * rows + r] = tile[tx][y];
+  }
+}
+
+template <typename TD, typename TS>
+__global__ void k_convert(TD *dst, const TS *src, int64_t n) {
+  GRID_STRIDE(i, n) dst[i] = (TD)src[i];
+}
+
+__global__ void k_axpby(int64_t n, double a, const double *x, double b, double *y) {
+  GRID_STRIDE(i, n) y[i] = a * x[i] + b * y[i];
+}
+template <typename T>
+__global__ void k_lincomb(int64_t n, double a, const T *x, double b, const T *y, T *out) {
+  GRID_STRIDE(i, n) out[i] = (T)(a * (double)x[i] + b * (double)y[i]);
+}
+__global__ void k_scale(int64_t n, double a, double *x) {
+  GRID_STRIDE(i, n) x[i] *= a;
+}
+__global__ void k_fill(double *x, int64_t n, double v) {
+  GRID_STRIDE(i, n) x[i] = v;
+}
+
+// block-level sum in fixed order
+__device__ double block_sum(double v) {
+  __shared__ double sh[TPB];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+template <typename TA, typename TB>
+__global__ void k_dot_partial(int64_t n, const TA *x, const TB *y, double *part) {
+  double s = 0.0;
+  GRID_STRIDE(i, n) s += (double)x[i] * (double)y[i];
+  const double b = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+__global__ void k_sum_final(int nb, const double *part, double *res) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += TPB) s += part[i];
+  const double b = block_sum(s);
+  if (threadIdx.x == 0) *res = b;
+}
+
+__global__ void k_nonfinite_partial(int64_t n, const double *x, double *part) {
+  double s = 0.0;
+  GRID_STRIDE(i, n) s += (isfinite(x[i]) ? 0.0 : 1.0);
+  const double b = block_sum(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = b;
+}
+
+// s = -g/eps_aibj, u = 2 s - s(i<->j).  ai = a*o + i; s(i<->j)[ai][bj] = s[aj][bi]
+// and eps_ajbi = eps_aibj.
+template <typename TG, typename TU>
+__global__ void k_mlcc2_s_u(int o, int v, const TG *g, const double *eps_ai, double *s, TU *u) {
+  const int64_t M = (int64_t)o * v;
+  GRID_STRIDE(t, M * M) {
+    const int64_t ai = t / M, bj = t - ai * M;
+    const int64_t a = ai / o, i = ai - a * o, b = bj / o, j = bj - b * o;
+    const double den = eps_ai[ai] + eps_ai[bj];
+    const double sv = -(double)g[t] / den;
+    const double sx = -(double)g[(a * o + j) * M + (b * o + i)] / den;
+    if (s) s[t] = sv;
+    u[t] = (TU)(2.0 * sv - sx);
+  }
+}
+
+template <typename TU>
+__global__ void k_u_of(int o, int v, const double *x, TU *u) {
+  const int64_t M = (int64_t)o * v;
+  GRID_STRIDE(t, M * M) {
+    const int64_t ai = t / M, bj = t - ai * M;
+    const int64_t a = ai / o, i = ai - a * o, b = bj / o, j = bj - b * o;
+    u[t] = (TU)(2.0 * x[t] - x[(a * o + j) * M + (b * o + i)]);
+  }
+}
+
+// out = G + G^T + eps_aibj * c  through 32x32 LDS tiles (coalesced transpose)
+template <typename TG>
+__global__ void k_sym_plus_diag(int64_t M, const TG *G, const double *eps_ai, const double *c,
+                                double *out) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  // load G[c0.., r0..] transposed into tile
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t rr = c0 + y, cc = r0 + tx;
+    tile[y][tx] = (rr < M && cc < M) ? (double)G[rr * M + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + y, cc = c0 + tx;
+    if (r < M && cc < M) {
+      const int64_t off = r * M + cc;
+      double v = (double)G[off] + tile[tx][y];
+      if (c) v += (eps_ai[r] + eps_ai[cc]) * c[off];
+      out[off] = v;
+    }
+  }
+}
+
+template <typename TG, typename TO>
+__global__ void k_sym_div(int64_t M, const TG *G, const double *eps_ai, double w, TO *out) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t rr = c0 + y, cc = r0 + tx;
+    tile[y][tx] = (rr < M && cc < M) ? (double)G[rr * M + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + y, cc = c0 + tx;
+    if (r < M && cc < M) {
+      const int64_t off = r * M + cc;
+      out[off] = (TO)(((double)G[off] + tile[tx][y]) / (w - (eps_ai[r] + eps_ai[cc])));
+    }
+  }
+}
+
+template <typename TG>
+__global__ void k_mlcc2_omega2(int64_t M, const TG *g, const double *eps_ai, const double *s,
+                               double *out) {
+  GRID_STRIDE(t, M * M) {
+    const int64_t ai = t / M, bj = t - ai * M;
+    out[t] = (double)g[t] + (eps_ai[ai] + eps_ai[bj]) * s[t];
+  }
+}
+
+__global__ void k_qn_singles(int V, int O, const double *eps, const double *om, double *t) {
+  GRID_STRIDE(x, (int64_t)V * O) {
+    const int64_t A = x / O, I = x - A * O;
+    t[x] -= om[x] / (eps[O + A] - eps[I]);
+  }
+}
+__global__ void k_qn_doubles(int64_t M, const double *eps_ai, const double *om, double *t) {
+  GRID_STRIDE(x, M * M) {
+    const int64_t ai = x / M, bj = x - ai * M;
+    t[x] -= om[x] / (eps_ai[ai] + eps_ai[bj]);
+  }
+}
+
+__global__ void k_precond(int64_t n1, int64_t M, const double *eps_vo, const double *eps_ai,
+                          double w, const double *r, double *out) {
+  GRID_STRIDE(x, n1 + M * M) {
+    double d;
+    if (x < n1) {
+      d = eps_vo[x];
+    } else {
+      const int64_t y = x - n1, ai = y / M, bj = y - ai * M;
+      d = eps_ai[ai] + eps_ai[bj];
+    }
+    double den = w - d;
+    if (fabs(den) < 1e-8) den = den < 0 ? -1e-8 : 1e-8;
+    out[x] = r[x] / den;
+  }
+}
+
+__global__ void k_denominators(int O, int V, int o, int v, const double *eps, double *eps_ai,
+                               double *eps_vo) {
+  GRID_STRIDE(x, (int64_t)V * O) {
+    const int64_t A = x / O, I = x - A * O;
+    eps_vo[x] = eps[O + A] - eps[I];
+  }
+  GRID_STRIDE(x, (int64_t)v * o) {
+    const int64_t a = x / o, i = x - a * o;
+    eps_ai[x] = eps[O + a] - eps[i];
+  }
+}
+
+template <typename T>
+__global__ void k_occ_trace(int64_t J, int64_t n, int O, const T *X, double *d) {
+  GRID_STRIDE(K, J) {
+    double s = 0.0;
+    const T *x = X + K * n * n;
+    for (int I = 0; I < O; ++I) s += (double)x[(int64_t)I * n + I];
+    d[K] = s;
+  }
+}
+
+// per Cholesky vector: 2 (tr Q)^2 - tr(Q Q), Q = Lt_oo - L_oo; one block per K
+template <typename T>
+__global__ void k_energy_singles(int64_t n, int O, const T *Lt, const T *L, double *part) {
+  const int64_t K = blockIdx.x;
+  const T *a = Lt + K * n * n;
+  const T *b = L + K * n * n;
+  double tr = 0.0, qq = 0.0;
+  for (int64_t x = threadIdx.x; x < (int64_t)O * O; x += TPB) {
+    const int64_t I = x / O, J = x - I * O;
+    const double qij = (double)a[I * n + J] - (double)b[I * n + J];
+    const double qji = (double)a[J * n + I] - (double)b[J * n + I];
+    qq += qij * qji;
+    if (I == J) tr += qij;
+  }
+  const double trs = block_sum(tr);
+  __syncthreads();
+  const double qqs = block_sum(qq);
+  if (threadIdx.x == 0) part[K] = 2.0 * trs * trs - qqs;
+}
+
+}  // namespace
+
+template <typename TD, typename TS>
+void pack2d(Exec &ex, TD *dst, const TS *src, int64_t Z, int64_t sz, int64_t rows, int64_t cols,
+            int64_t ld) {
+  const int64_t n = Z * rows * cols;
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_pack2d<TD, TS>), dim3(blocks_for(n)), dim3(TPB), 0, ex.stream, dst, src,
+                     Z, sz, rows, cols, ld);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TD, typename TS>
+void pack2d_t(Exec &ex, TD *dst, const TS *src, int64_t Z, int64_t sz, int64_t rows, int64_t cols,
+              int64_t ld) {
+  if (Z * rows * cols <= 0) return;
+  MLCC_REQUIRE(Z <= 65535, MLCC_E_ARG, "pack2d_t: batch too large");
+  dim3 grid((unsigned)((cols + 31) / 32), (unsigned)((rows + 31) / 32), (unsigned)Z);
+  hipLaunchKernelGGL((k_pack2d_t<TD, TS>), grid, dim3(256), 0, ex.stream, dst, src, sz, rows,
+                     cols, ld);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TD, typename TS> void convert(Exec &ex, TD *dst, const TS *src, int64_t n) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_convert<TD, TS>), dim3(blocks_for(n)), dim3(TPB), 0, ex.stream, dst, src,
+                     n);
+  MLCC_HIP(hipGetLastError());
+}
+
+void axpby(Exec &ex, int64_t n, double a, const double *x, double b, double *y) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_axpby, dim3(blocks_for(n)), dim3(TPB), 0, ex.stream, n, a, x, b, y);
+  MLCC_HIP(hipGetLastError());
+}
+template <typename T>
+void lincomb(Exec &ex, int64_t n, double a, const T *x, double b, const T *y, T *out) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL((k_lincomb<T>), dim3(blocks_for(n)), dim3(TPB), 0, ex.stream, n, a, x, b, y,
+                     out);
+  MLCC_HIP(hipGetLastError());
+}
+template void lincomb<double>(Exec &, int64_t, double, const double *, double, const double *,
+                              double *);
+template void lincomb<float>(Exec &, int64_t, double, const float *, double, const float *,
+                             float *);
+void scale(Exec &ex, int64_t n, double a, double *x) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_scale, dim3(blocks_for(n)), dim3(TPB), 0, ex.stream, n, a, x);
+  MLCC_HIP(hipGetLastError());
+}
+void fill(Exec &ex, double *x, int64_t n, double v) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(TPB), 0, ex.stream, x, n, v);
+  MLCC_HIP(hipGetLastError());
+}
+
+static double *red_part(Exec &ex, int nb) {
+  ex.red.ensure(ex.al, sizeof(double) * (size_t)(nb + 8));
+  return ex.red.as<double>();
+}
+
+template <typename TA, typename TB>
+void dot_mixed(Exec &ex, int64_t n, const TA *x, const TB *y, double *res) {
+  const unsigned nb = blocks_for(n, 1024);
+  double *part = red_part(ex, nb);
+  hipLaunchKernelGGL((k_dot_partial<TA, TB>), dim3(nb), dim3(TPB), 0, ex.stream, n, x, y, part);
+  MLCC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, ex.stream, (int)nb, part, res);
+  MLCC_HIP(hipGetLastError());
+}
+void dot(Exec &ex, int64_t n, const double *x, const double *y, double *res) {
+  dot_mixed<double, double>(ex, n, x, y, res);
+}
+
+void nonfinite(Exec &ex, int64_t n, const double *x, double *res) {
+  const unsigned nb = blocks_for(n, 1024);
+  double *part = red_part(ex, nb);
+  hipLaunchKernelGGL(k_nonfinite_partial, dim3(nb), dim3(TPB), 0, ex.stream, n, x, part);
+  MLCC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, ex.stream, (int)nb, part, res);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TG, typename TU>
+void mlcc2_s_u(Exec &ex, int o, int v, const TG *g, const double *eps_ai, double *s, TU *u) {
+  const int64_t M = (int64_t)o * v;
+  if (M == 0) return;
+  hipLaunchKernelGGL((k_mlcc2_s_u<TG, TU>), dim3(blocks_for(M * M)), dim3(TPB), 0, ex.stream, o,
+                     v, g, eps_ai, s, u);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TU> void u_of(Exec &ex, int o, int v, const double *x, TU *u) {
+  const int64_t M = (int64_t)o * v;
+  if (M == 0) return;
+  hipLaunchKernelGGL((k_u_of<TU>), dim3(blocks_for(M * M)), dim3(TPB), 0, ex.stream, o, v, x, u);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TG>
+void sym_plus_diag(Exec &ex, int64_t M, const TG *G, const double *eps_ai, const double *c,
+                   double *out) {
+  if (M == 0) return;
+  dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32));
+  hipLaunchKernelGGL((k_sym_plus_diag<TG>), grid, dim3(256), 0, ex.stream, M, G, eps_ai, c, out);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TG, typename TO>
+void sym_div(Exec &ex, int64_t M, const TG *G, const double *eps_ai, double w, TO *out) {
+  if (M == 0) return;
+  dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32));
+  hipLaunchKernelGGL((k_sym_div<TG, TO>), grid, dim3(256), 0, ex.stream, M, G, eps_ai, w, out);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TG>
+void mlcc2_omega2(Exec &ex, int64_t M, const TG *g, const double *eps_ai, const double *s,
+                  double *out) {
+  if (M == 0) return;
+  hipLaunchKernelGGL((k_mlcc2_omega2<TG>), dim3(blocks_for(M * M)), dim3(TPB), 0, ex.stream, M,
+                     g, eps_ai, s, out);
+  MLCC_HIP(hipGetLastError());
+}
+
+void qn_step_singles(Exec &ex, int V, int O, const double *eps, const double *om, double *t) {
+  hipLaunchKernelGGL(k_qn_singles, dim3(blocks_for((int64_t)V * O)), dim3(TPB), 0, ex.stream, V,
+                     O, eps, om, t);
+  MLCC_HIP(hipGetLastError());
+}
+void qn_step_doubles(Exec &ex, int64_t M, const double *eps_ai, const double *om, double *t) {
+  if (M == 0) return;
+  hipLaunchKernelGGL(k_qn_doubles, dim3(blocks_for(M * M)), dim3(TPB), 0, ex.stream, M, eps_ai,
+                     om, t);
+  MLCC_HIP(hipGetLastError());
+}
+void precond(Exec &ex, int64_t n1, int64_t M, const double *eps_vo, const double *eps_ai,
+             double w, const double *r, double *out) {
+  hipLaunchKernelGGL(k_precond, dim3(blocks_for(n1 + M * M)), dim3(TPB), 0, ex.stream, n1, M,
+                     eps_vo, eps_ai, w, r, out);
+  MLCC_HIP(hipGetLastError());
+}
+void denominators(Exec &ex, int O, int V, int o, int v, const double *eps, double *eps_ai,
+                  double *eps_vo) {
+  hipLaunchKernelGGL(k_denominators, dim3(blocks_for((int64_t)V * O)), dim3(TPB), 0, ex.stream,
+                     O, V, o, v, eps, eps_ai, eps_vo);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename T>
+void occ_trace(Exec &ex, int64_t J, int64_t n, int O, const T *X, double *d) {
+  hipLaunchKernelGGL((k_occ_trace<T>), dim3(blocks_for(J)), dim3(TPB), 0, ex.stream, J, n, O, X,
+                     d);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename T>
+void energy_singles(Exec &ex, int64_t J, int64_t n, int O, const T *Lt, const T *L, double *res) {
+  MLCC_REQUIRE(J <= 2147483647, MLCC_E_ARG, "too many Cholesky vectors");
+  double *part = red_part(ex, (int)J + 1024);
+  double *part2 = part + J;
+  hipLaunchKernelGGL((k_energy_singles<T>), dim3((unsigned)J), dim3(TPB), 0, ex.stream, n, O, Lt,
+                     L, part);
+  MLCC_HIP(hipGetLastError());
+  // sum the J partials in a fixed order
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(TPB), 0, ex.stream, (int)J, part, res);
+  MLCC_HIP(hipGetLastError());
+  (void)part2;
+}
+
+// explicit instantiations
+#define INST_PACK(TD, TS)                                                                      \
+  template void pack2d<TD, TS>(Exec &, TD *, const TS *, int64_t, int64_t, int64_t, int64_t,   \
+                               int64_t);                                                       \
+  template void pack2d_t<TD, TS>(Exec &, TD *, const TS *, int64_t, int64_t, int64_t, int64_t, \
+                                 int64_t);                                                     \
+  template void convert<TD, TS>(Exec &, TD *, const TS *, int64_t);
+INST_PACK(double, double)
+INST_PACK(float, double)
+INST_PACK(float, float)
+INST_PACK(double, float)
+template void dot_mixed<double, double>(Exec &, int64_t, const double *, const double *, double *);
+template void dot_mixed<float, float>(Exec &, int64_t, const float *, const float *, double *);
+template void dot_mixed<double, float>(Exec &, int64_t, const double *, const float *, double *);
+template void mlcc2_s_u<double, double>(Exec &, int, int, const double *, const double *, double *,
+                                        double *);
+template void mlcc2_s_u<double, float>(Exec &, int, int, const double *, const double *, double *,
+                                       float *);
+template void u_of<double>(Exec &, int, int, const double *, double *);
+template void u_of<float>(Exec &, int, int, const double *, float *);
+template void sym_plus_diag<double>(Exec &, int64_t, const double *, const double *,
+                                    const double *, double *);
+template void sym_plus_diag<float>(Exec &, int64_t, const float *, const double *, const double *,
+                                   double *);
+template void sym_div<double, double>(Exec &, int64_t, const double *, const double *, double,
+                                      double *);
+template void sym_div<double, float>(Exec &, int64_t, const double *, const double *, double,
+                                     float *);
+template void mlcc2_omega2<double>(Exec &, int64_t, const double *, const double *,
+                                   const double *, double *);
+template void occ_trace<double>(Exec &, int64_t, int64_t, int, const double *, double *);
+template void occ_trace<float>(Exec &, int64_t, int64_t, int, const float *, double *);
+template void energy_singles<double>(Exec &, int64_t, int64_t, int, const double *,
+                                     const double *, double *);
+template void energy_singles<float>(Exec &, int64_t, int64_t, int, const float *, const float *,
+                                    double *);
+
+}  // namespace k
+}  // namespace mlcc

@@ -1,0 +1,182 @@
+// Internal declarations shared by the translation units of libmlcc.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mlcc.h"
+
+namespace mlcc {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+struct Error {
+  mlcc_status code;
+  std::string msg;
+};
+
+#define MLCC_HIP(expr)                                                                   \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::mlcc::Error{e_ == hipErrorOutOfMemory ? MLCC_E_OOM : MLCC_E_DEVICE,        \
+                          std::string(#expr) + ": " + hipGetErrorString(e_)};            \
+  } while (0)
+
+#define MLCC_REQUIRE(cond, code, msg)                          \
+  do {                                                         \
+    if (!(cond)) throw ::mlcc::Error{(code), std::string(msg)}; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device memory accounting
+// ---------------------------------------------------------------------------
+struct Alloc {
+  int device = 0;
+  uint64_t budget = 0;  // 0: unlimited
+  uint64_t used = 0;
+  std::mutex mu;
+  void *get(size_t bytes);
+  void put(void *p, size_t bytes);
+};
+
+// RAII device buffer accounted against an Alloc.
+struct DBuf {
+  Alloc *al = nullptr;
+  void *p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf &) = delete;
+  DBuf &operator=(const DBuf &) = delete;
+  DBuf(DBuf &&o) noexcept { *this = std::move(o); }
+  DBuf &operator=(DBuf &&o) noexcept {
+    if (this != &o) {
+      release();
+      al = o.al; p = o.p; bytes = o.bytes;
+      o.p = nullptr; o.bytes = 0;
+    }
+    return *this;
+  }
+  ~DBuf() { release(); }
+  void alloc(Alloc *a, size_t nbytes) {
+    release();
+    al = a;
+    bytes = nbytes;
+    p = nbytes ? a->get(nbytes) : nullptr;
+  }
+  // grow-only
+  void ensure(Alloc *a, size_t nbytes) {
+    if (nbytes > bytes) alloc(a, nbytes);
+  }
+  void release() {
+    if (p && al) al->put(p, bytes);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// An execution lane: a stream plus its scratch for split reductions.
+struct Exec {
+  Alloc *al = nullptr;
+  hipStream_t stream = nullptr;
+  DBuf work;      // split-K partials
+  DBuf red;       // reduction partials (dot products)
+  DBuf pinned_dummy;
+  double *host_red = nullptr;  // pinned host scalars
+  int n_host_red = 0;
+  void *scratch(size_t bytes) {
+    work.ensure(al, bytes);
+    return work.p;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// GEMM engine (gemm.hip)
+// ---------------------------------------------------------------------------
+enum class Prec : int { F64 = 0, F32 = 1 };
+
+struct GemmArgs {
+  int64_t M = 0, N = 0, K = 0, R = 1, Z = 1;
+  const void *A = nullptr;
+  int64_t sAm = 0, sAk = 0, sAr = 0, sAz = 0;
+  const void *B = nullptr;
+  int64_t sBk = 0, sBn = 0, sBr = 0, sBz = 0;
+  const void *Cin = nullptr;  // may alias C; read only if beta != 0
+  void *C = nullptr;
+  int64_t sCm = 0, sCn = 0, sCz = 0;
+  double alpha = 1.0, beta = 0.0;
+};
+
+// prec selects the operand type (double or float) and the MFMA; out_f64
+// selects the type of C (only meaningful for F32: FP32 operands with an FP32
+// accumulator written out as double).
+void gemm(Exec &ex, Prec prec, const GemmArgs &a, bool out_f64);
+
+// ---------------------------------------------------------------------------
+// element-wise and reduction kernels (kernels.hip)
+// ---------------------------------------------------------------------------
+namespace k {
+// dst[z][r*cols + c] = src[z*sz + (r)*ld + c] for r<rows, c<cols (convert type)
+template <typename TD, typename TS>
+void pack2d(Exec &ex, TD *dst, const TS *src, int64_t Z, int64_t sz, int64_t rows, int64_t cols,
+            int64_t ld);
+// dst[z][c*rows + r] = src[z*sz + r*ld + c]   (transposing pack)
+template <typename TD, typename TS>
+void pack2d_t(Exec &ex, TD *dst, const TS *src, int64_t Z, int64_t sz, int64_t rows,
+              int64_t cols, int64_t ld);
+template <typename TD, typename TS> void convert(Exec &ex, TD *dst, const TS *src, int64_t n);
+// y = a*x + b*y
+void axpby(Exec &ex, int64_t n, double a, const double *x, double b, double *y);
+void scale(Exec &ex, int64_t n, double a, double *x);
+// out = a*x + b*y (element type T, arithmetic in double)
+template <typename T>
+void lincomb(Exec &ex, int64_t n, double a, const T *x, double b, const T *y, T *out);
+void fill(Exec &ex, double *x, int64_t n, double v);
+// deterministic dot products into a device scalar array (res[i])
+void dot(Exec &ex, int64_t n, const double *x, const double *y, double *res);
+template <typename TA, typename TB>
+void dot_mixed(Exec &ex, int64_t n, const TA *x, const TB *y, double *res);
+// MLCC2 doubles from g~: s = -g/eps_aibj (f64), u = 2s - s(i<->j) (TU)
+template <typename TG, typename TU>
+void mlcc2_s_u(Exec &ex, int o, int v, const TG *g, const double *eps_ai, double *s, TU *u);
+// u = 2x - x(i<->j) of a full doubles array (TU output), optional scale of x by 1
+template <typename TU>
+void u_of(Exec &ex, int o, int v, const double *x, TU *u);
+// out = G + G^T + d .* c  (M x M, f64 out); G type TG
+template <typename TG>
+void sym_plus_diag(Exec &ex, int64_t M, const TG *G, const double *eps_ai, const double *c,
+                   double *out);
+// x[ai][bj] /= (w - eps_aibj) after forming G + G^T  (effective singles)
+template <typename TG, typename TO>
+void sym_div(Exec &ex, int64_t M, const TG *G, const double *eps_ai, double w, TO *out);
+// Delta t = -Omega / denominators
+void qn_step_singles(Exec &ex, int V, int O, const double *eps, const double *om, double *t);
+void qn_step_doubles(Exec &ex, int64_t M, const double *eps_ai, const double *om, double *t);
+// Davidson preconditioner r / (w - D) with clamp
+void precond(Exec &ex, int64_t n1, int64_t M, const double *eps_vo, const double *eps_ai,
+             double w, const double *r, double *out);
+// eps_ai[a*o+i] = e_a - e_i (active) and eps_vo[A*O+I] = e_A - e_I
+void denominators(Exec &ex, int O, int V, int o, int v, const double *eps, double *eps_ai,
+                  double *eps_vo);
+// d^K = sum_I X^K_II (trace over occupied) , X stacked [J][n][n]
+template <typename T>
+void occ_trace(Exec &ex, int64_t J, int64_t n, int O, const T *X, double *d);
+// singles energy: E1 = 2 sum_K (tr Q^K)^2 - sum_K tr(Q^K Q^K),  Q^K = Lt_oo - L_oo
+template <typename T>
+void energy_singles(Exec &ex, int64_t J, int64_t n, int O, const T *Lt, const T *L, double *res);
+// NaN/Inf check, result count into res (double)
+void nonfinite(Exec &ex, int64_t n, const double *x, double *res);
+// Omega2 (MLCC2) = g~ + eps_aibj s ; elementwise
+template <typename TG>
+void mlcc2_omega2(Exec &ex, int64_t M, const TG *g, const double *eps_ai, const double *s,
+                  double *out);
+}  // namespace k
+
+}  // namespace mlcc

@@ -1,0 +1,461 @@
+// MLCC2 / MLCCSD model layer: the Omega vector, the energy and the Jacobian
+// transformation, each written as a sequence of GEMM-engine calls and a few
+// element-wise kernels (Sec. 2.1 and Appendix A of Folkestad et al.).
+//
+// Operand type T is double (MLCC_FP64) or float (MLCC_FP32) for everything
+// contracted over Cholesky vectors; Fock matrices, amplitudes, residuals,
+// transformed vectors and energies are FP64.
+//
+// Layout in HBM (n = O + V, J Cholesky vectors, M = o*v active pairs):
+//   L, Lt      [J][n][n]   Cholesky vectors and their X1 transform
+//   Lvo0, Lai  [J][M]      packed active L_ai (untransformed) and L~_ai
+//   Z          [J][M]      Z^K_ai = sum_bj u_ai,bj L^K_bj  (shared by Omega_1
+//                          and the energy)
+//   g, u       [M][M]      g~_aibj and u = 2x - x(i<->j)
+//   amp, om    [n1 + M*M]  (t1 | doubles) and (Omega_1 | Omega_2)
+#include "problem.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace mlcc {
+
+void *Alloc::get(size_t bytes) {
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (budget && used + bytes > budget)
+      throw Error{MLCC_E_OOM, "HBM budget exceeded: need " + std::to_string(bytes) +
+                                  " bytes, " + std::to_string(budget - used) + " left"};
+    used += bytes;
+  }
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(mu);
+    used -= bytes;
+    throw Error{e == hipErrorOutOfMemory ? MLCC_E_OOM : MLCC_E_DEVICE,
+                std::string("hipMalloc: ") + hipGetErrorString(e)};
+  }
+  return p;
+}
+
+void Alloc::put(void *p, size_t bytes) {
+  (void)hipFree(p);
+  std::lock_guard<std::mutex> lk(mu);
+  used -= bytes;
+}
+
+}  // namespace mlcc
+
+using namespace mlcc;
+
+double mlcc_problem::fetch(const double *dev) {
+  double *h = ctx->pinned;
+  MLCC_HIP(hipMemcpyAsync(h, dev, sizeof(double), hipMemcpyDeviceToHost, ex->stream));
+  MLCC_HIP(hipStreamSynchronize(ex->stream));
+  return h[0];
+}
+
+void mlcc_problem::fetch_n(const double *dev, double *host, int n) {
+  MLCC_HIP(hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, ex->stream));
+  MLCC_HIP(hipStreamSynchronize(ex->stream));
+}
+
+// ---------------------------------------------------------------------------
+// setup: inputs, core Hamiltonian h = diag(eps) - G(D_HF), denominators
+// ---------------------------------------------------------------------------
+template <typename T>
+void mlcc_problem::setup_t(const double *Lsrc, bool dev) {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O;
+  const size_t nL = (size_t)J * n2;
+  // FP64 staging copy of L (the input), used for h and converted if FP32
+  DBuf L64;
+  double *L64p;
+  if (sizeof(T) == 8) {
+    L.alloc(al, nL * sizeof(double));
+    L64p = L.as<double>();
+  } else {
+    L64.alloc(al, nL * sizeof(double));
+    L64p = L64.as<double>();
+  }
+  MLCC_HIP(hipMemcpyAsync(L64p, Lsrc, nL * sizeof(double),
+                          dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, x.stream));
+  // h = diag(eps) - 2 sum_K L^K d^K + sum_{K,I} L^K_pI L^K_Iq   (FP64); the
+  // diagonal is added by the caller
+  h.alloc(al, n2 * sizeof(double));
+  k::fill(x, h.as<double>(), n2, 0.0);
+  dK.alloc(al, J * sizeof(double));
+  k::occ_trace<double>(x, J, n, d.O, L64p, dK.as<double>());
+  {
+    // exchange: h += sum_r L^r[:, occ] L^r[occ, :]
+    G(n, n, O, J).A(L64p, n, 1, n2).B(L64p, n, 1, n2).C(h.as<double>(), n, 1, 0, 1.0, 1.0)
+        .run(x, Prec::F64, true);
+    // Coulomb: row p: h[p][:] += -2 sum_K d^K L^K[p][:]
+    G(1, n, J, 1, n).A(dK.p, 0, 1, 0, 0).B(L64p, n2, 1, 0, n).C(h.as<double>(), 0, 1, n, -2.0,
+                                                                  1.0)
+        .run(x, Prec::F64, true);
+  }
+  if (sizeof(T) == 4) {
+    L.alloc(al, nL * sizeof(float));
+    k::convert<float, double>(x, L.as<float>(), L64p, nL);
+  }
+  // packed active L_ai (= L_ia): Lvo0[K][a*o+i] = L^K[O+a][i]
+  if (d.M > 0) {
+    Lvo0.alloc(al, (size_t)J * d.M * sizeof(T));
+    k::pack2d<T, T>(x, off<T>(Lvo0), off<T>(L, (int64_t)O * n), J, n2, d.v, d.o, n);
+  }
+  MLCC_HIP(hipStreamSynchronize(x.stream));
+}
+
+namespace {
+__global__ void k_add_diag(int64_t n, const double *eps, double *h) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    h[i * n + i] += eps[i];
+}
+}  // namespace
+
+void mlcc_problem::setup(const mlcc_problem_desc &desc) {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  d.O = desc.n_occ;
+  d.V = desc.n_vir;
+  d.J = desc.n_chol;
+  d.n = d.O + d.V;
+  model = desc.model;
+  prec = desc.precision;
+  if (model == MLCC_CCS) {
+    d.o = 0;
+    d.v = 0;
+  } else {
+    d.o = desc.n_occ_act;
+    d.v = desc.n_vir_act;
+  }
+  d.M = (int64_t)d.o * d.v;
+  d.n1 = (int64_t)d.O * d.V;
+  d.n2 = (int64_t)d.n * d.n;
+  tsize = prec == MLCC_FP64 ? 8 : 4;
+
+  hipPointerAttribute_t at;
+  auto is_dev = [&](const void *p) {
+    hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return false;
+    }
+    return at.type == hipMemoryTypeDevice;
+  };
+  eps.alloc(al, d.n * sizeof(double));
+  MLCC_HIP(hipMemcpyAsync(eps.p, desc.eps, d.n * sizeof(double),
+                          is_dev(desc.eps) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                          x.stream));
+  eps_vo.alloc(al, d.n1 * sizeof(double));
+  eps_ai.alloc(al, std::max<int64_t>(d.M, 1) * sizeof(double));
+  k::denominators(x, d.O, d.V, d.o, d.v, eps.as<double>(), eps_ai.as<double>(),
+                  eps_vo.as<double>());
+  res.alloc(al, 64 * sizeof(double));
+  // NaN/Inf in eps
+  k::nonfinite(x, d.n, eps.as<double>(), res.as<double>());
+  MLCC_REQUIRE(fetch(res.as<double>()) == 0.0, MLCC_E_NUMERIC, "non-finite orbital energy");
+
+  const bool ldev = is_dev(desc.L);
+  if (prec == MLCC_FP64) setup_t<double>(desc.L, ldev);
+  else setup_t<float>(desc.L, ldev);
+  // h += diag(eps)  (the setup above accumulated -G into a zeroed h)
+  hipLaunchKernelGGL(k_add_diag, dim3(64), dim3(256), 0, x.stream, (int64_t)d.n,
+                     eps.as<double>(), h.as<double>());
+  MLCC_HIP(hipGetLastError());
+  // NaN/Inf in L shows up in h
+  k::nonfinite(x, d.n2, h.as<double>(), res.as<double>());
+  MLCC_REQUIRE(fetch(res.as<double>()) == 0.0, MLCC_E_NUMERIC, "non-finite Cholesky vectors");
+
+  amp.alloc(al, (size_t)(d.n1 + d.M * d.M) * sizeof(double));
+  MLCC_HIP(hipMemsetAsync(amp.p, 0, amp.bytes, x.stream));
+  om.alloc(al, amp.bytes);
+  MLCC_HIP(hipStreamSynchronize(x.stream));
+}
+
+// ---------------------------------------------------------------------------
+// X1 basis (Appendix A): L~ = (1 - T) L (1 + T), T[A][I] = t_AI, blockwise
+//   L~_ov = L_ov
+//   L~_oo = L_oo + L_ov t
+//   L~_vv = L_vv - t L_ov
+//   L~_vo = L_vo + L_vv t - t L~_oo
+// and the Fock matrix F~ = h~ + sum_I (2 g~_pqII - g~_pIIq).
+// ---------------------------------------------------------------------------
+namespace {
+template <typename T>
+void x1_blocks(Exec &x, const Dims &d, const T *src, T *dst, int64_t Z, const T *t) {
+  const int64_t n = d.n, n2 = d.n2, O = d.O, V = d.V;
+  const Prec p = prec_of<T>();
+  const bool o64 = sizeof(T) == 8;
+  // ov copy: C = 1 * Cin with an empty reduction
+  G(O, V, 0, 1, Z).C(dst + O, n, 1, n2, 0.0, 1.0, src + O).run(x, p, o64);
+  G(O, O, V, 1, Z).A(src + O, n, 1, 0, n2).B(t, O, 1, 0, 0).C(dst, n, 1, n2, 1.0, 1.0, src)
+      .run(x, p, o64);
+  G(V, V, O, 1, Z).A(t, O, 1, 0, 0).B(src + O, n, 1, 0, n2)
+      .C(dst + O * n + O, n, 1, n2, -1.0, 1.0, src + O * n + O).run(x, p, o64);
+  G(V, O, V, 1, Z).A(src + O * n + O, n, 1, 0, n2).B(t, O, 1, 0, 0)
+      .C(dst + O * n, n, 1, n2, 1.0, 1.0, src + O * n).run(x, p, o64);
+  G(V, O, O, 1, Z).A(t, O, 1, 0, 0).B(dst, n, 1, 0, n2)
+      .C(dst + O * n, n, 1, n2, -1.0, 1.0, dst + O * n).run(x, p, o64);
+}
+}  // namespace
+
+template <typename T> void mlcc_problem::dress_t(bool full_fock) {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v;
+  const Prec p = prec_of<T>();
+  t1T.ensure(al, d.n1 * sizeof(T));
+  if (sizeof(T) == 8) MLCC_HIP(hipMemcpyAsync(t1T.p, t1(), d.n1 * 8, hipMemcpyDeviceToDevice, x.stream));
+  else k::convert<float, double>(x, t1T.as<float>(), t1(), d.n1);
+  Lt.ensure(al, (size_t)J * n2 * sizeof(T));
+  x1_blocks<T>(x, d, off<T>(L), off<T>(Lt), J, off<T>(t1T));
+  ht.ensure(al, n2 * sizeof(double));
+  x1_blocks<double>(x, d, h.as<double>(), ht.as<double>(), 1, t1());
+  // F~ = h~ + 2 sum_K L~^K d~^K - sum_{K,I} L~^K_pI L~^K_Iq
+  Ft.ensure(al, n2 * sizeof(double));
+  MLCC_HIP(hipMemcpyAsync(Ft.p, ht.p, n2 * sizeof(double), hipMemcpyDeviceToDevice, x.stream));
+  dK.ensure(al, J * sizeof(double));
+  dKT.ensure(al, J * sizeof(T));
+  k::occ_trace<T>(x, J, n, (int)O, off<T>(Lt), dK.as<double>());
+  k::convert<T, double>(x, off<T>(dKT), dK.as<double>(), J);
+  const T *lt = off<T>(Lt);
+  double *F = Ft.as<double>();
+  auto fock_block = [&](int64_t r0, int64_t nr, int64_t c0, int64_t nc) {
+    if (nr <= 0 || nc <= 0) return;
+    G(nr, nc, O, J).A(lt + r0 * n, n, 1, n2).B(lt + c0, n, 1, n2)
+        .C(F + r0 * n + c0, n, 1, 0, -1.0, 1.0).run(x, p, true);
+    G(1, nc, J, 1, nr).A(off<T>(dKT), 0, 1, 0, 0).B(lt + r0 * n + c0, n2, 1, 0, n)
+        .C(F + r0 * n + c0, 0, 1, n, 2.0, 1.0).run(x, p, true);
+  };
+  if (full_fock) {
+    fock_block(0, n, 0, n);
+  } else {
+    fock_block(O, V, 0, O);   // F~_AI
+    fock_block(0, o, O, v);   // F~_jb (active)
+  }
+  fock_full = full_fock;
+}
+
+// MLCC2 / MLCCSD doubles-dependent quantities at the current amplitudes:
+// L~_ai packed, g~_aibj (MLCC2), s = -g~/eps (unless given), u, and
+// Z^K_ai = sum_bj u_ai,bj L^K_bj.
+template <typename T> void mlcc_problem::doubles_mlcc2_t() {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, M = d.M;
+  const Prec p = prec_of<T>();
+  Lai.ensure(al, (size_t)J * M * sizeof(T));
+  k::pack2d<T, T>(x, off<T>(Lai), off<T>(Lt, O * n), J, n2, d.v, d.o, n);
+  u.ensure(al, (size_t)M * M * sizeof(T));
+  if (model == MLCC_MLCC2) {
+    g.ensure(al, (size_t)M * M * sizeof(double));
+    // g~_ai,bj = sum_K L~^K_ai L~^K_bj
+    G(M, M, J).A(off<T>(Lai), 1, M).B(off<T>(Lai), M, 1).C(g.p, M, 1).run(x, p, true);
+    if (!x2_set)
+      k::mlcc2_s_u<double, T>(x, d.o, d.v, g.as<double>(), eps_ai.as<double>(), x2(), off<T>(u));
+    else
+      k::u_of<T>(x, d.o, d.v, x2(), off<T>(u));
+  } else {
+    k::u_of<T>(x, d.o, d.v, x2(), off<T>(u));
+  }
+  Z.ensure(al, (size_t)J * M * sizeof(T));
+  G(J, M, M).A(off<T>(Lvo0), M, 1).B(off<T>(u), M, 1).C(Z.p, M, 1).run(x, p, sizeof(T) == 8);
+}
+
+// Omega_AI += [I act] sum_Kb L~^K_Ab Z^K_bi - [A act] sum_Kk Z^K_ak L~^K_kI
+//           + [A,I act] sum_bj u_ai,bj F~_jb    (Appendix A, MLCC2 Omega vector)
+// optionally starting from F~_AI.  Also the singles-from-doubles part of the
+// Jacobian transformation when Zb/ub come from a trial vector.
+template <typename T>
+void mlcc_problem::omega_singles_t(const void *Zb, const void *ub, double *om1, bool add_fock) {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
+  const Prec p = prec_of<T>();
+  if (add_fock) k::pack2d<double, double>(x, om1, Ft.as<double>() + O * n, 1, 0, V, O, n);
+  if (M == 0 || Zb == nullptr) return;
+  const T *lt = off<T>(Lt);
+  const T *zb = static_cast<const T *>(Zb);
+  G(V, o, v, J).A(lt + O * n + O, n, 1, n2).B(zb, o, 1, M).C(om1, O, 1, 0, 1.0, 1.0)
+      .run(x, p, true);
+  G(v, O, o, J).A(zb, o, 1, M).B(lt, n, 1, n2).C(om1, O, 1, 0, -1.0, 1.0).run(x, p, true);
+  fvec.ensure(al, M * sizeof(T));
+  k::pack2d_t<T, double>(x, off<T>(fvec), Ft.as<double>() + O, 1, 0, o, v, n);
+  G(o, 1, M, 1, v).A(ub, M, 1, 0, o * M).B(fvec.p, 1, 0).C(om1, 1, 0, O, 1.0, 1.0)
+      .run(x, p, true);
+}
+
+template <typename T> void mlcc_problem::compute_state_t(bool full_fock) {
+  Exec &x = *ex;
+  const int64_t J = d.J, n = d.n, M = d.M, n1 = d.n1;
+  dress_t<T>(full_fock);
+  double *om1 = om.as<double>();
+  if (has_doubles()) {
+    doubles_mlcc2_t<T>();
+    omega_singles_t<T>(Z.p, u.p, om1, true);
+    if (model == MLCC_MLCC2)
+      k::mlcc2_omega2<double>(x, M, g.as<double>(), eps_ai.as<double>(), x2(), om1 + n1);
+    else
+      ccsd_omega2_t<T>();
+  } else {
+    omega_singles_t<T>(nullptr, nullptr, om1, true);
+  }
+  // energy: E1 = 2 sum_K (tr Q^K)^2 - sum_K tr(Q^K Q^K), Q^K = (L_ov t)^K = L~_oo - L_oo;
+  //         E2 = sum_ai,bj u_ai,bj g_ai,bj = sum_K sum_ai L^K_ai Z^K_ai
+  double *r = res.as<double>();
+  k::energy_singles<T>(x, J, n, d.O, off<T>(Lt), off<T>(L), r + 0);
+  if (has_doubles()) k::dot_mixed<T, T>(x, J * M, off<T>(Lvo0), off<T>(Z), r + 1);
+  else k::fill(x, r + 1, 1, 0.0);
+  // residual norms
+  k::dot(x, n1, om1, om1, r + 2);
+  if (has_doubles() && (model == MLCC_MLCCSD || x2_set))
+    k::dot(x, M * M, om1 + n1, om1 + n1, r + 3);
+  else
+    k::fill(x, r + 3, 1, 0.0);
+  double hr[4];
+  fetch_n(r, hr, 4);
+  e_corr = hr[0] + hr[1];
+  omega_norm = std::sqrt(hr[2] + hr[3]);
+  state_valid = true;
+}
+
+#include "ccsd.inl"
+
+void mlcc_problem::compute_state(bool full_fock) {
+  if (prec == MLCC_FP64) compute_state_t<double>(full_fock);
+  else compute_state_t<float>(full_fock);
+}
+
+// ---------------------------------------------------------------------------
+// Jacobian transformation (Appendix A.2), the derivative of the Omega vector:
+// with dL~ = L~ C - C L~ (C[A][I] = c_AI) and dF~ likewise, the singles part is
+//   CCS:   F~_AB c_BI - c_AJ F~_JI + 2 (L~^K_JB c_BJ) L~^K_AI - (L~^K_AB c_BJ) L~^K_JI
+//   MLCC2: - c_AJ X_Ji - Y_aB c_BI + u_ai,ck (2 q_ck - r_ck)
+//          with X_Ji = sum L~^K_Jb Z^K_bi, Y_aB = sum Z^K_ak L~^K_kB,
+//          q_ck = sum_K L^K_ck (L~^K_JB c_BJ), r_ck = sum (L~^K_kB c_BJ) L~^K_Jc
+//   doubles -> singles: the Omega_1 doubles terms with u -> 2c - c(i<->j)
+// and the doubles part is dg~ + eps * c2 = P[(dL~^K_ai) L~^K_bj] + eps c2.
+// ---------------------------------------------------------------------------
+template <typename T> void mlcc_problem::prepare_jacobian_t() {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
+  const Prec p = prec_of<T>();
+  compute_state_t<T>(true);
+  if (has_doubles()) {
+    Xint.ensure(al, O * o * sizeof(T));
+    Yint.ensure(al, v * V * sizeof(T));
+    const T *lt = off<T>(Lt);
+    G(O, o, v, J).A(lt + O, n, 1, n2).B(Z.p, o, 1, M).C(Xint.p, o, 1).run(x, p, sizeof(T) == 8);
+    G(v, V, o, J).A(Z.p, o, 1, M).B(lt + O, n, 1, n2).C(Yint.p, V, 1).run(x, p, sizeof(T) == 8);
+    if (model == MLCC_MLCCSD) ccsd_prepare_t<T>();
+  }
+  jac_ready = true;
+}
+
+void mlcc_problem::prepare_jacobian() {
+  if (prec == MLCC_FP64) prepare_jacobian_t<double>();
+  else prepare_jacobian_t<float>();
+}
+
+// One vector.  c2/s2 may be null (singles-only).  w_eff: when finite and c2 is
+// null, the doubles are eliminated, c2 = (A21 c1)/(w - eps) (MLCC2 only).
+template <typename T>
+void mlcc_problem::transform_one_t(const double *c1, const double *c2, double *s1, double *s2,
+                                   double w_eff) {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
+  const Prec p = prec_of<T>();
+  const bool o64 = sizeof(T) == 8;
+  const T *lt = off<T>(Lt);
+  const double *F = Ft.as<double>();
+  cT.ensure(al, d.n1 * sizeof(T));
+  T *ct = off<T>(cT);
+  if (o64) MLCC_HIP(hipMemcpyAsync(ct, c1, d.n1 * 8, hipMemcpyDeviceToDevice, x.stream));
+  else k::convert<float, double>(x, cT.as<float>(), c1, d.n1);
+
+  // CCS terms
+  G(V, O, V).A(F + O * n + O, n, 1).B(c1, O, 1).C(s1, O, 1).run(x, Prec::F64, true);
+  G(V, O, O).A(c1, O, 1).B(F, n, 1).C(s1, O, 1, 0, -1.0, 1.0).run(x, Prec::F64, true);
+  Xk.ensure(al, J * sizeof(T));
+  G(J, 1, V, O).A(lt + O, n2, 1, n).B(ct, O, 0, 1).C(Xk.p, 1, 0).run(x, p, o64);
+  G(O, 1, J, 1, V).A(lt + O * n, 1, n2, 0, n).B(Xk.p, 1, 0).C(s1, 1, 0, O, 2.0, 1.0)
+      .run(x, p, true);
+  W.ensure(al, (size_t)J * V * O * sizeof(T));
+  G(V, O, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(W.p, O, 1, V * O).run(x, p, o64);
+  G(V, O, V, J).A(lt + O * n + O, n, 1, n2).B(W.p, O, 1, V * O).C(s1, O, 1, 0, -1.0, 1.0)
+      .run(x, p, true);
+  if (!has_doubles()) return;
+
+  // MLCC2 singles-singles terms with the ground-state u
+  G(V, o, O).A(ct, O, 1).B(Xint.p, o, 1).C(s1, O, 1, 0, -1.0, 1.0).run(x, p, true);
+  G(v, O, V).A(Yint.p, V, 1).B(ct, O, 1).C(s1, O, 1, 0, -1.0, 1.0).run(x, p, true);
+  qv.ensure(al, M * sizeof(T));
+  rv.ensure(al, M * sizeof(T));
+  P.ensure(al, (size_t)J * o * O * sizeof(T));
+  G(M, 1, J).A(off<T>(Lvo0), 1, M).B(Xk.p, 1, 0).C(qv.p, 1, 0).run(x, p, o64);
+  G(o, O, V, 1, J).A(lt + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).C(P.p, O, 1, o * O).run(x, p, o64);
+  G(v, o, O, J).A(lt + O, 1, n, n2).B(P.p, 1, O, o * O).C(rv.p, o, 1).run(x, p, o64);
+  // w = 2 q - r, in place of q
+  k::lincomb<T>(x, M, 2.0, off<T>(qv), -1.0, off<T>(rv), off<T>(qv));
+  G(o, 1, M, 1, v).A(u.p, M, 1, 0, o * M).B(qv.p, 1, 0).C(s1, 1, 0, O, 1.0, 1.0).run(x, p, true);
+
+  // doubles part: dL~_ai = sum_B L~_aB c_Bi - sum_J c_aJ L~_Ji, G = L~ai^T dL~ai
+  dLai.ensure(al, (size_t)J * M * sizeof(T));
+  G(v, o, V, 1, J).A(lt + O * n + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).C(dLai.p, o, 1, M)
+      .run(x, p, o64);
+  G(v, o, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(dLai.p, o, 1, M, -1.0, 1.0)
+      .run(x, p, o64);
+  Gm.ensure(al, (size_t)M * M * sizeof(double));
+  G(M, M, J).A(off<T>(Lai), 1, M).B(dLai.p, M, 1).C(Gm.p, M, 1).run(x, p, true);
+
+  const double *c2u = c2;
+  if (!c2 && std::isfinite(w_eff)) {
+    c2e.ensure(al, (size_t)M * M * sizeof(double));
+    k::sym_div<double, double>(x, M, Gm.as<double>(), eps_ai.as<double>(), w_eff,
+                               c2e.as<double>());
+    c2u = c2e.as<double>();
+  } else if (s2) {
+    if (model == MLCC_MLCC2)
+      k::sym_plus_diag<double>(x, M, Gm.as<double>(), eps_ai.as<double>(), c2, s2);
+    else
+      ccsd_sigma2_t<T>(c1, c2, s2);
+  }
+  if (c2u) {
+    // doubles -> singles with u = 2 c2 - c2(i<->j)
+    ut.ensure(al, (size_t)M * M * sizeof(T));
+    Zc.ensure(al, (size_t)J * M * sizeof(T));
+    k::u_of<T>(x, d.o, d.v, c2u, off<T>(ut));
+    G(J, M, M).A(off<T>(Lvo0), M, 1).B(ut.p, M, 1).C(Zc.p, M, 1).run(x, p, o64);
+    omega_singles_t<T>(Zc.p, ut.p, s1, false);
+    if (model == MLCC_MLCCSD && c2) ccsd_sigma1_doubles_t<T>(c2, s1);
+  }
+}
+
+void mlcc_problem::transform(int nvec, const double *c, double *sigma) {
+  const int64_t dm = dim();
+  for (int i = 0; i < nvec; ++i) {
+    const double *c1 = c + i * dm;
+    double *s1 = sigma + i * dm;
+    const double *c2 = has_doubles() ? c1 + d.n1 : nullptr;
+    double *s2 = has_doubles() ? s1 + d.n1 : nullptr;
+    if (prec == MLCC_FP64) transform_one_t<double>(c1, c2, s1, s2, NAN);
+    else transform_one_t<float>(c1, c2, s1, s2, NAN);
+  }
+}
+
+void mlcc_problem::transform_eff(double w, int nvec, const double *c1, double *s1) {
+  for (int i = 0; i < nvec; ++i) {
+    if (prec == MLCC_FP64)
+      transform_one_t<double>(c1 + i * d.n1, nullptr, s1 + i * d.n1, nullptr, w);
+    else
+      transform_one_t<float>(c1 + i * d.n1, nullptr, s1 + i * d.n1, nullptr, w);
+  }
+}

@@ -1,0 +1,120 @@
+// The context and problem objects behind the C ABI.
+#pragma once
+
+#include <memory>
+#include <string>
+
+#include "mlcc_internal.h"
+
+struct mlcc_context {
+  int device = 0;
+  bool own_stream = false;
+  mlcc::Alloc al;
+  mlcc::Exec ex;
+  std::string last_error;
+  double *pinned = nullptr;  // host scalars for device->host results
+};
+
+namespace mlcc {
+
+struct Dims {
+  int O = 0, V = 0, n = 0, J = 0, o = 0, v = 0;
+  int64_t M = 0, n1 = 0, n2 = 0;  // pairs, singles, n*n
+  int64_t dim_full() const { return n1 + M * M; }
+};
+
+// Builder for one GEMM-engine call.
+struct G {
+  GemmArgs a;
+  G(int64_t M, int64_t N, int64_t K, int64_t R = 1, int64_t Z = 1) {
+    a.M = M; a.N = N; a.K = K; a.R = R; a.Z = Z;
+  }
+  G &A(const void *p, int64_t sm, int64_t sk, int64_t sr = 0, int64_t sz = 0) {
+    a.A = p; a.sAm = sm; a.sAk = sk; a.sAr = sr; a.sAz = sz;
+    return *this;
+  }
+  G &B(const void *p, int64_t sk, int64_t sn, int64_t sr = 0, int64_t sz = 0) {
+    a.B = p; a.sBk = sk; a.sBn = sn; a.sBr = sr; a.sBz = sz;
+    return *this;
+  }
+  G &C(void *p, int64_t sm, int64_t sn, int64_t sz = 0, double alpha = 1.0, double beta = 0.0,
+       const void *cin = nullptr) {
+    a.C = p; a.sCm = sm; a.sCn = sn; a.sCz = sz; a.alpha = alpha; a.beta = beta;
+    a.Cin = cin ? cin : p;
+    return *this;
+  }
+  void run(Exec &ex, Prec p, bool out64) const { gemm(ex, p, a, out64); }
+};
+
+template <typename T> inline Prec prec_of() { return sizeof(T) == 8 ? Prec::F64 : Prec::F32; }
+template <typename T> inline T *off(const DBuf &b, int64_t elems = 0) {
+  return static_cast<T *>(b.p) + elems;
+}
+template <typename T> inline T *off(void *p, int64_t elems) { return static_cast<T *>(p) + elems; }
+template <typename T> inline const T *off(const void *p, int64_t elems) {
+  return static_cast<const T *>(p) + elems;
+}
+
+}  // namespace mlcc
+
+struct mlcc_problem {
+  mlcc_context *ctx = nullptr;
+  mlcc::Exec *ex = nullptr;
+  mlcc::Dims d;
+  int model = MLCC_MLCC2;
+  int prec = MLCC_FP64;
+  size_t tsize = 8;  // bytes of the operand type
+
+  // inputs and derived constants
+  mlcc::DBuf L, eps, h, eps_ai, eps_vo, Lvo0;
+  // state at the current amplitudes
+  mlcc::DBuf amp;      // f64 [n1 + M*M]: t1 then doubles
+  mlcc::DBuf t1T;      // op [n1]
+  mlcc::DBuf Lt, ht, Ft, dK, dKT;
+  mlcc::DBuf Lai, g, u, Z;
+  mlcc::DBuf om;       // f64 [n1 + M*M]
+  mlcc::DBuf res;      // f64 device scalars
+  // Jacobian intermediates
+  mlcc::DBuf Xint, Yint, fvec;
+  // MLCCSD intermediates and scratch
+  mlcc::DBuf cc_work;
+  // transform scratch
+  mlcc::DBuf cT, Xk, W, P, qv, rv, wv, ut, Zc, dLai, Gm, c2e;
+
+  bool have_amp = false;
+  bool x2_set = false;     // MLCC2: an independent s2 was given
+  bool state_valid = false;  // dressed quantities match amp
+  bool jac_ready = false;
+  bool fock_full = false;
+  double e_corr = 0.0;
+  double omega_norm = 0.0;
+
+  bool has_doubles() const { return model != MLCC_CCS && d.M > 0; }
+  int64_t dim() const { return d.n1 + (has_doubles() ? d.M * d.M : 0); }
+  double *t1() const { return amp.as<double>(); }
+  double *x2() const { return amp.as<double>() + d.n1; }
+
+  // model steps (problem.cpp)
+  void setup(const mlcc_problem_desc &desc);
+  void compute_state(bool full_fock);  // dress + doubles + Z + Omega + energy
+  void prepare_jacobian();
+  void transform(int nvec, const double *c, double *sigma);       // device pointers
+  void transform_eff(double w, int nvec, const double *c1, double *s1);
+  double fetch(const double *dev);
+  void fetch_n(const double *dev, double *host, int n);
+
+ private:
+  template <typename T> void setup_t(const double *Lhost_or_dev, bool dev);
+  template <typename T> void dress_t(bool full_fock);
+  template <typename T> void doubles_mlcc2_t();
+  template <typename T> void omega_singles_t(const void *Zb, const void *ub, double *om1,
+                                             bool add_fock);
+  template <typename T> void compute_state_t(bool full_fock);
+  template <typename T> void prepare_jacobian_t();
+  template <typename T> void transform_one_t(const double *c1, const double *c2, double *s1,
+                                             double *s2, double w_eff);
+  template <typename T> void ccsd_omega2_t();
+  template <typename T> void ccsd_prepare_t();
+  template <typename T> void ccsd_sigma2_t(const double *c1, const double *c2, double *s2);
+  template <typename T> void ccsd_sigma1_doubles_t(const double *c2, double *s1);
+};

@@ -1,0 +1,280 @@
+"""Thin ctypes binding of libmlcc.so (the C ABI in include/mlcc.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Arrays may be NumPy arrays (host) or torch CUDA tensors (device);
+torch is used only for device memory and streams.  The library must be built
+(``python -m paper_2006_05226_amd.build``); importing this module without it
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmlcc.so")
+
+OK, PENDING = 0, 1
+E_ARG, E_OOM, E_NOCONV, E_NUMERIC, E_DEVICE, E_BUSY, E_STATE = -1, -2, -3, -4, -5, -6, -7
+CCS, MLCC2, MLCCSD = 0, 1, 2
+FP64, FP32 = 0, 1
+MODEL = {"ccs": CCS, "mlcc2": MLCC2, "mlccsd": MLCCSD}
+PREC = {"fp64": FP64, "fp32": FP32}
+
+_STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_ARG", -2: "E_OOM", -3: "E_NOCONV",
+                 -4: "E_NUMERIC", -5: "E_DEVICE", -6: "E_BUSY", -7: "E_STATE"}
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("n_occ", C.c_int32), ("n_vir", C.c_int32), ("n_chol", C.c_int32),
+                ("n_occ_act", C.c_int32), ("n_vir_act", C.c_int32), ("model", C.c_int32),
+                ("precision", C.c_int32), ("L", C.c_void_p), ("eps", C.c_void_p)]
+
+
+class SolverOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("diis_dim", C.c_int32),
+                ("max_subspace", C.c_int32), ("n_guess", C.c_int32), ("effective", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("residual", C.c_double),
+                ("energy", C.c_double), ("complex_roots", C.c_int32), ("transforms", C.c_int32)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("max_queue", C.c_int32), ("hbm_budget", C.c_uint64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("n_roots", C.c_int32), ("omega", C.c_double * 16),
+                ("e_corr", C.c_double), ("t_submit", C.c_double), ("t_admit", C.c_double),
+                ("t_done", C.c_double), ("gs_iterations", C.c_int32),
+                ("es_iterations", C.c_int32)]
+
+
+EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "mlcc_context_bytes",
+           "mlcc_problem_create", "mlcc_problem_destroy", "mlcc_problem_dims",
+           "mlcc_set_amplitudes", "mlcc_residual", "mlcc_ground_state",
+           "mlcc_jacobian_transform", "mlcc_jacobian_transform_eff", "mlcc_davidson_solve",
+           "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
+           "mlcc_request_footprint", "mlcc_gemm", "mlcc_debug_get"]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the library and declare the signatures (no device call is made)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run python -m paper_2006_05226_amd.build")
+    lib = C.CDLL(path)
+    vp, i32, i64, u64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64, C.c_double
+    P = C.POINTER
+    sig = {
+        "mlcc_context_create": (i32, [C.c_int, vp, u64, P(vp)]),
+        "mlcc_context_destroy": (i32, [vp]),
+        "mlcc_last_error": (C.c_char_p, [vp]),
+        "mlcc_context_bytes": (u64, [vp]),
+        "mlcc_problem_create": (i32, [vp, P(ProblemDesc), P(vp)]),
+        "mlcc_problem_destroy": (i32, [vp]),
+        "mlcc_problem_dims": (i32, [vp, P(i64)]),
+        "mlcc_set_amplitudes": (i32, [vp, vp, vp]),
+        "mlcc_residual": (i32, [vp, vp, vp, vp, P(dbl)]),
+        "mlcc_ground_state": (i32, [vp, P(SolverOpts), vp, P(dbl), P(Info)]),
+        "mlcc_jacobian_transform": (i32, [vp, i32, vp, vp]),
+        "mlcc_jacobian_transform_eff": (i32, [vp, dbl, i32, vp, vp]),
+        "mlcc_davidson_solve": (i32, [vp, i32, P(SolverOpts), vp, vp, P(Info)]),
+        "mlcc_server_create": (i32, [vp, P(ServerOpts), P(vp)]),
+        "mlcc_server_destroy": (i32, [vp]),
+        "mlcc_submit": (i32, [vp, P(ProblemDesc), i32, P(SolverOpts), P(SolverOpts), P(u64)]),
+        "mlcc_poll": (i32, [vp, u64, P(Result)]),
+        "mlcc_request_footprint": (u64, [P(ProblemDesc), i32, P(SolverOpts)]),
+        "mlcc_gemm": (i32, [vp, i32, i64, i64, i64, i64, i64, dbl, vp, P(i64), vp, P(i64), dbl,
+                            vp, P(i64)]),
+        "mlcc_debug_get": (i32, [vp, i32, vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class MlccError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(a):
+    """Data pointer of a NumPy array or a torch tensor (device or host)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous, "arrays must be C-contiguous"
+        return a.ctypes.data
+    if hasattr(a, "data_ptr"):
+        assert a.is_contiguous(), "tensors must be contiguous"
+        return a.data_ptr()
+    raise TypeError(type(a))
+
+
+def _f64(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return np.ascontiguousarray(a, dtype=np.float64)
+    return a
+
+
+def opts(tol=1e-8, max_iter=100, diis_dim=8, max_subspace=0, n_guess=0, effective=False):
+    return SolverOpts(tol, max_iter, diis_dim, max_subspace, n_guess, 1 if effective else 0)
+
+
+class Context:
+    def __init__(self, device=0, stream=None, hbm_budget=0):
+        self.lib = load()
+        h = C.c_void_p()
+        st = self.lib.mlcc_context_create(device, stream, hbm_budget, C.byref(h))
+        if st != OK:
+            raise MlccError(st, self.lib.mlcc_last_error(None).decode())
+        self.h = h
+
+    def check(self, st, ok=(OK,)):
+        if st not in ok:
+            raise MlccError(st, self.lib.mlcc_last_error(self.h).decode())
+        return st
+
+    def last_error(self):
+        return self.lib.mlcc_last_error(self.h).decode()
+
+    def bytes(self):
+        return self.lib.mlcc_context_bytes(self.h)
+
+    def gemm(self, prec, M, N, K, R, Z, alpha, A, sA, B, sB, beta, Cm, sC):
+        a4 = (C.c_int64 * 4)(*sA)
+        b4 = (C.c_int64 * 4)(*sB)
+        c3 = (C.c_int64 * 3)(*sC)
+        return self.check(self.lib.mlcc_gemm(self.h, prec, M, N, K, R, Z, alpha, _ptr(A), a4,
+                                             _ptr(B), b4, beta, _ptr(Cm), c3))
+
+    def close(self):
+        if self.h:
+            self.lib.mlcc_context_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """One MLCC problem on a context (see mlcc_problem_create)."""
+
+    def __init__(self, ctx: Context, L, eps, n_occ, n_vir, n_occ_act=None, n_vir_act=None,
+                 model="mlcc2", precision="fp64"):
+        self.ctx = ctx
+        L = _f64(L)
+        eps = _f64(eps)
+        n_chol = L.shape[0]
+        self._keep = (L, eps)
+        d = ProblemDesc(n_occ, n_vir, n_chol,
+                        n_occ if n_occ_act is None else n_occ_act,
+                        n_vir if n_vir_act is None else n_vir_act,
+                        MODEL[model], PREC[precision], _ptr(L), _ptr(eps))
+        h = C.c_void_p()
+        ctx.check(ctx.lib.mlcc_problem_create(ctx.h, C.byref(d), C.byref(h)))
+        self._keep = None  # the library copied the inputs
+        self.h = h
+        dims = (C.c_int64 * 8)()
+        ctx.check(ctx.lib.mlcc_problem_dims(h, dims))
+        (self.n_occ, self.n_vir, self.n_chol, self.o, self.v, self.M, self.n1,
+         self.dim) = list(dims)
+        self.model = model
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.mlcc_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_amplitudes(self, t1, x2=None):
+        t1 = _f64(t1)
+        x2 = _f64(x2)
+        self.ctx.check(self.ctx.lib.mlcc_set_amplitudes(self.h, _ptr(t1), _ptr(x2)))
+
+    def residual(self):
+        om1 = np.empty((self.n_vir, self.n_occ))
+        om2 = np.empty((self.M, self.M)) if self.M else None
+        x2 = np.empty((self.M, self.M)) if self.M else None
+        e = C.c_double()
+        self.ctx.check(self.ctx.lib.mlcc_residual(self.h, _ptr(om1), _ptr(om2), _ptr(x2),
+                                                  C.byref(e)))
+        return om1, om2, x2, e.value
+
+    def ground_state(self, tol=1e-10, max_iter=100, diis_dim=8):
+        t1 = np.empty((self.n_vir, self.n_occ))
+        e = C.c_double()
+        info = Info()
+        o = opts(tol=tol, max_iter=max_iter, diis_dim=diis_dim)
+        st = self.ctx.lib.mlcc_ground_state(self.h, C.byref(o), _ptr(t1), C.byref(e),
+                                            C.byref(info))
+        self.ctx.check(st, ok=(OK, E_NOCONV))
+        return dict(t1=t1, energy=e.value, iterations=info.iterations,
+                    converged=bool(info.converged), residual=info.residual, status=st)
+
+    def jacobian_transform(self, c, sigma=None):
+        """c: [n_vec][dim] (numpy host or torch device); returns sigma alike."""
+        n_vec = c.shape[0] if c.ndim > 1 else 1
+        if sigma is None:
+            if isinstance(c, np.ndarray):
+                sigma = np.empty_like(c, dtype=np.float64)
+            else:
+                sigma = c.new_empty(c.shape)
+        c = _f64(c)
+        self.ctx.check(self.ctx.lib.mlcc_jacobian_transform(self.h, n_vec, _ptr(c), _ptr(sigma)))
+        return sigma
+
+    def jacobian_transform_eff(self, omega, c1, s1=None):
+        n_vec = c1.shape[0] if c1.ndim > 1 else 1
+        if s1 is None:
+            s1 = np.empty_like(c1, dtype=np.float64) if isinstance(c1, np.ndarray) \
+                else c1.new_empty(c1.shape)
+        c1 = _f64(c1)
+        self.ctx.check(self.ctx.lib.mlcc_jacobian_transform_eff(self.h, float(omega), n_vec,
+                                                                _ptr(c1), _ptr(s1)))
+        return s1
+
+    def davidson(self, n_roots, tol=1e-8, max_iter=100, max_subspace=0, n_guess=0,
+                 effective=False, want_vectors=False):
+        w = np.empty(n_roots)
+        r1 = np.empty((n_roots, self.n1)) if want_vectors else None
+        info = Info()
+        o = opts(tol=tol, max_iter=max_iter, max_subspace=max_subspace, n_guess=n_guess,
+                 effective=effective)
+        st = self.ctx.lib.mlcc_davidson_solve(self.h, n_roots, C.byref(o), _ptr(w), _ptr(r1),
+                                              C.byref(info))
+        self.ctx.check(st, ok=(OK, E_NOCONV))
+        return dict(omega=w, r1=r1, iterations=info.iterations, converged=bool(info.converged),
+                    residual=info.residual, transforms=info.transforms,
+                    complex_roots=info.complex_roots, status=st)
+
+    def debug_get(self, which):
+        sizes = {0: (self.n_occ + self.n_vir,) * 2,
+                 1: (self.n_chol, self.n_occ + self.n_vir, self.n_occ + self.n_vir),
+                 2: (self.M, self.M), 3: (self.n_vir, self.n_occ), 4: (self.M, self.M)}
+        out = np.empty(sizes[which])
+        self.ctx.check(self.ctx.lib.mlcc_debug_get(self.h, which, _ptr(out)))
+        return out
