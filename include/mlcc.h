@@ -223,6 +223,20 @@ mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int
                       const void *B, const int64_t sB[4], double beta, void *C,
                       const int64_t sC[3]);
 
+/* Per-contraction timing: when enabled, every GEMM-engine launch is bracketed
+ * by HIP events on the context stream and accumulated under the name of the
+ * contraction it computes (e.g. "g_aibj", "ccs_vv").  flops counts the
+ * algorithmic 2*M*N*K*R*Z of each launch.  Enabling clears the record. */
+typedef struct {
+  char name[40];
+  int64_t launches;
+  double ms;      /* summed kernel time of the GEMM launches */
+  double flops;   /* summed algorithmic flops */
+} mlcc_kernel_stat;
+mlcc_status mlcc_profile_enable(mlcc_context *ctx, int32_t on);
+/* Fills up to max entries, returns how many there are (synchronises). */
+int32_t mlcc_profile_get(mlcc_context *ctx, mlcc_kernel_stat *out, int32_t max);
+
 /* Internal intermediates for step-by-step parity tests.  which: 0 = F~ [n][n],
  * 1 = L~ [n_chol][n][n] (FP64 copy), 2 = g~_aibj [M][M], 3 = t1 [n_vir][n_occ],
  * 4 = doubles [M][M].  out is host memory of the stated size.  The values are

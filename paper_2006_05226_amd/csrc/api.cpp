@@ -115,6 +115,7 @@ mlcc_status mlcc_context_create(int device, void *hip_stream, uint64_t hbm_budge
     c->al.device = device;
     c->al.budget = hbm_budget;
     c->ex.al = &c->al;
+    c->ex.prof = &c->prof;
     if (hip_stream) {
       c->ex.stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -458,6 +459,42 @@ mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int
     MLCC_HIP(hipStreamSynchronize(ctx->ex.stream));
     return MLCC_OK;
   });
+}
+
+mlcc_status mlcc_profile_enable(mlcc_context *ctx, int32_t on) {
+  if (!ctx) return MLCC_E_ARG;
+  return guarded(ctx, [&]() -> mlcc_status {
+    MLCC_HIP(hipStreamSynchronize(ctx->ex.stream));
+    ctx->prof.clear();
+    ctx->prof.on = on != 0;
+    return MLCC_OK;
+  });
+}
+
+int32_t mlcc_profile_get(mlcc_context *ctx, mlcc_kernel_stat *out, int32_t max) {
+  if (!ctx) return MLCC_E_ARG;
+  mlcc_status st = guarded(ctx, [&]() -> mlcc_status {
+    MLCC_HIP(hipStreamSynchronize(ctx->ex.stream));
+    std::vector<mlcc_kernel_stat> agg;
+    for (const auto &r : ctx->prof.recs) {
+      float ms = 0.f;
+      MLCC_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+      auto it = std::find_if(agg.begin(), agg.end(),
+                             [&](const mlcc_kernel_stat &k) { return std::strcmp(k.name, r.tag) == 0; });
+      if (it == agg.end()) {
+        mlcc_kernel_stat k{};
+        std::strncpy(k.name, r.tag, sizeof(k.name) - 1);
+        agg.push_back(k);
+        it = agg.end() - 1;
+      }
+      it->launches += 1;
+      it->ms += ms;
+      it->flops += r.flops;
+    }
+    for (int i = 0; i < (int)agg.size() && i < max; ++i) out[i] = agg[i];
+    return (mlcc_status)agg.size();
+  });
+  return st;
 }
 
 mlcc_status mlcc_debug_get(mlcc_problem *P, int32_t which, double *out) {

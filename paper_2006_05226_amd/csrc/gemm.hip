@@ -213,6 +213,11 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   dim3 grid((unsigned)((a.N + BN - 1) / BN), (unsigned)((a.M + BM - 1) / BM),
             (unsigned)(a.Z * splits));
   // coalescing: let threads run along the smaller stride
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (ex.prof && ex.prof->on) {
+    ev = ex.prof->next();
+    MLCC_HIP(hipEventRecord(ev.first, ex.stream));
+  }
   const bool akf = std::llabs(a.sAk) <= std::llabs(a.sAm);
   const bool bkf = std::llabs(a.sBk) <= std::llabs(a.sBn);
   if (akf && bkf)
@@ -224,6 +229,11 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   else
     hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, BK, false, false>), grid, dim3(256), 0, ex.stream, kp);
   MLCC_HIP(hipGetLastError());
+  if (ev.first) {
+    MLCC_HIP(hipEventRecord(ev.second, ex.stream));
+    ex.prof->recs.push_back({a.tag, ev.first, ev.second,
+                             2.0 * (double)a.M * a.N * a.K * a.R * a.Z});
+  }
   if (splits > 1) {
     const int64_t n = a.Z * a.M * a.N;
     const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
@@ -257,6 +267,16 @@ void dispatch(Exec &ex, const GemmArgs &a) {
 }
 
 }  // namespace
+
+std::pair<hipEvent_t, hipEvent_t> Profiler::next() {
+  if (used == pool.size()) {
+    hipEvent_t a, b;
+    MLCC_HIP(hipEventCreate(&a));
+    MLCC_HIP(hipEventCreate(&b));
+    pool.push_back({a, b});
+  }
+  return pool[used++];
+}
 
 void gemm(Exec &ex, Prec prec, const GemmArgs &a, bool out_f64) {
   if (a.M <= 0 || a.N <= 0 || a.Z <= 0) return;

@@ -82,8 +82,24 @@ struct DBuf {
   template <typename T> T *as() const { return static_cast<T *>(p); }
 };
 
+// Event-based timing of GEMM-engine launches, grouped by contraction name.
+struct Profiler {
+  struct Rec {
+    const char *tag;
+    hipEvent_t a, b;
+    double flops;
+  };
+  bool on = false;
+  std::vector<Rec> recs;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+  size_t used = 0;
+  std::pair<hipEvent_t, hipEvent_t> next();
+  void clear() { recs.clear(); used = 0; }
+};
+
 // An execution lane: a stream plus its scratch for split reductions.
 struct Exec {
+  Profiler *prof = nullptr;
   Alloc *al = nullptr;
   hipStream_t stream = nullptr;
   DBuf work;      // split-K partials
@@ -112,6 +128,7 @@ struct GemmArgs {
   void *C = nullptr;
   int64_t sCm = 0, sCn = 0, sCz = 0;
   double alpha = 1.0, beta = 0.0;
+  const char *tag = "gemm";  // contraction name for the profiler
 };
 
 // prec selects the operand type (double or float) and the MFMA; out_f64

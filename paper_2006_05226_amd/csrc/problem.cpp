@@ -197,9 +197,9 @@ void x1_blocks(Exec &x, const Dims &d, const T *src, T *dst, int64_t Z, const T 
   G(O, O, V, 1, Z).A(src + O, n, 1, 0, n2).B(t, O, 1, 0, 0).C(dst, n, 1, n2, 1.0, 1.0, src)
       .run(x, p, o64);
   G(V, V, O, 1, Z).A(t, O, 1, 0, 0).B(src + O, n, 1, 0, n2)
-      .C(dst + O * n + O, n, 1, n2, -1.0, 1.0, src + O * n + O).run(x, p, o64);
+      .C(dst + O * n + O, n, 1, n2, -1.0, 1.0, src + O * n + O).tag("x1_vv").run(x, p, o64);
   G(V, O, V, 1, Z).A(src + O * n + O, n, 1, 0, n2).B(t, O, 1, 0, 0)
-      .C(dst + O * n, n, 1, n2, 1.0, 1.0, src + O * n).run(x, p, o64);
+      .C(dst + O * n, n, 1, n2, 1.0, 1.0, src + O * n).tag("x1_vo").run(x, p, o64);
   G(V, O, O, 1, Z).A(t, O, 1, 0, 0).B(dst, n, 1, 0, n2)
       .C(dst + O * n, n, 1, n2, -1.0, 1.0, dst + O * n).run(x, p, o64);
 }
@@ -229,7 +229,7 @@ template <typename T> void mlcc_problem::dress_t(bool full_fock) {
   auto fock_block = [&](int64_t r0, int64_t nr, int64_t c0, int64_t nc) {
     if (nr <= 0 || nc <= 0) return;
     G(nr, nc, O, J).A(lt + r0 * n, n, 1, n2).B(lt + c0, n, 1, n2)
-        .C(F + r0 * n + c0, n, 1, 0, -1.0, 1.0).run(x, p, true);
+        .C(F + r0 * n + c0, n, 1, 0, -1.0, 1.0).tag("fock_exch").run(x, p, true);
     G(1, nc, J, 1, nr).A(off<T>(dKT), 0, 1, 0, 0).B(lt + r0 * n + c0, n2, 1, 0, n)
         .C(F + r0 * n + c0, 0, 1, n, 2.0, 1.0).run(x, p, true);
   };
@@ -256,7 +256,7 @@ template <typename T> void mlcc_problem::doubles_mlcc2_t() {
   if (model == MLCC_MLCC2) {
     g.ensure(al, (size_t)M * M * sizeof(double));
     // g~_ai,bj = sum_K L~^K_ai L~^K_bj
-    G(M, M, J).A(off<T>(Lai), 1, M).B(off<T>(Lai), M, 1).C(g.p, M, 1).run(x, p, true);
+    G(M, M, J).A(off<T>(Lai), 1, M).B(off<T>(Lai), M, 1).C(g.p, M, 1).tag("g_aibj").run(x, p, true);
     if (!x2_set)
       k::mlcc2_s_u<double, T>(x, d.o, d.v, g.as<double>(), eps_ai.as<double>(), x2(), off<T>(u));
     else
@@ -265,7 +265,7 @@ template <typename T> void mlcc_problem::doubles_mlcc2_t() {
     k::u_of<T>(x, d.o, d.v, x2(), off<T>(u));
   }
   Z.ensure(al, (size_t)J * M * sizeof(T));
-  G(J, M, M).A(off<T>(Lvo0), M, 1).B(off<T>(u), M, 1).C(Z.p, M, 1).run(x, p, sizeof(T) == 8);
+  G(J, M, M).A(off<T>(Lvo0), M, 1).B(off<T>(u), M, 1).C(Z.p, M, 1).tag("Z_uL").run(x, p, sizeof(T) == 8);
 }
 
 // Omega_AI += [I act] sum_Kb L~^K_Ab Z^K_bi - [A act] sum_Kk Z^K_ak L~^K_kI
@@ -389,9 +389,9 @@ void mlcc_problem::transform_one_t(const double *c1, const double *c2, double *s
   G(O, 1, J, 1, V).A(lt + O * n, 1, n2, 0, n).B(Xk.p, 1, 0).C(s1, 1, 0, O, 2.0, 1.0)
       .run(x, p, true);
   W.ensure(al, (size_t)J * V * O * sizeof(T));
-  G(V, O, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(W.p, O, 1, V * O).run(x, p, o64);
+  G(V, O, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(W.p, O, 1, V * O).tag("ccs_W").run(x, p, o64);
   G(V, O, V, J).A(lt + O * n + O, n, 1, n2).B(W.p, O, 1, V * O).C(s1, O, 1, 0, -1.0, 1.0)
-      .run(x, p, true);
+      .tag("ccs_vv").run(x, p, true);
   if (!has_doubles()) return;
 
   // MLCC2 singles-singles terms with the ground-state u
@@ -410,11 +410,11 @@ void mlcc_problem::transform_one_t(const double *c1, const double *c2, double *s
   // doubles part: dL~_ai = sum_B L~_aB c_Bi - sum_J c_aJ L~_Ji, G = L~ai^T dL~ai
   dLai.ensure(al, (size_t)J * M * sizeof(T));
   G(v, o, V, 1, J).A(lt + O * n + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).C(dLai.p, o, 1, M)
-      .run(x, p, o64);
+      .tag("dLai").run(x, p, o64);
   G(v, o, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(dLai.p, o, 1, M, -1.0, 1.0)
       .run(x, p, o64);
   Gm.ensure(al, (size_t)M * M * sizeof(double));
-  G(M, M, J).A(off<T>(Lai), 1, M).B(dLai.p, M, 1).C(Gm.p, M, 1).run(x, p, true);
+  G(M, M, J).A(off<T>(Lai), 1, M).B(dLai.p, M, 1).C(Gm.p, M, 1).tag("sigma2_LdL").run(x, p, true);
 
   const double *c2u = c2;
   if (!c2 && std::isfinite(w_eff)) {
@@ -433,7 +433,7 @@ void mlcc_problem::transform_one_t(const double *c1, const double *c2, double *s
     ut.ensure(al, (size_t)M * M * sizeof(T));
     Zc.ensure(al, (size_t)J * M * sizeof(T));
     k::u_of<T>(x, d.o, d.v, c2u, off<T>(ut));
-    G(J, M, M).A(off<T>(Lvo0), M, 1).B(ut.p, M, 1).C(Zc.p, M, 1).run(x, p, o64);
+    G(J, M, M).A(off<T>(Lvo0), M, 1).B(ut.p, M, 1).C(Zc.p, M, 1).tag("Zc_uL").run(x, p, o64);
     omega_singles_t<T>(Zc.p, ut.p, s1, false);
     if (model == MLCC_MLCCSD && c2) ccsd_sigma1_doubles_t<T>(c2, s1);
   }

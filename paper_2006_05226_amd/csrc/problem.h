@@ -8,6 +8,7 @@
 
 struct mlcc_context {
   int device = 0;
+  mlcc::Profiler prof;
   bool own_stream = false;
   mlcc::Alloc al;
   mlcc::Exec ex;
@@ -41,6 +42,10 @@ struct G {
        const void *cin = nullptr) {
     a.C = p; a.sCm = sm; a.sCn = sn; a.sCz = sz; a.alpha = alpha; a.beta = beta;
     a.Cin = cin ? cin : p;
+    return *this;
+  }
+  G &tag(const char *t) {
+    a.tag = t;
     return *this;
   }
   void run(Exec &ex, Prec p, bool out64) const { gemm(ex, p, a, out64); }

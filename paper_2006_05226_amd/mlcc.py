@@ -54,12 +54,18 @@ class Result(C.Structure):
                 ("es_iterations", C.c_int32)]
 
 
+class KernelStat(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("ms", C.c_double),
+                ("flops", C.c_double)]
+
+
 EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "mlcc_context_bytes",
            "mlcc_problem_create", "mlcc_problem_destroy", "mlcc_problem_dims",
            "mlcc_set_amplitudes", "mlcc_residual", "mlcc_ground_state",
            "mlcc_jacobian_transform", "mlcc_jacobian_transform_eff", "mlcc_davidson_solve",
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
-           "mlcc_request_footprint", "mlcc_gemm", "mlcc_debug_get"]
+           "mlcc_request_footprint", "mlcc_gemm", "mlcc_debug_get", "mlcc_profile_enable",
+           "mlcc_profile_get"]
 
 _lib = None
 
@@ -96,6 +102,8 @@ def load(path: str = LIB_PATH):
         "mlcc_gemm": (i32, [vp, i32, i64, i64, i64, i64, i64, dbl, vp, P(i64), vp, P(i64), dbl,
                             vp, P(i64)]),
         "mlcc_debug_get": (i32, [vp, i32, vp]),
+        "mlcc_profile_enable": (i32, [vp, i32]),
+        "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -162,6 +170,17 @@ class Context:
         c3 = (C.c_int64 * 3)(*sC)
         return self.check(self.lib.mlcc_gemm(self.h, prec, M, N, K, R, Z, alpha, _ptr(A), a4,
                                              _ptr(B), b4, beta, _ptr(Cm), c3))
+
+    def profile(self, on=True):
+        self.check(self.lib.mlcc_profile_enable(self.h, 1 if on else 0))
+
+    def profile_stats(self):
+        buf = (KernelStat * 256)()
+        n = self.lib.mlcc_profile_get(self.h, buf, 256)
+        if n < 0:
+            self.check(n)
+        return {buf[i].name.decode(): dict(launches=buf[i].launches, ms=buf[i].ms,
+                                           flops=buf[i].flops) for i in range(min(n, 256))}
 
     def close(self):
         if self.h:

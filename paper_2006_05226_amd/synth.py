@@ -64,13 +64,14 @@ def gen_inputs(n_occ: int, n_vir: int, n_chol: int, n_occ_act: int | None = None
     rng = np.random.default_rng(seed)
     sigma = chol_scale(n_occ, n_vir) if scale is None else scale
     L = np.empty((n_chol, n, n), dtype=dtype)
-    iu = np.triu_indices(n)
-    for K in range(n_chol):
-        z = rng.standard_normal((n, n))
-        blk = np.zeros((n, n))
-        blk[iu] = z[iu]
-        blk = blk + np.triu(blk, 1).T
-        L[K] = (sigma * np.exp(-K / 10.0)) * blk
+    chunk = max(1, min(n_chol, (1 << 24) // (n * n)))
+    for K0 in range(0, n_chol, chunk):
+        # drawing a (k, n, n) block consumes the stream exactly like k (n, n) draws
+        z = rng.standard_normal((min(chunk, n_chol - K0), n, n))
+        up = np.triu(z)
+        blk = up + np.triu(z, 1).transpose(0, 2, 1)
+        scale = sigma * np.exp(-np.arange(K0, K0 + len(z)) / 10.0)
+        L[K0:K0 + len(z)] = scale[:, None, None] * blk
     e_occ = np.sort(rng.uniform(-1.5, -0.3, n_occ))
     e_vir = np.sort(rng.uniform(0.1, 3.0, n_vir))
     e_occ = np.concatenate([e_occ[n_occ - n_occ_act:], e_occ[: n_occ - n_occ_act]])
