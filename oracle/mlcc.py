@@ -505,7 +505,12 @@ def davidson(P: Problem, t1, x2, n_roots, tol=1e-8, max_iter=100, n_guess=None,
              max_space=None):
     """Lowest n_roots eigenvalues of the Jacobian.  Vectors are stored as
     (singles, full symmetric doubles) and the Euclidean metric of that storage
-    is used throughout.  Guesses: unit singles at the lowest e_A - e_I."""
+    is used throughout.  Guesses: unit singles at the lowest e_A - e_I.
+
+    The doubles amplitudes live in the subspace symmetric under (ai) <-> (bj);
+    transformed vectors and new directions are projected onto it, so that the
+    rounding-level asymmetry of the complex-step transform cannot excite the
+    (unphysical) antisymmetric part of the operator."""
     d = P.d
     n1 = d.V * d.O
     full2 = has_doubles(P)
@@ -514,11 +519,19 @@ def davidson(P: Problem, t1, x2, n_roots, tol=1e-8, max_iter=100, n_guess=None,
     n_guess = n_guess or (n_roots + 2)
     max_space = max_space or max(20 * n_roots, n_guess + 2 * n_roots)
 
+    def sym(x):
+        if not full2:
+            return x
+        y = x.copy()
+        D2 = y[n1:].reshape(d.M, d.M)
+        y[n1:] = (0.5 * (D2 + D2.T)).ravel()
+        return y
+
     def apply(x):
         c1 = x[:n1].reshape(d.V, d.O)
         c2 = x[n1:].reshape(d.v, d.o, d.v, d.o) if full2 else None
         s1, s2 = jacobian_transform(P, t1, x2, c1, c2)
-        return np.concatenate([s1.ravel(), s2.ravel()]) if full2 else s1.ravel()
+        return sym(np.concatenate([s1.ravel(), s2.ravel()]) if full2 else s1.ravel())
 
     order = np.lexsort((np.arange(n1) % d.O, np.arange(n1) // d.O, Dg[:n1]))
     V = np.zeros((0, dim))
@@ -531,10 +544,12 @@ def davidson(P: Problem, t1, x2, n_roots, tol=1e-8, max_iter=100, n_guess=None,
     omega = None
     for it in range(1, max_iter + 1):
         for w in new:
+            w = sym(w)
+            n0 = np.linalg.norm(w)
             for _ in range(2):
                 w = w - V.T @ (V @ w)
             nw = np.linalg.norm(w)
-            if nw < 1e-10:
+            if nw < 1e-10 or nw < 1e-8 * n0:
                 continue
             w = w / nw
             V = np.vstack([V, w])
