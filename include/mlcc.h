@@ -223,6 +223,14 @@ mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int
                       const void *B, const int64_t sB[4], double beta, void *C,
                       const int64_t sC[3]);
 
+/* As mlcc_gemm with two-level row and column indices: lvl = {Mlo, sA_m_hi,
+ * sC_m_hi, Nlo, sB_n_hi, sC_n_hi}; row m has offset (m/Mlo)*hi + (m%Mlo)*lo
+ * (lo = the ordinary stride), columns likewise; Mlo or Nlo 0 = one level. */
+mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int64_t K,
+                       int64_t R, int64_t Z, double alpha, const void *A, const int64_t sA[4],
+                       const void *B, const int64_t sB[4], double beta, void *C,
+                       const int64_t sC[3], const int64_t lvl[6]);
+
 /* Per-contraction timing: when enabled, every GEMM-engine launch is bracketed
  * by HIP events on the context stream and accumulated under the name of the
  * contraction it computes (e.g. "g_aibj", "ccs_vv").  flops counts the

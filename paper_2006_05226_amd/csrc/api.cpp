@@ -461,6 +461,33 @@ mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int
   });
 }
 
+mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int64_t K,
+                       int64_t R, int64_t Z, double alpha, const void *A, const int64_t sA[4],
+                       const void *B, const int64_t sB[4], double beta, void *C,
+                       const int64_t sC[3], const int64_t lvl[6]) {
+  if (!ctx) return MLCC_E_ARG;
+  return guarded(ctx, [&]() -> mlcc_status {
+    MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32, MLCC_E_ARG, "bad precision");
+    MLCC_REQUIRE(M >= 0 && N >= 0 && K >= 0 && R >= 1 && Z >= 1, MLCC_E_ARG, "bad sizes");
+    MLCC_REQUIRE(A && B && C && sA && sB && sC && lvl, MLCC_E_ARG, "NULL argument");
+    MLCC_REQUIRE(lvl[0] >= 0 && lvl[3] >= 0, MLCC_E_ARG, "bad two-level sizes");
+    MLCC_REQUIRE(is_device_ptr(A) && is_device_ptr(B) && is_device_ptr(C), MLCC_E_ARG,
+                 "mlcc_gemm2 takes device pointers");
+    GemmArgs a;
+    a.M = M; a.N = N; a.K = K; a.R = R; a.Z = Z;
+    a.A = A; a.sAm = sA[0]; a.sAk = sA[1]; a.sAr = sA[2]; a.sAz = sA[3];
+    a.B = B; a.sBk = sB[0]; a.sBn = sB[1]; a.sBr = sB[2]; a.sBz = sB[3];
+    a.C = C; a.Cin = C; a.sCm = sC[0]; a.sCn = sC[1]; a.sCz = sC[2];
+    a.alpha = alpha; a.beta = beta;
+    a.Mlo = lvl[0]; a.sAm_hi = lvl[1]; a.sCm_hi = lvl[2];
+    a.Nlo = lvl[3]; a.sBn_hi = lvl[4]; a.sCn_hi = lvl[5];
+    MLCC_HIP(hipSetDevice(ctx->device));
+    gemm(ctx->ex, prec == MLCC_FP64 ? Prec::F64 : Prec::F32, a, prec == MLCC_FP64);
+    MLCC_HIP(hipStreamSynchronize(ctx->ex.stream));
+    return MLCC_OK;
+  });
+}
+
 mlcc_status mlcc_profile_enable(mlcc_context *ctx, int32_t on) {
   if (!ctx) return MLCC_E_ARG;
   return guarded(ctx, [&]() -> mlcc_status {

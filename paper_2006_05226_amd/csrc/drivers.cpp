@@ -156,8 +156,16 @@ DavidsonResult davidson(Exec &ex, Alloc *al, int64_t dim, int n_roots, int n_gue
   std::vector<double> Yh;
   for (int it = 1; it <= max_iter; ++it) {
     out.iterations = it;
-    // --- orthonormalise the new block against V and within itself
+    // --- orthonormalise the new block against V and within itself; a
+    // direction that loses all but 1e-8 of its norm is dropped
     const int k_old = k;
+    std::vector<double> n0(nw, 0.0);
+    for (int w = 0; w < nw; ++w)
+      k::dot(ex, dim, W + (int64_t)w * dim, W + (int64_t)w * dim, small.as<double>() + w);
+    if (nw > 0) {
+      fetch(small.as<double>(), nw);
+      for (int w = 0; w < nw; ++w) n0[w] = std::sqrt(hbuf[w]);
+    }
     for (int pass = 0; pass < 2 && k > 0; ++pass) {
       double *C = Cb.as<double>();
       gram(ex, k, nw, dim, V, W, dim, C);  // C[i][w] = v_i . w
@@ -177,7 +185,7 @@ DavidsonResult davidson(Exec &ex, Alloc *al, int64_t dim, int n_roots, int n_gue
       k::dot(ex, dim, wv, wv, small.as<double>());
       fetch(small.as<double>(), 1);
       nrm = std::sqrt(hbuf[0]);
-      if (!(nrm > 1e-10) || k >= max_space) continue;
+      if (!(nrm > 1e-10) || nrm < 1e-8 * n0[w] || k >= max_space) continue;
       MLCC_HIP(hipMemcpyAsync(V + (int64_t)k * dim, wv, dim * sizeof(double),
                               hipMemcpyDeviceToDevice, ex.stream));
       k::scale(ex, dim, 1.0 / nrm, V + (int64_t)k * dim);

@@ -136,22 +136,22 @@ __global__ void k_u_of(int o, int v, const double *x, TU *u) {
 
 // out = G + G^T + eps_aibj * c  through 32x32 LDS tiles (coalesced transpose)
 template <typename TG>
-__global__ void k_sym_plus_diag(int64_t M, const TG *G, const double *eps_ai, const double *c,
-                                double *out) {
+__global__ void k_sym_plus_diag(int64_t M, const TG *G, int64_t ldg, const double *eps_ai,
+                                const double *c, double *out) {
   __shared__ double tile[32][33];
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   // load G[c0.., r0..] transposed into tile
   for (int y = ty; y < 32; y += 8) {
     const int64_t rr = c0 + y, cc = r0 + tx;
-    tile[y][tx] = (rr < M && cc < M) ? (double)G[rr * M + cc] : 0.0;
+    tile[y][tx] = (rr < M && cc < M) ? (double)G[rr * ldg + cc] : 0.0;
   }
   __syncthreads();
   for (int y = ty; y < 32; y += 8) {
     const int64_t r = r0 + y, cc = c0 + tx;
     if (r < M && cc < M) {
       const int64_t off = r * M + cc;
-      double v = (double)G[off] + tile[tx][y];
+      double v = (double)G[r * ldg + cc] + tile[tx][y];
       if (c) v += (eps_ai[r] + eps_ai[cc]) * c[off];
       out[off] = v;
     }
@@ -159,20 +159,21 @@ __global__ void k_sym_plus_diag(int64_t M, const TG *G, const double *eps_ai, co
 }
 
 template <typename TG, typename TO>
-__global__ void k_sym_div(int64_t M, const TG *G, const double *eps_ai, double w, TO *out) {
+__global__ void k_sym_div(int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
+                          TO *out) {
   __shared__ double tile[32][33];
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int y = ty; y < 32; y += 8) {
     const int64_t rr = c0 + y, cc = r0 + tx;
-    tile[y][tx] = (rr < M && cc < M) ? (double)G[rr * M + cc] : 0.0;
+    tile[y][tx] = (rr < M && cc < M) ? (double)G[rr * ldg + cc] : 0.0;
   }
   __syncthreads();
   for (int y = ty; y < 32; y += 8) {
     const int64_t r = r0 + y, cc = c0 + tx;
     if (r < M && cc < M) {
       const int64_t off = r * M + cc;
-      out[off] = (TO)(((double)G[off] + tile[tx][y]) / (w - (eps_ai[r] + eps_ai[cc])));
+      out[off] = (TO)(((double)G[r * ldg + cc] + tile[tx][y]) / (w - (eps_ai[r] + eps_ai[cc])));
     }
   }
 }
@@ -255,6 +256,41 @@ __global__ void k_energy_singles(int64_t n, int O, const T *Lt, const T *L, doub
   __syncthreads();
   const double qqs = block_sum(qq);
   if (threadIdx.x == 0) part[K] = 2.0 * trs * trs - qqs;
+}
+
+// dst[j0][j1][j2][j3] (contiguous, dims n0..n3) = a * src[sum j_k s_k] + b * dst
+template <typename TD, typename TS>
+__global__ void k_permute4(TD *dst, const TS *src, int64_t n0, int64_t n1, int64_t n2, int64_t n3,
+                           int64_t s0, int64_t s1, int64_t s2, int64_t s3, double a, double b) {
+  const int64_t total = n0 * n1 * n2 * n3;
+  GRID_STRIDE(t, total) {
+    int64_t r = t;
+    const int64_t j3 = r % n3;
+    r /= n3;
+    const int64_t j2 = r % n2;
+    r /= n2;
+    const int64_t j1 = r % n1;
+    const int64_t j0 = r / n1;
+    double v = a * (double)src[j0 * s0 + j1 * s1 + j2 * s2 + j3 * s3];
+    if (b != 0.0) v += b * (double)dst[t];
+    dst[t] = (TD)v;
+  }
+}
+
+// out += R + R^T  (M x M) through 32x32 LDS tiles
+__global__ void k_sym_accum(int64_t M, const double *R, double *out) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t rr = c0 + y, cc = r0 + tx;
+    tile[y][tx] = (rr < M && cc < M) ? R[rr * M + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + y, cc = c0 + tx;
+    if (r < M && cc < M) out[r * M + cc] += R[r * M + cc] + tile[tx][y];
+  }
 }
 
 }  // namespace
@@ -358,19 +394,22 @@ template <typename TU> void u_of(Exec &ex, int o, int v, const double *x, TU *u)
 }
 
 template <typename TG>
-void sym_plus_diag(Exec &ex, int64_t M, const TG *G, const double *eps_ai, const double *c,
-                   double *out) {
+void sym_plus_diag(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai,
+                   const double *c, double *out) {
   if (M == 0) return;
   dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32));
-  hipLaunchKernelGGL((k_sym_plus_diag<TG>), grid, dim3(256), 0, ex.stream, M, G, eps_ai, c, out);
+  hipLaunchKernelGGL((k_sym_plus_diag<TG>), grid, dim3(256), 0, ex.stream, M, G, ldg, eps_ai, c,
+                     out);
   MLCC_HIP(hipGetLastError());
 }
 
 template <typename TG, typename TO>
-void sym_div(Exec &ex, int64_t M, const TG *G, const double *eps_ai, double w, TO *out) {
+void sym_div(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
+             TO *out) {
   if (M == 0) return;
   dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32));
-  hipLaunchKernelGGL((k_sym_div<TG, TO>), grid, dim3(256), 0, ex.stream, M, G, eps_ai, w, out);
+  hipLaunchKernelGGL((k_sym_div<TG, TO>), grid, dim3(256), 0, ex.stream, M, G, ldg, eps_ai, w,
+                     out);
   MLCC_HIP(hipGetLastError());
 }
 
@@ -428,6 +467,31 @@ void energy_singles(Exec &ex, int64_t J, int64_t n, int O, const T *Lt, const T 
   (void)part2;
 }
 
+template <typename TD, typename TS>
+void permute4(Exec &ex, TD *dst, const TS *src, const int64_t n[4], const int64_t s[4], double a,
+              double b) {
+  const int64_t total = n[0] * n[1] * n[2] * n[3];
+  if (total <= 0) return;
+  hipLaunchKernelGGL((k_permute4<TD, TS>), dim3(blocks_for(total)), dim3(TPB), 0, ex.stream, dst,
+                     src, n[0], n[1], n[2], n[3], s[0], s[1], s[2], s[3], a, b);
+  MLCC_HIP(hipGetLastError());
+}
+template void permute4<double, double>(Exec &, double *, const double *, const int64_t *,
+                                       const int64_t *, double, double);
+template void permute4<float, float>(Exec &, float *, const float *, const int64_t *,
+                                     const int64_t *, double, double);
+template void permute4<float, double>(Exec &, float *, const double *, const int64_t *,
+                                      const int64_t *, double, double);
+template void permute4<double, float>(Exec &, double *, const float *, const int64_t *,
+                                      const int64_t *, double, double);
+
+void sym_accum(Exec &ex, int64_t M, const double *R, double *out) {
+  if (M == 0) return;
+  dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32));
+  hipLaunchKernelGGL(k_sym_accum, grid, dim3(256), 0, ex.stream, M, R, out);
+  MLCC_HIP(hipGetLastError());
+}
+
 // explicit instantiations
 #define INST_PACK(TD, TS)                                                                      \
   template void pack2d<TD, TS>(Exec &, TD *, const TS *, int64_t, int64_t, int64_t, int64_t,   \
@@ -448,14 +512,14 @@ template void mlcc2_s_u<double, float>(Exec &, int, int, const double *, const d
                                        float *);
 template void u_of<double>(Exec &, int, int, const double *, double *);
 template void u_of<float>(Exec &, int, int, const double *, float *);
-template void sym_plus_diag<double>(Exec &, int64_t, const double *, const double *,
+template void sym_plus_diag<double>(Exec &, int64_t, const double *, int64_t, const double *,
                                     const double *, double *);
-template void sym_plus_diag<float>(Exec &, int64_t, const float *, const double *, const double *,
-                                   double *);
-template void sym_div<double, double>(Exec &, int64_t, const double *, const double *, double,
-                                      double *);
-template void sym_div<double, float>(Exec &, int64_t, const double *, const double *, double,
-                                     float *);
+template void sym_plus_diag<float>(Exec &, int64_t, const float *, int64_t, const double *,
+                                   const double *, double *);
+template void sym_div<double, double>(Exec &, int64_t, const double *, int64_t, const double *,
+                                      double, double *);
+template void sym_div<double, float>(Exec &, int64_t, const double *, int64_t, const double *,
+                                     double, float *);
 template void mlcc2_omega2<double>(Exec &, int64_t, const double *, const double *,
                                    const double *, double *);
 template void occ_trace<double>(Exec &, int64_t, int64_t, int, const double *, double *);

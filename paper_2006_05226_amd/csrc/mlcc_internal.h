@@ -129,6 +129,13 @@ struct GemmArgs {
   int64_t sCm = 0, sCn = 0, sCz = 0;
   double alpha = 1.0, beta = 0.0;
   const char *tag = "gemm";  // contraction name for the profiler
+  // Optional two-level row / column index: when Mlo > 0, row m is
+  // (m / Mlo, m % Mlo) and its offset is (m / Mlo) * s_hi + (m % Mlo) * s_lo,
+  // where s_lo is the ordinary stride (sAm, sCm) and s_hi is sAm_hi / sCm_hi.
+  // Likewise Nlo for columns (sBn, sCn with sBn_hi, sCn_hi).  This lets one
+  // launch cover a batch of trial vectors stored back to back.
+  int64_t Mlo = 0, sAm_hi = 0, sCm_hi = 0;
+  int64_t Nlo = 0, sBn_hi = 0, sCn_hi = 0;
 };
 
 // prec selects the operand type (double or float) and the MFMA; out_f64
@@ -168,11 +175,12 @@ template <typename TU>
 void u_of(Exec &ex, int o, int v, const double *x, TU *u);
 // out = G + G^T + d .* c  (M x M, f64 out); G type TG
 template <typename TG>
-void sym_plus_diag(Exec &ex, int64_t M, const TG *G, const double *eps_ai, const double *c,
-                   double *out);
+void sym_plus_diag(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai,
+                   const double *c, double *out);
 // x[ai][bj] /= (w - eps_aibj) after forming G + G^T  (effective singles)
 template <typename TG, typename TO>
-void sym_div(Exec &ex, int64_t M, const TG *G, const double *eps_ai, double w, TO *out);
+void sym_div(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
+             TO *out);
 // Delta t = -Omega / denominators
 void qn_step_singles(Exec &ex, int V, int O, const double *eps, const double *om, double *t);
 void qn_step_doubles(Exec &ex, int64_t M, const double *eps_ai, const double *om, double *t);
@@ -194,6 +202,12 @@ void nonfinite(Exec &ex, int64_t n, const double *x, double *res);
 template <typename TG>
 void mlcc2_omega2(Exec &ex, int64_t M, const TG *g, const double *eps_ai, const double *s,
                   double *out);
+// dst[j0][j1][j2][j3] (contiguous, dims n[]) = a * src[sum_k j_k s[k]] + b * dst
+template <typename TD, typename TS>
+void permute4(Exec &ex, TD *dst, const TS *src, const int64_t n[4], const int64_t s[4], double a,
+              double b);
+// out += R + R^T (M x M)
+void sym_accum(Exec &ex, int64_t M, const double *R, double *out);
 }  // namespace k
 
 }  // namespace mlcc

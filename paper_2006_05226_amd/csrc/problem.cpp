@@ -238,6 +238,10 @@ template <typename T> void mlcc_problem::dress_t(bool full_fock) {
   } else {
     fock_block(O, V, 0, O);   // F~_AI
     fock_block(0, o, O, v);   // F~_jb (active)
+    if (model == MLCC_MLCCSD) {
+      fock_block(O, v, O, v);  // F~_bc (active)
+      fock_block(0, o, 0, o);  // F~_kj (active)
+    }
   }
   fock_full = full_fock;
 }
@@ -364,98 +368,132 @@ void mlcc_problem::prepare_jacobian() {
   else prepare_jacobian_t<float>();
 }
 
-// One vector.  c2/s2 may be null (singles-only).  w_eff: when finite and c2 is
-// null, the doubles are eliminated, c2 = (A21 c1)/(w - eps) (MLCC2 only).
+// A batch of nb vectors at once: c[vec] at c + vec*ld (singles first, then
+// the doubles when c2 is present), sigma likewise.  With has_c2 false the
+// vectors are singles only; then, if w_eff is finite (MLCC2), the doubles are
+// eliminated, c2 = (A21 c1)/(w_eff - eps_aibj), and only sigma_1 is produced.
 template <typename T>
-void mlcc_problem::transform_one_t(const double *c1, const double *c2, double *s1, double *s2,
-                                   double w_eff) {
+void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool has_c2,
+                                     double *sigma, double w_eff) {
   Exec &x = *ex;
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
+  const int64_t n1 = d.n1, b = nb;
   const Prec p = prec_of<T>();
   const bool o64 = sizeof(T) == 8;
   const T *lt = off<T>(Lt);
   const double *F = Ft.as<double>();
-  cT.ensure(al, d.n1 * sizeof(T));
+  cT.ensure(al, b * n1 * sizeof(T));
   T *ct = off<T>(cT);
-  if (o64) MLCC_HIP(hipMemcpyAsync(ct, c1, d.n1 * 8, hipMemcpyDeviceToDevice, x.stream));
-  else k::convert<float, double>(x, cT.as<float>(), c1, d.n1);
+  k::pack2d<T, double>(x, ct, c, b, ld, 1, n1, 0);
 
-  // CCS terms
-  G(V, O, V).A(F + O * n + O, n, 1).B(c1, O, 1).C(s1, O, 1).run(x, Prec::F64, true);
-  G(V, O, O).A(c1, O, 1).B(F, n, 1).C(s1, O, 1, 0, -1.0, 1.0).run(x, Prec::F64, true);
-  Xk.ensure(al, J * sizeof(T));
-  G(J, 1, V, O).A(lt + O, n2, 1, n).B(ct, O, 0, 1).C(Xk.p, 1, 0).run(x, p, o64);
-  G(O, 1, J, 1, V).A(lt + O * n, 1, n2, 0, n).B(Xk.p, 1, 0).C(s1, 1, 0, O, 2.0, 1.0)
-      .run(x, p, true);
-  W.ensure(al, (size_t)J * V * O * sizeof(T));
-  G(V, O, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(W.p, O, 1, V * O).tag("ccs_W").run(x, p, o64);
-  G(V, O, V, J).A(lt + O * n + O, n, 1, n2).B(W.p, O, 1, V * O).C(s1, O, 1, 0, -1.0, 1.0)
-      .tag("ccs_vv").run(x, p, true);
+  // CCS terms: F~_AB c_BI - c_AJ F~_JI + 2 (L~^K_JB c_BJ) L~^K_AI - (L~^K_AB c_BJ) L~^K_JI
+  G(V, O, V, 1, b).A(F + O * n + O, n, 1, 0, 0).B(c, O, 1, 0, ld).C(sigma, O, 1, ld)
+      .tag("ccs_fock").run(x, Prec::F64, true);
+  G(V, O, O, 1, b).A(c, O, 1, 0, ld).B(F, n, 1, 0, 0).C(sigma, O, 1, ld, -1.0, 1.0)
+      .tag("ccs_fock").run(x, Prec::F64, true);
+  Xk.ensure(al, J * b * sizeof(T));
+  G(J, b, V, O).A(lt + O, n2, 1, n).B(ct, O, n1, 1).C(Xk.p, b, 1).tag("ccs_Xk").run(x, p, o64);
+  G(O, b, J, 1, V).A(lt + O * n, 1, n2, 0, n).B(Xk.p, b, 1).C(sigma, 1, ld, O, 2.0, 1.0)
+      .tag("ccs_coul").run(x, p, true);
+  W.ensure(al, (size_t)J * b * V * O * sizeof(T));
+  G(b * V, O, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(W.p, O, 1, b * V * O)
+      .tag("ccs_W").run(x, p, o64);
+  G(V, b * O, V, J).A(lt + O * n + O, n, 1, n2).B(W.p, O, 1, b * V * O).Nhi(O, V * O, ld)
+      .C(sigma, O, 1, 0, -1.0, 1.0).tag("ccs_vv").run(x, p, true);
   if (!has_doubles()) return;
 
-  // MLCC2 singles-singles terms with the ground-state u
-  G(V, o, O).A(ct, O, 1).B(Xint.p, o, 1).C(s1, O, 1, 0, -1.0, 1.0).run(x, p, true);
-  G(v, O, V).A(Yint.p, V, 1).B(ct, O, 1).C(s1, O, 1, 0, -1.0, 1.0).run(x, p, true);
-  qv.ensure(al, M * sizeof(T));
-  rv.ensure(al, M * sizeof(T));
-  P.ensure(al, (size_t)J * o * O * sizeof(T));
-  G(M, 1, J).A(off<T>(Lvo0), 1, M).B(Xk.p, 1, 0).C(qv.p, 1, 0).run(x, p, o64);
-  G(o, O, V, 1, J).A(lt + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).C(P.p, O, 1, o * O).run(x, p, o64);
-  G(v, o, O, J).A(lt + O, 1, n, n2).B(P.p, 1, O, o * O).C(rv.p, o, 1).run(x, p, o64);
-  // w = 2 q - r, in place of q
-  k::lincomb<T>(x, M, 2.0, off<T>(qv), -1.0, off<T>(rv), off<T>(qv));
-  G(o, 1, M, 1, v).A(u.p, M, 1, 0, o * M).B(qv.p, 1, 0).C(s1, 1, 0, O, 1.0, 1.0).run(x, p, true);
+  // MLCC2 singles-singles terms with the ground-state u:
+  //   - c_AJ X_Ji - Y_aB c_BI + u_ai,ck (2 q_ck - r_ck)
+  G(V, o, O, 1, b).A(ct, O, 1, 0, n1).B(Xint.p, o, 1, 0, 0).C(sigma, O, 1, ld, -1.0, 1.0)
+      .tag("jac_X").run(x, p, true);
+  G(v, O, V, 1, b).A(Yint.p, V, 1, 0, 0).B(ct, O, 1, 0, n1).C(sigma, O, 1, ld, -1.0, 1.0)
+      .tag("jac_Y").run(x, p, true);
+  qv.ensure(al, M * b * sizeof(T));
+  rv.ensure(al, M * b * sizeof(T));
+  P.ensure(al, (size_t)J * o * b * O * sizeof(T));
+  G(M, b, J).A(off<T>(Lvo0), 1, M).B(Xk.p, b, 1).C(qv.p, b, 1).tag("jac_q").run(x, p, o64);
+  G(o, b * O, V, 1, J).A(lt + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).Nhi(O, n1, O)
+      .C(P.p, b * O, 1, o * b * O).tag("jac_P").run(x, p, o64);
+  G(v, o * b, O, J).A(lt + O, 1, n, n2).B(P.p, 1, O, o * b * O).C(rv.p, o * b, 1)
+      .tag("jac_r").run(x, p, o64);
+  k::lincomb<T>(x, M * b, 2.0, off<T>(qv), -1.0, off<T>(rv), off<T>(qv));
+  G(o, b, M, 1, v).A(u.p, M, 1, 0, o * M).B(qv.p, b, 1).C(sigma, 1, ld, O, 1.0, 1.0)
+      .tag("jac_uw").run(x, p, true);
 
-  // doubles part: dL~_ai = sum_B L~_aB c_Bi - sum_J c_aJ L~_Ji, G = L~ai^T dL~ai
-  dLai.ensure(al, (size_t)J * M * sizeof(T));
-  G(v, o, V, 1, J).A(lt + O * n + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).C(dLai.p, o, 1, M)
-      .tag("dLai").run(x, p, o64);
-  G(v, o, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(dLai.p, o, 1, M, -1.0, 1.0)
-      .run(x, p, o64);
-  Gm.ensure(al, (size_t)M * M * sizeof(double));
-  G(M, M, J).A(off<T>(Lai), 1, M).B(dLai.p, M, 1).C(Gm.p, M, 1).tag("sigma2_LdL").run(x, p, true);
+  // singles -> doubles: dL~_ai = sum_B L~_aB c_Bi - sum_J c_aJ L~_Ji  ([K][vec][ai]),
+  // G[ai][vec, bj] = sum_K L~^K_ai dL~^K_bj
+  dLai.ensure(al, (size_t)J * b * M * sizeof(T));
+  G(v, b * o, V, 1, J).A(lt + O * n + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).Nhi(o, n1, M)
+      .C(dLai.p, o, 1, b * M).tag("dLai").run(x, p, o64);
+  G(b * v, o, O, 1, J).A(ct, O, 1, 0, 0).Mhi(v, n1, M).B(lt, n, 1, 0, n2)
+      .C(dLai.p, o, 1, b * M, -1.0, 1.0).tag("dLai").run(x, p, o64);
+  Gm.ensure(al, (size_t)M * b * M * sizeof(double));
+  G(M, b * M, J).A(off<T>(Lai), 1, M).B(dLai.p, b * M, 1).C(Gm.p, b * M, 1)
+      .tag("sigma2_LdL").run(x, p, true);
 
-  const double *c2u = c2;
-  if (!c2 && std::isfinite(w_eff)) {
-    c2e.ensure(al, (size_t)M * M * sizeof(double));
-    k::sym_div<double, double>(x, M, Gm.as<double>(), eps_ai.as<double>(), w_eff,
-                               c2e.as<double>());
-    c2u = c2e.as<double>();
-  } else if (s2) {
-    if (model == MLCC_MLCC2)
-      k::sym_plus_diag<double>(x, M, Gm.as<double>(), eps_ai.as<double>(), c2, s2);
-    else
-      ccsd_sigma2_t<T>(c1, c2, s2);
+  // the doubles used by doubles -> singles: the trial doubles, or the
+  // eliminated ones of the effective transformation
+  const double *c2base = nullptr;
+  int64_t c2ld = 0;
+  if (has_c2) {
+    c2base = c + n1;
+    c2ld = ld;
+    for (int64_t vec = 0; vec < b; ++vec) {
+      double *s2 = sigma + vec * ld + n1;
+      if (model == MLCC_MLCC2)
+        k::sym_plus_diag<double>(x, M, Gm.as<double>() + vec * M, b * M, eps_ai.as<double>(),
+                                 c + vec * ld + n1, s2);
+      else
+        ccsd_sigma2_t<T>(c + vec * ld, c + vec * ld + n1, Gm.as<double>() + vec * M, b * M,
+                         off<T>(dLai, vec * M), b * M, s2);
+    }
+  } else if (std::isfinite(w_eff)) {
+    c2e.ensure(al, (size_t)b * M * M * sizeof(double));
+    for (int64_t vec = 0; vec < b; ++vec)
+      k::sym_div<double, double>(x, M, Gm.as<double>() + vec * M, b * M, eps_ai.as<double>(),
+                                 w_eff, c2e.as<double>() + vec * M * M);
+    c2base = c2e.as<double>();
+    c2ld = M * M;
   }
-  if (c2u) {
-    // doubles -> singles with u = 2 c2 - c2(i<->j)
-    ut.ensure(al, (size_t)M * M * sizeof(T));
-    Zc.ensure(al, (size_t)J * M * sizeof(T));
-    k::u_of<T>(x, d.o, d.v, c2u, off<T>(ut));
-    G(J, M, M).A(off<T>(Lvo0), M, 1).B(ut.p, M, 1).C(Zc.p, M, 1).tag("Zc_uL").run(x, p, o64);
-    omega_singles_t<T>(Zc.p, ut.p, s1, false);
-    if (model == MLCC_MLCCSD && c2) ccsd_sigma1_doubles_t<T>(c2, s1);
-  }
+  if (!c2base) return;
+  // doubles -> singles: the Omega_1 doubles terms with u = 2 c2 - c2(i<->j)
+  ut.ensure(al, (size_t)b * M * M * sizeof(T));
+  Zc.ensure(al, (size_t)J * b * M * sizeof(T));
+  for (int64_t vec = 0; vec < b; ++vec)
+    k::u_of<T>(x, d.o, d.v, c2base + vec * c2ld, off<T>(ut, vec * M * M));
+  G(J, b * M, M).A(off<T>(Lvo0), M, 1).B(ut.p, M, 1).Nhi(M, M * M, M).C(Zc.p, b * M, 1)
+      .tag("Zc_uL").run(x, p, o64);
+  G(V, b * o, v, J).A(lt + O * n + O, n, 1, n2).B(Zc.p, o, 1, b * M).Nhi(o, M, ld)
+      .C(sigma, O, 1, 0, 1.0, 1.0).tag("d2s_A1").run(x, p, true);
+  G(b * v, O, o, J).A(Zc.p, o, 1, b * M).Mhi(v, M, ld).B(lt, n, 1, n2)
+      .C(sigma, O, 1, 0, -1.0, 1.0).tag("d2s_B1").run(x, p, true);
+  fvec.ensure(al, M * sizeof(T));
+  k::pack2d_t<T, double>(x, off<T>(fvec), F + O, 1, 0, o, v, n);
+  for (int64_t vec = 0; vec < b; ++vec)
+    G(o, 1, M, 1, v).A(off<T>(ut, vec * M * M), M, 1, 0, o * M).B(fvec.p, 1, 0)
+        .C(sigma + vec * ld, 1, 0, O, 1.0, 1.0).tag("d2s_C1").run(x, p, true);
 }
+
+static constexpr int kMaxBatch = 8;
 
 void mlcc_problem::transform(int nvec, const double *c, double *sigma) {
   const int64_t dm = dim();
-  for (int i = 0; i < nvec; ++i) {
-    const double *c1 = c + i * dm;
-    double *s1 = sigma + i * dm;
-    const double *c2 = has_doubles() ? c1 + d.n1 : nullptr;
-    double *s2 = has_doubles() ? s1 + d.n1 : nullptr;
-    if (prec == MLCC_FP64) transform_one_t<double>(c1, c2, s1, s2, NAN);
-    else transform_one_t<float>(c1, c2, s1, s2, NAN);
+  for (int i0 = 0; i0 < nvec; i0 += kMaxBatch) {
+    const int nb = std::min(kMaxBatch, nvec - i0);
+    if (prec == MLCC_FP64)
+      transform_batch_t<double>(nb, c + i0 * dm, dm, has_doubles(), sigma + i0 * dm, NAN);
+    else
+      transform_batch_t<float>(nb, c + i0 * dm, dm, has_doubles(), sigma + i0 * dm, NAN);
   }
 }
 
 void mlcc_problem::transform_eff(double w, int nvec, const double *c1, double *s1) {
-  for (int i = 0; i < nvec; ++i) {
+  for (int i0 = 0; i0 < nvec; i0 += kMaxBatch) {
+    const int nb = std::min(kMaxBatch, nvec - i0);
     if (prec == MLCC_FP64)
-      transform_one_t<double>(c1 + i * d.n1, nullptr, s1 + i * d.n1, nullptr, w);
+      transform_batch_t<double>(nb, c1 + i0 * d.n1, d.n1, false, s1 + i0 * d.n1, w);
     else
-      transform_one_t<float>(c1 + i * d.n1, nullptr, s1 + i * d.n1, nullptr, w);
+      transform_batch_t<float>(nb, c1 + i0 * d.n1, d.n1, false, s1 + i0 * d.n1, w);
   }
 }

@@ -44,6 +44,16 @@ struct G {
     a.Cin = cin ? cin : p;
     return *this;
   }
+  // two-level rows: m = (hi, lo) with lo < mlo; strides of hi for A and C
+  G &Mhi(int64_t mlo, int64_t sA_hi, int64_t sC_hi) {
+    a.Mlo = mlo; a.sAm_hi = sA_hi; a.sCm_hi = sC_hi;
+    return *this;
+  }
+  // two-level columns: n = (hi, lo) with lo < nlo; strides of hi for B and C
+  G &Nhi(int64_t nlo, int64_t sB_hi, int64_t sC_hi) {
+    a.Nlo = nlo; a.sBn_hi = sB_hi; a.sCn_hi = sC_hi;
+    return *this;
+  }
   G &tag(const char *t) {
     a.tag = t;
     return *this;
@@ -62,7 +72,13 @@ template <typename T> inline const T *off(const void *p, int64_t elems) {
 
 }  // namespace mlcc
 
+namespace mlcc {
+struct CcsdState;  // MLCCSD doubles: integral blocks, intermediates (ccsd.inl)
+}
+
 struct mlcc_problem {
+  ~mlcc_problem();
+  mlcc::CcsdState *cc = nullptr;
   mlcc_context *ctx = nullptr;
   mlcc::Exec *ex = nullptr;
   mlcc::Dims d;
@@ -116,10 +132,18 @@ struct mlcc_problem {
                                              bool add_fock);
   template <typename T> void compute_state_t(bool full_fock);
   template <typename T> void prepare_jacobian_t();
-  template <typename T> void transform_one_t(const double *c1, const double *c2, double *s1,
-                                             double *s2, double w_eff);
+  template <typename T> void transform_batch_t(int nb, const double *c, int64_t ld,
+                                               bool has_c2, double *sigma, double w_eff);
+  template <typename T> void ccsd_integrals_t();
   template <typename T> void ccsd_omega2_t();
   template <typename T> void ccsd_prepare_t();
-  template <typename T> void ccsd_sigma2_t(const double *c1, const double *c2, double *s2);
-  template <typename T> void ccsd_sigma1_doubles_t(const double *c2, double *s1);
+  // MLCCSD doubles of sigma for one vector; Gv[ai][bj] (row stride ldg) holds
+  // sum_K L~^K_ai dL~^K_bj and dLvo[K][ai] (row stride ldl) the derivative
+  // dL~_ai of that vector
+  template <typename T> void ccsd_sigma2_t(const double *c1, const double *c2, const double *Gv,
+                                           int64_t ldg, const void *dLvo, int64_t ldl,
+                                           double *s2);
+  template <typename T> void ccsd_terms_t(const void *const *blk, const void *tA, const void *uA,
+                                          const void *tB, const void *uB, bool incL, bool incB,
+                                          bool incQ, bool ladder, double *sym, double *R);
 };

@@ -64,7 +64,7 @@ EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "ml
            "mlcc_set_amplitudes", "mlcc_residual", "mlcc_ground_state",
            "mlcc_jacobian_transform", "mlcc_jacobian_transform_eff", "mlcc_davidson_solve",
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
-           "mlcc_request_footprint", "mlcc_gemm", "mlcc_debug_get", "mlcc_profile_enable",
+           "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_debug_get", "mlcc_profile_enable",
            "mlcc_profile_get"]
 
 _lib = None
@@ -101,6 +101,8 @@ def load(path: str = LIB_PATH):
         "mlcc_request_footprint": (u64, [P(ProblemDesc), i32, P(SolverOpts)]),
         "mlcc_gemm": (i32, [vp, i32, i64, i64, i64, i64, i64, dbl, vp, P(i64), vp, P(i64), dbl,
                             vp, P(i64)]),
+        "mlcc_gemm2": (i32, [vp, i32, i64, i64, i64, i64, i64, dbl, vp, P(i64), vp, P(i64), dbl,
+                             vp, P(i64), P(i64)]),
         "mlcc_debug_get": (i32, [vp, i32, vp]),
         "mlcc_profile_enable": (i32, [vp, i32]),
         "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
