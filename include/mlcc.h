@@ -86,7 +86,18 @@ typedef struct {
   int32_t precision;              /* MLCC_FP64 | MLCC_FP32 */
   const double *L;                /* [n_chol][n][n], symmetric in the last two */
   const double *eps;              /* [n] orbital energies in the order above */
+  uint32_t flags;                 /* MLCC_SYNTH_L, or 0 */
+  uint64_t seed;                  /* seed of MLCC_SYNTH_L */
 } mlcc_problem_desc;
+
+/* flags: L is not read; the library draws synthetic Cholesky vectors on the
+ * device from seed: L[J][p][q] = L[J][q][p] = sigma exp(-J/10) z, sigma =
+ * 0.5 / sqrt(n_occ n_vir), z standard normal from the Philox4x32-10
+ * counter-based generator (Salmon et al., SC'11) with key (seed lo, seed hi)
+ * and counter (p*n + q, J, 0, 0), Box-Muller on its first two words.  For
+ * benchmark and serving workloads too large to stage from the host; eps is
+ * still read. */
+#define MLCC_SYNTH_L 1u
 
 typedef struct {
   double tol;             /* ground state: ||Omega||_2; Davidson: residual norm */

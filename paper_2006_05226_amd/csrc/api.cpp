@@ -24,21 +24,29 @@ bool is_device_ptr(const void *p) {
   return at.type == hipMemoryTypeDevice;
 }
 
+void set_error(mlcc_context *ctx, const std::string &m) {
+  if (!ctx) {
+    g_create_error = m;
+    return;
+  }
+  std::lock_guard<std::mutex> lk(ctx->err_mu);
+  ctx->last_error = m;
+}
+
 template <typename F> mlcc_status guarded(mlcc_context *ctx, F &&f) {
   try {
     return f();
   } catch (const Error &e) {
-    if (ctx) ctx->last_error = e.msg;
-    else g_create_error = e.msg;
+    set_error(ctx, e.msg);
     return e.code;
   } catch (const std::bad_alloc &) {
-    if (ctx) ctx->last_error = "host allocation failed";
+    set_error(ctx, "host allocation failed");
     return MLCC_E_OOM;
   } catch (const std::exception &e) {
-    if (ctx) ctx->last_error = e.what();
+    set_error(ctx, e.what());
     return MLCC_E_DEVICE;
   } catch (...) {
-    if (ctx) ctx->last_error = "unknown error";
+    set_error(ctx, "unknown error");
     return MLCC_E_DEVICE;
   }
 }
@@ -80,7 +88,9 @@ struct Out {
 
 void check_desc(const mlcc_problem_desc *d) {
   MLCC_REQUIRE(d != nullptr, MLCC_E_ARG, "NULL problem descriptor");
-  MLCC_REQUIRE(d->L != nullptr && d->eps != nullptr, MLCC_E_ARG, "NULL L or eps");
+  MLCC_REQUIRE((d->L != nullptr || (d->flags & MLCC_SYNTH_L)) && d->eps != nullptr, MLCC_E_ARG,
+               "NULL L or eps");
+  MLCC_REQUIRE((d->flags & ~MLCC_SYNTH_L) == 0, MLCC_E_ARG, "unknown flags");
   MLCC_REQUIRE(d->n_occ >= 1 && d->n_vir >= 1 && d->n_chol >= 1, MLCC_E_ARG,
                "n_occ, n_vir and n_chol must be >= 1");
   MLCC_REQUIRE(d->model == MLCC_CCS || d->model == MLCC_MLCC2 || d->model == MLCC_MLCCSD,
@@ -126,9 +136,12 @@ mlcc_status mlcc_context_create(int device, void *hip_stream, uint64_t hbm_budge
       }
       c->own_stream = true;
     }
-    if (hipHostMalloc((void **)&c->pinned, 4096, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->ex.pinned, 512 * sizeof(double), hipHostMallocDefault) !=
+        hipSuccess) {
       (void)hipGetLastError();
-      c->pinned = new double[512];
+      if (c->own_stream) (void)hipStreamDestroy(c->ex.stream);
+      delete c;
+      throw Error{MLCC_E_DEVICE, "pinned host allocation failed"};
     }
     *out = c;
     return MLCC_OK;
@@ -142,7 +155,7 @@ mlcc_status mlcc_context_destroy(mlcc_context *ctx) {
   ctx->ex.work.release();
   ctx->ex.red.release();
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->ex.stream);
-  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->ex.pinned) (void)hipHostFree(ctx->ex.pinned);
   delete ctx;
   return MLCC_OK;
 }
@@ -153,23 +166,34 @@ const char *mlcc_last_error(mlcc_context *ctx) {
 
 uint64_t mlcc_context_bytes(mlcc_context *ctx) { return ctx ? ctx->al.used : 0; }
 
+}  // extern "C"
+
+namespace mlcc {
+mlcc_problem *problem_new(mlcc_context *ctx, Exec *ex, const mlcc_problem_desc *desc) {
+  check_desc(desc);
+  MLCC_HIP(hipSetDevice(ctx->device));
+  auto *P = new mlcc_problem();
+  P->ctx = ctx;
+  P->ex = ex;
+  try {
+    P->setup(*desc);
+  } catch (...) {
+    delete P;
+    throw;
+  }
+  return P;
+}
+void validate_desc(const mlcc_problem_desc *desc) { check_desc(desc); }
+}  // namespace mlcc
+
+extern "C" {
+
 mlcc_status mlcc_problem_create(mlcc_context *ctx, const mlcc_problem_desc *desc,
                                 mlcc_problem **prob) {
   if (!ctx) return MLCC_E_ARG;
   return guarded(ctx, [&]() -> mlcc_status {
     MLCC_REQUIRE(prob != nullptr, MLCC_E_ARG, "NULL output pointer");
-    check_desc(desc);
-    MLCC_HIP(hipSetDevice(ctx->device));
-    auto *P = new mlcc_problem();
-    P->ctx = ctx;
-    P->ex = &ctx->ex;
-    try {
-      P->setup(*desc);
-    } catch (...) {
-      delete P;
-      throw;
-    }
-    *prob = P;
+    *prob = problem_new(ctx, &ctx->ex, desc);
     return MLCC_OK;
   });
 }

@@ -10,6 +10,10 @@ namespace mlcc {
 
 mlcc_status ground_state(mlcc_problem &P, const mlcc_solver_opts &o, mlcc_info &info);
 
+// problem on a given execution lane (throws Error); descriptor validation
+mlcc_problem *problem_new(mlcc_context *ctx, Exec *ex, const mlcc_problem_desc *desc);
+void validate_desc(const mlcc_problem_desc *desc);
+
 // out[n][dim] = A in[n][dim]  (device pointers)
 typedef std::function<void(int n, const double *in, double *out)> TransformFn;
 // out = precond(w) r  (device pointers, one vector)

@@ -104,9 +104,7 @@ struct Exec {
   hipStream_t stream = nullptr;
   DBuf work;      // split-K partials
   DBuf red;       // reduction partials (dot products)
-  DBuf pinned_dummy;
-  double *host_red = nullptr;  // pinned host scalars
-  int n_host_red = 0;
+  double *pinned = nullptr;    // pinned host scalars (512 doubles) for results
   void *scratch(size_t bytes) {
     work.ensure(al, bytes);
     return work.p;
@@ -208,6 +206,8 @@ void permute4(Exec &ex, TD *dst, const TS *src, const int64_t n[4], const int64_
               double b);
 // out += R + R^T (M x M)
 void sym_accum(Exec &ex, int64_t M, const double *R, double *out);
+// synthetic Cholesky vectors on the device (see MLCC_SYNTH_L in mlcc.h)
+void synth_cholesky(Exec &ex, double *L, int64_t J, int64_t n, int O, int V, uint64_t seed);
 }  // namespace k
 
 }  // namespace mlcc

@@ -51,7 +51,7 @@ void Alloc::put(void *p, size_t bytes) {
 using namespace mlcc;
 
 double mlcc_problem::fetch(const double *dev) {
-  double *h = ctx->pinned;
+  double *h = ex->pinned;
   MLCC_HIP(hipMemcpyAsync(h, dev, sizeof(double), hipMemcpyDeviceToHost, ex->stream));
   MLCC_HIP(hipStreamSynchronize(ex->stream));
   return h[0];
@@ -66,7 +66,7 @@ void mlcc_problem::fetch_n(const double *dev, double *host, int n) {
 // setup: inputs, core Hamiltonian h = diag(eps) - G(D_HF), denominators
 // ---------------------------------------------------------------------------
 template <typename T>
-void mlcc_problem::setup_t(const double *Lsrc, bool dev) {
+void mlcc_problem::setup_t(const double *Lsrc, bool dev, const uint64_t *synth_seed) {
   Exec &x = *ex;
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O;
@@ -81,8 +81,11 @@ void mlcc_problem::setup_t(const double *Lsrc, bool dev) {
     L64.alloc(al, nL * sizeof(double));
     L64p = L64.as<double>();
   }
-  MLCC_HIP(hipMemcpyAsync(L64p, Lsrc, nL * sizeof(double),
-                          dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, x.stream));
+  if (synth_seed)
+    k::synth_cholesky(x, L64p, J, n, d.O, d.V, *synth_seed);
+  else
+    MLCC_HIP(hipMemcpyAsync(L64p, Lsrc, nL * sizeof(double),
+                            dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, x.stream));
   // h = diag(eps) - 2 sum_K L^K d^K + sum_{K,I} L^K_pI L^K_Iq   (FP64); the
   // diagonal is added by the caller
   h.alloc(al, n2 * sizeof(double));
@@ -161,9 +164,11 @@ void mlcc_problem::setup(const mlcc_problem_desc &desc) {
   k::nonfinite(x, d.n, eps.as<double>(), res.as<double>());
   MLCC_REQUIRE(fetch(res.as<double>()) == 0.0, MLCC_E_NUMERIC, "non-finite orbital energy");
 
-  const bool ldev = is_dev(desc.L);
-  if (prec == MLCC_FP64) setup_t<double>(desc.L, ldev);
-  else setup_t<float>(desc.L, ldev);
+  const bool synth = (desc.flags & MLCC_SYNTH_L) != 0;
+  const bool ldev = !synth && is_dev(desc.L);
+  const uint64_t *sp = synth ? &desc.seed : nullptr;
+  if (prec == MLCC_FP64) setup_t<double>(desc.L, ldev, sp);
+  else setup_t<float>(desc.L, ldev, sp);
   // h += diag(eps)  (the setup above accumulated -G into a zeroed h)
   hipLaunchKernelGGL(k_add_diag, dim3(64), dim3(256), 0, x.stream, (int64_t)d.n,
                      eps.as<double>(), h.as<double>());

@@ -13,7 +13,7 @@ struct mlcc_context {
   mlcc::Alloc al;
   mlcc::Exec ex;
   std::string last_error;
-  double *pinned = nullptr;  // host scalars for device->host results
+  std::mutex err_mu;
 };
 
 namespace mlcc {
@@ -125,7 +125,8 @@ struct mlcc_problem {
   void fetch_n(const double *dev, double *host, int n);
 
  private:
-  template <typename T> void setup_t(const double *Lhost_or_dev, bool dev);
+  template <typename T> void setup_t(const double *Lhost_or_dev, bool dev,
+                                     const uint64_t *synth_seed);
   template <typename T> void dress_t(bool full_fock);
   template <typename T> void doubles_mlcc2_t();
   template <typename T> void omega_singles_t(const void *Zb, const void *ub, double *om1,

@@ -1,17 +1,293 @@
-// Serving loop (continuous batching of excitation solves).
+// Serving loop: continuous batching of MLCC excitation solves of uneven size
+// on one GPU.
+//
+// * mlcc_submit (any host thread) validates the request, copies its inputs to
+//   host memory owned by the request and queues it with a ticket.
+// * max_slots execution lanes, each with its own HIP stream (default priority)
+//   and its own scratch, run admitted requests concurrently, so the kernels of
+//   requests of different sizes overlap on the device.  A lane takes the
+//   first queued request whose HBM footprint estimate fits in what the budget
+//   has left (FIFO with backfill); memory and the slot are returned when the
+//   request finishes and waiting requests are admitted at once.
+// * Each request runs its ground state, then the Davidson solve for its roots;
+//   the result and the submit / admit / done times go to the ticket table that
+//   mlcc_poll reads.  The kernels and reductions are deterministic, so a
+//   request gives the same result alone and in a mix.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <thread>
+#include <unordered_map>
+
 #include "drivers.h"
 
+namespace mlcc {
+namespace {
+
+struct Request {
+  uint64_t ticket = 0;
+  mlcc_problem_desc desc{};
+  std::vector<double> L, eps;  // owned copies (L empty for synthetic inputs)
+  int32_t n_roots = 0;
+  mlcc_solver_opts gs{}, es{};
+  uint64_t footprint = 0;
+  bool done = false;
+  mlcc_result res{};
+};
+
+struct Lane {
+  Exec ex;
+};
+
+double now_s(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+}  // namespace mlcc
+
+using namespace mlcc;
+
+struct mlcc_server {
+  mlcc_context *ctx = nullptr;
+  int max_slots = 8;
+  size_t max_queue = 1024;
+  uint64_t budget = 0;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<Request *> queue;
+  std::unordered_map<uint64_t, Request *> table;
+  uint64_t next_ticket = 1;
+  uint64_t in_use = 0;
+  bool stop = false;
+  std::vector<std::unique_ptr<Lane>> lanes;
+  std::vector<std::thread> workers;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+  void work(Lane *lane);
+};
+
+// Device bytes one request needs at its peak (inputs, X1-transformed vectors,
+// doubles arrays, Davidson subspace, batch scratch), with a 15% margin.
+extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n_roots,
+                                           const mlcc_solver_opts *es) {
+  if (!d || n_roots < 1) return 0;
+  const double O = d->n_occ, V = d->n_vir, J = d->n_chol, n = O + V;
+  const bool dbl = d->model != MLCC_CCS;
+  const double M = dbl ? (double)d->n_occ_act * d->n_vir_act : 0.0;
+  const double ts = d->precision == MLCC_FP64 ? 8.0 : 4.0;
+  const double nL = J * n * n, n1 = O * V, MM = M * M;
+  const bool eff = es && es->effective && d->model == MLCC_MLCC2;
+  const double dim = n1 + ((dbl && !eff) ? MM : 0.0);
+  const double b = std::min(n_roots + 2, 8);
+  double bytes = 0.0;
+  bytes += nL * ts + nL * ts;                  // L and L~
+  if (ts == 4.0) bytes += nL * 8.0;            // FP64 staging of L at setup
+  bytes += 6.0 * n * n * 8.0;                  // h, h~, F~ and scratch
+  bytes += MM * (8.0 * 4 + ts * 2);            // amplitudes, residual, g~, G, u
+  bytes += MM * b * (ts + 8.0);                // batched u(c2), G
+  if (eff) bytes += MM * b * 8.0;              // eliminated doubles
+  bytes += J * M * ts * (3.0 + 2.0 * b);       // packed L_ai, Z, Zc, dL_ai
+  bytes += J * V * O * b * ts;                 // CCS intermediate
+  const double space = es && es->max_subspace > 0 ? es->max_subspace : 20.0 * n_roots;
+  bytes += dim * 8.0 * (2.0 * space + 3.0 * (n_roots + 2));  // Davidson
+  bytes += 2.0 * 8.0 * (n1 + (d->model == MLCC_MLCCSD ? MM : 0.0)) * 8;  // DIIS
+  if (d->model == MLCC_MLCCSD) {
+    const double v = d->n_vir_act, o = d->n_occ_act;
+    bytes += (v * v * v * v + O * v * v * v + O * o * M) * ts + 16.0 * MM * ts;
+  }
+  return (uint64_t)(bytes * 1.15) + (64ull << 20);
+}
+
+void mlcc_server::work(Lane *lane) {
+  (void)hipSetDevice(ctx->device);
+  for (;;) {
+    Request *r = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      for (;;) {
+        if (stop) return;
+        for (auto it = queue.begin(); it != queue.end(); ++it) {
+          if ((*it)->footprint <= budget - in_use) {
+            r = *it;
+            queue.erase(it);
+            break;
+          }
+        }
+        if (r) break;
+        cv.wait(lk);
+      }
+      in_use += r->footprint;
+      r->res.t_admit = now_s(t0);
+    }
+    mlcc_status st = MLCC_OK;
+    mlcc_result &out = r->res;
+    out.n_roots = r->n_roots;
+    try {
+      mlcc_problem_desc d = r->desc;
+      if (!(d.flags & MLCC_SYNTH_L)) d.L = r->L.data();
+      d.eps = r->eps.data();
+      std::unique_ptr<mlcc_problem> P(problem_new(ctx, &lane->ex, &d));
+      mlcc_info gi{};
+      mlcc_status gs = ground_state(*P, r->gs, gi);
+      out.e_corr = gi.energy;
+      out.gs_iterations = gi.iterations;
+      std::vector<double> w(r->n_roots, 0.0);
+      mlcc_info ei{};
+      mlcc_status es = mlcc_davidson_solve(P.get(), r->n_roots, &r->es, w.data(), nullptr, &ei);
+      out.es_iterations = ei.iterations;
+      for (int i = 0; i < r->n_roots && i < 16; ++i) out.omega[i] = w[i];
+      st = gs != MLCC_OK ? gs : es;
+      P.reset();
+      MLCC_HIP(hipStreamSynchronize(lane->ex.stream));
+    } catch (const Error &e) {
+      st = e.code;
+    } catch (...) {
+      st = MLCC_E_DEVICE;
+    }
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      in_use -= r->footprint;
+      out.status = st;
+      out.t_done = now_s(t0);
+      r->done = true;
+      r->L.clear();
+      r->L.shrink_to_fit();
+    }
+    cv.notify_all();
+  }
+}
+
 extern "C" {
-mlcc_status mlcc_server_create(mlcc_context *, const mlcc_server_opts *, mlcc_server **) {
-  return MLCC_E_ARG;
+
+mlcc_status mlcc_server_create(mlcc_context *ctx, const mlcc_server_opts *opts,
+                               mlcc_server **out) {
+  if (!ctx || !out) return MLCC_E_ARG;
+  auto *s = new mlcc_server();
+  s->ctx = ctx;
+  if (opts) {
+    if (opts->max_slots > 0) s->max_slots = opts->max_slots;
+    if (opts->max_queue > 0) s->max_queue = (size_t)opts->max_queue;
+    s->budget = opts->hbm_budget;
+  }
+  if (s->budget == 0) s->budget = ctx->al.budget;
+  if (s->budget == 0) {
+    size_t fr = 0, tot = 0;
+    if (hipSetDevice(ctx->device) != hipSuccess || hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      (void)hipGetLastError();
+      delete s;
+      return MLCC_E_DEVICE;
+    }
+    s->budget = (uint64_t)(fr * 0.9);
+  }
+  for (int i = 0; i < s->max_slots; ++i) {
+    auto lane = std::make_unique<Lane>();
+    lane->ex.al = &ctx->al;
+    if (hipStreamCreateWithFlags(&lane->ex.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipHostMalloc((void **)&lane->ex.pinned, 512 * sizeof(double), hipHostMallocDefault) !=
+            hipSuccess) {
+      (void)hipGetLastError();
+      delete s;
+      return MLCC_E_DEVICE;
+    }
+    s->lanes.push_back(std::move(lane));
+  }
+  for (auto &l : s->lanes) s->workers.emplace_back(&mlcc_server::work, s, l.get());
+  *out = s;
+  return MLCC_OK;
 }
-mlcc_status mlcc_server_destroy(mlcc_server *) { return MLCC_E_ARG; }
-mlcc_status mlcc_submit(mlcc_server *, const mlcc_problem_desc *, int32_t,
-                        const mlcc_solver_opts *, const mlcc_solver_opts *, uint64_t *) {
-  return MLCC_E_ARG;
+
+mlcc_status mlcc_server_destroy(mlcc_server *s) {
+  if (!s) return MLCC_E_ARG;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+    for (Request *r : s->queue) {
+      s->table.erase(r->ticket);
+      delete r;
+    }
+    s->queue.clear();
+  }
+  s->cv.notify_all();
+  for (auto &t : s->workers) t.join();
+  for (auto &kv : s->table) delete kv.second;
+  for (auto &l : s->lanes) {
+    l->ex.work.release();
+    l->ex.red.release();
+    if (l->ex.stream) (void)hipStreamDestroy(l->ex.stream);
+    if (l->ex.pinned) (void)hipHostFree(l->ex.pinned);
+  }
+  delete s;
+  return MLCC_OK;
 }
-mlcc_status mlcc_poll(mlcc_server *, uint64_t, mlcc_result *) { return MLCC_E_ARG; }
-uint64_t mlcc_request_footprint(const mlcc_problem_desc *, int32_t, const mlcc_solver_opts *) {
-  return 0;
+
+mlcc_status mlcc_submit(mlcc_server *s, const mlcc_problem_desc *desc, int32_t n_roots,
+                        const mlcc_solver_opts *gs, const mlcc_solver_opts *es, uint64_t *ticket) {
+  if (!s || !desc || !gs || !es || !ticket) return MLCC_E_ARG;
+  if (n_roots < 1 || gs->tol <= 0 || es->tol <= 0) return MLCC_E_ARG;
+  try {
+    validate_desc(desc);
+  } catch (const Error &e) {
+    return e.code;
+  }
+  if (n_roots > (int64_t)desc->n_occ * desc->n_vir) return MLCC_E_ARG;
+  auto r = std::make_unique<Request>();
+  r->desc = *desc;
+  r->n_roots = n_roots;
+  r->gs = *gs;
+  r->es = *es;
+  r->footprint = mlcc_request_footprint(desc, n_roots, es);
+  if (r->footprint > s->budget) return MLCC_E_OOM;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->queue.size() >= s->max_queue) return MLCC_E_BUSY;
+  }
+  // copy the inputs (host or device memory) before returning
+  const int64_t n = (int64_t)desc->n_occ + desc->n_vir;
+  auto copy_in = [&](std::vector<double> &dst, const double *src, int64_t cnt) -> bool {
+    dst.resize(cnt);
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, src) == hipSuccess && at.type == hipMemoryTypeDevice)
+      return hipMemcpy(dst.data(), src, cnt * sizeof(double), hipMemcpyDeviceToHost) ==
+             hipSuccess;
+    (void)hipGetLastError();
+    std::memcpy(dst.data(), src, cnt * sizeof(double));
+    return true;
+  };
+  try {
+    if (!copy_in(r->eps, desc->eps, n)) return MLCC_E_DEVICE;
+    if (!(desc->flags & MLCC_SYNTH_L) && !copy_in(r->L, desc->L, (int64_t)desc->n_chol * n * n))
+      return MLCC_E_DEVICE;
+  } catch (const std::bad_alloc &) {
+    return MLCC_E_OOM;
+  }
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return MLCC_E_STATE;
+    if (s->queue.size() >= s->max_queue) return MLCC_E_BUSY;
+    r->ticket = s->next_ticket++;
+    r->res.t_submit = now_s(s->t0);
+    *ticket = r->ticket;
+    s->table[r->ticket] = r.get();
+    s->queue.push_back(r.release());
+  }
+  s->cv.notify_all();
+  return MLCC_OK;
 }
+
+mlcc_status mlcc_poll(mlcc_server *s, uint64_t ticket, mlcc_result *out) {
+  if (!s || !out) return MLCC_E_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->table.find(ticket);
+  if (it == s->table.end()) return MLCC_E_ARG;
+  Request *r = it->second;
+  if (!r->done) return MLCC_PENDING;
+  *out = r->res;
+  s->table.erase(it);
+  delete r;
+  return MLCC_OK;
 }
+
+}  // extern "C"

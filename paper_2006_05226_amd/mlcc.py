@@ -30,7 +30,11 @@ _STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_ARG", -2: "E_OOM", -3: "E_NOCONV"
 class ProblemDesc(C.Structure):
     _fields_ = [("n_occ", C.c_int32), ("n_vir", C.c_int32), ("n_chol", C.c_int32),
                 ("n_occ_act", C.c_int32), ("n_vir_act", C.c_int32), ("model", C.c_int32),
-                ("precision", C.c_int32), ("L", C.c_void_p), ("eps", C.c_void_p)]
+                ("precision", C.c_int32), ("L", C.c_void_p), ("eps", C.c_void_p),
+                ("flags", C.c_uint32), ("seed", C.c_uint64)]
+
+
+SYNTH_L = 1
 
 
 class SolverOpts(C.Structure):
@@ -200,16 +204,20 @@ class Problem:
     """One MLCC problem on a context (see mlcc_problem_create)."""
 
     def __init__(self, ctx: Context, L, eps, n_occ, n_vir, n_occ_act=None, n_vir_act=None,
-                 model="mlcc2", precision="fp64"):
+                 model="mlcc2", precision="fp64", n_chol=None, seed=None):
+        """L=None with n_chol and seed: Cholesky vectors drawn on the device
+        (MLCC_SYNTH_L)."""
         self.ctx = ctx
         L = _f64(L)
         eps = _f64(eps)
-        n_chol = L.shape[0]
+        synth = L is None
+        n_chol = n_chol if synth else L.shape[0]
         self._keep = (L, eps)
         d = ProblemDesc(n_occ, n_vir, n_chol,
                         n_occ if n_occ_act is None else n_occ_act,
                         n_vir if n_vir_act is None else n_vir_act,
-                        MODEL[model], PREC[precision], _ptr(L), _ptr(eps))
+                        MODEL[model], PREC[precision], _ptr(L), _ptr(eps),
+                        SYNTH_L if synth else 0, int(seed or 0))
         h = C.c_void_p()
         ctx.check(ctx.lib.mlcc_problem_create(ctx.h, C.byref(d), C.byref(h)))
         self._keep = None  # the library copied the inputs
@@ -299,3 +307,92 @@ class Problem:
         out = np.empty(sizes[which])
         self.ctx.check(self.ctx.lib.mlcc_debug_get(self.h, which, _ptr(out)))
         return out
+
+
+class Server:
+    """Continuous-batching server on a context (mlcc_server_create)."""
+
+    def __init__(self, ctx: Context, max_slots=0, max_queue=0, hbm_budget=0):
+        self.ctx = ctx
+        h = C.c_void_p()
+        o = ServerOpts(max_slots, max_queue, hbm_budget)
+        ctx.check(ctx.lib.mlcc_server_create(ctx.h, C.byref(o), C.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    @staticmethod
+    def desc(L, eps, n_occ, n_vir, n_occ_act, n_vir_act, model="mlcc2", precision="fp64",
+             n_chol=None, seed=None):
+        """Problem descriptor; L=None with seed set draws L on the device."""
+        eps = _f64(eps)
+        if L is None:
+            d = ProblemDesc(n_occ, n_vir, n_chol, n_occ_act, n_vir_act, MODEL[model],
+                            PREC[precision], None, _ptr(eps), SYNTH_L, seed)
+            return d, (eps,)
+        L = _f64(L)
+        d = ProblemDesc(n_occ, n_vir, L.shape[0], n_occ_act, n_vir_act, MODEL[model],
+                        PREC[precision], _ptr(L), _ptr(eps), 0, 0)
+        return d, (L, eps)
+
+    def submit(self, desc, n_roots, gs_tol=1e-8, es_tol=1e-6, effective=True, max_iter=100):
+        gs = opts(tol=gs_tol, max_iter=max_iter)
+        es = opts(tol=es_tol, max_iter=max_iter, effective=effective)
+        t = C.c_uint64()
+        st = self.ctx.lib.mlcc_submit(self.h, C.byref(desc), n_roots, C.byref(gs), C.byref(es),
+                                      C.byref(t))
+        if st != OK:
+            raise MlccError(st, "submit rejected")
+        return t.value
+
+    def poll(self, ticket):
+        r = Result()
+        st = self.ctx.lib.mlcc_poll(self.h, ticket, C.byref(r))
+        if st == PENDING:
+            return None
+        if st != OK:
+            raise MlccError(st, "poll failed")
+        return dict(status=r.status, omega=list(r.omega[: min(r.n_roots, 16)]), e_corr=r.e_corr,
+                    t_submit=r.t_submit, t_admit=r.t_admit, t_done=r.t_done,
+                    gs_iterations=r.gs_iterations, es_iterations=r.es_iterations)
+
+    def wait(self, ticket, poll_s=0.001, timeout_s=600.0):
+        import time
+        t0 = time.time()
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.time() - t0 > timeout_s:
+                raise TimeoutError(ticket)
+            time.sleep(poll_s)
+
+    def close(self):
+        if self.h:
+            self.ctx.lib.mlcc_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def footprint(desc, n_roots, effective=True):
+    lib = load()
+    es = opts(effective=effective)
+    return lib.mlcc_request_footprint(C.byref(desc), n_roots, C.byref(es))
+
+
+def philox4x32_10(ctr, key):
+    """Reference Philox4x32-10 (Salmon et al., SC'11) on Python ints, used by
+    the tests to pin the device generator of MLCC_SYNTH_L."""
+    M0, M1, W0, W1 = 0xD2511F53, 0xCD9E8D57, 0x9E3779B9, 0xBB67AE85
+    x0, x1, x2, x3 = ctr
+    k0, k1 = key
+    for _ in range(10):
+        p0, p1 = M0 * x0, M1 * x2
+        x0, x1, x2, x3 = ((p1 >> 32) ^ x1 ^ k0) & 0xFFFFFFFF, p1 & 0xFFFFFFFF, \
+            ((p0 >> 32) ^ x3 ^ k1) & 0xFFFFFFFF, p0 & 0xFFFFFFFF
+        k0, k1 = (k0 + W0) & 0xFFFFFFFF, (k1 + W1) & 0xFFFFFFFF
+    return x0, x1, x2, x3
