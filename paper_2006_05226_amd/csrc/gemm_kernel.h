@@ -1,0 +1,547 @@
+// Batched, batch-reduced, strided GEMM on CDNA4 matrix cores (MFMA): the
+// kernel template, included by one translation unit per operand type.
+//
+//   C_z[m][n] = alpha * sum_{r<R} sum_{k<K} A_zr[m][k] * B_zr[k][n] + beta * Cin_z[m][n]
+//
+// Design
+// * 256 threads = 4 waves in a 2x2 grid; a block owns a BM x BN tile of C,
+//   each wave a (BM/2) x (BN/2) sub-tile of 16 x 16 fragments.
+// * FP32: v_mfma_f32_16x16x4f32, one instruction per 16x16x4 fragment product.
+//   Lane l holds A[i = l%16][k], B[k][j = l%16] with k-group l/16; output
+//   element e of lane l is D[4*(l/16) + e][l%16].
+// * FP64: v_mfma_f64_4x4x4f64 (four independent 4x4x4 blocks per wave, twice
+//   the FP64 rate of the 16x16x4 form on gfx950).  Lane 16*k + 4*b + i holds
+//   A_b[i][k] and B_b[k][i]; lane 16*i + 4*b + j receives D_b[i][j] (measured
+//   with a one-wave probe).  A 16x16x4 fragment product is four instructions:
+//   in instruction r the B fragment is read with its 16 columns rotated by 4r,
+//   so block b multiplies rows 4b..4b+3 with columns 4((b+r)%4)..+3.
+// * Within one k-step of BK, k-group g of a fragment covers k = g*S .. g*S+S-1
+//   (S = BK/4), the same assignment for A and B, so a lane's k-values are
+//   contiguous.
+// * Each operand is staged through double-buffered LDS in the layout of its
+//   contiguous global dimension: [m][k] rows when k is contiguous (fragment
+//   reads are 16-byte vectors along k), [k][m] rows when m is contiguous.
+//   Global loads move 16 bytes per thread along the contiguous dimension when
+//   stride, alignment and bounds allow it, element by element otherwise.
+//   Row padding keeps fragment reads free of bank conflicts.
+// * The next k-step's global loads are issued before the MFMAs of the current
+//   one; one barrier per k-step.
+// * The reduction range (R x ceil(K/BK) k-steps) can be split over blocks;
+//   split partials go to a workspace and are summed in a fixed order, so the
+//   result is deterministic.
+// * One-dimensional grid, remapped so that each XCD (consecutive workgroup
+//   ids go round-robin over the 8 XCDs) receives a contiguous range of output
+//   tiles, which share operand rows in that XCD's L2.
+#pragma once
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <type_traits>
+
+#include "mlcc_internal.h"
+
+namespace mlcc {
+namespace gk {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kThreads = 256;
+constexpr int kXcd = 8;
+
+struct KParams {
+  GemmArgs a;
+  int splits;
+  int tiles_m, tiles_n;
+  int64_t ktiles, steps_per_split, nwork, per_xcd;
+  void *work;  // [splits][Z][M][N] accumulators when splits > 1
+  int vec_a, vec_b;  // 16-byte global loads allowed (stride and base alignment)
+};
+
+__device__ __forceinline__ int64_t two_level(int64_t i, int64_t lo_n, int64_t s_lo, int64_t s_hi) {
+  if (lo_n <= 0) return i * s_lo;
+  const int64_t hi = i / lo_n;
+  return hi * s_hi + (i - hi * lo_n) * s_lo;
+}
+
+template <typename T> struct Tr;
+#ifndef MLCC_F64_BK
+#define MLCC_F64_BK 16
+#endif
+template <> struct Tr<double> {
+  static constexpr int BK = MLCC_F64_BK, VEC = 2, S = BK / 4;
+  typedef d2 v16;
+};
+template <> struct Tr<float> {
+  static constexpr int BK = 32, VEC = 4, S = 8;
+  typedef f4 v16;
+};
+
+// Operand tile of a block: ROWS x COLS in LDS (COLS contiguous), loaded from
+// global memory as units of VEC contiguous elements.  KMAJ: the operand's
+// contiguous global dimension is its output dimension (m or n), so LDS holds
+// [k][m]; otherwise LDS holds [m][k].
+template <typename T, int BMN, bool KMAJ> struct Stage {
+  static constexpr int BK = Tr<T>::BK, VEC = Tr<T>::VEC;
+  static constexpr int PK = 16 / (int)sizeof(T);      // [m][k] rows: +16 bytes
+  static constexpr int PM = sizeof(T) == 8 ? 4 : 2;   // [k][m] rows: see the bank note
+  static constexpr int ROWS = KMAJ ? BK : BMN;
+  static constexpr int LEN = KMAJ ? BMN + PM : BK + PK;
+  static constexpr int U = BMN * BK / VEC / kThreads;  // units per thread
+  static_assert(U * VEC * kThreads == BMN * BK, "tile");
+  // Bank note: with k = g*S + s, the four k-groups of a [k][m] fragment read
+  // sit S rows apart; S * LEN * sizeof(T) is 64 mod 256 (FP32) or 128 mod 256
+  // (FP64), so one pass of a ds_read touches disjoint banks.
+
+  int64_t off[U];   // element offset of the unit's first element (valid rows)
+  int row[U], col[U];
+  bool ok[U];       // output index of the unit's first element in range
+  bool vec[U];      // the unit may use one 16-byte load
+  bool contig[U];   // KMAJ: the unit's VEC output indices are consecutive in memory
+  bool fast;        // every unit of every thread of the block may use 16-byte loads
+
+  // mn0: first output index of the tile; n_mn, lo, s_lo, s_hi: extent and
+  // two-level strides of the output dimension.  Units wholly outside the
+  // operand read the tile's first row instead: those values reach only
+  // outputs that are never written.
+  __device__ __forceinline__ void init(int tid, int64_t mn0, int64_t n_mn, int64_t lo, int64_t s_mn,
+                                       int64_t s_hi, bool vec_ok) {
+    const int64_t off0 = two_level(mn0, lo, s_mn, s_hi);
+    bool base_ok = off0 % VEC == 0;
+    if (KMAJ) base_ok = base_ok && mn0 + VEC <= n_mn && (lo <= 0 || (mn0 % lo) + VEC <= lo);
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      const int u = tid + e * kThreads;
+      int mn;
+      if (KMAJ) {
+        row[e] = u / (BMN / VEC);
+        mn = (u % (BMN / VEC)) * VEC;
+        col[e] = mn;
+      } else {
+        mn = u / (BK / VEC);
+        row[e] = mn;
+        col[e] = (u % (BK / VEC)) * VEC;
+      }
+      const int64_t i = mn0 + mn;
+      ok[e] = i < n_mn;
+      off[e] = ok[e] ? two_level(i, lo, s_mn, s_hi) : off0;
+      if (KMAJ) {
+        bool c = i + VEC <= n_mn;
+        if (c && lo > 0) c = (i % lo) + VEC <= lo;
+        contig[e] = c;
+        if (c) vec[e] = vec_ok && off[e] % VEC == 0;
+        else vec[e] = vec_ok && !ok[e] && base_ok;  // straddling units are never vectorised
+      } else {
+        contig[e] = true;
+        vec[e] = vec_ok && off[e] % VEC == 0;
+      }
+    }
+    bool all = true;
+#pragma unroll
+    for (int e = 0; e < U; ++e) all = all && vec[e];
+    fast = __syncthreads_and(all) != 0;
+  }
+
+  // a k-step of the block's interior: every unit in range and aligned, so
+  // the loads are unconditional and issue back to back
+  __device__ __forceinline__ void load_fast(T (&rg)[U][VEC], const T *X, int64_t k0,
+                                            int64_t s_k) const {
+    typedef typename Tr<T>::v16 v16;
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      const T *src = KMAJ ? X + off[e] + (k0 + row[e]) * s_k : X + off[e] + k0 + col[e];
+      const v16 v = *reinterpret_cast<const v16 *>(src);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) rg[e][q] = v[q];
+    }
+  }
+
+  // general k-step (tile edges, a partial last k-step, unaligned operands):
+  // element by element, every load unconditional from a valid address (the
+  // slice's first element when out of range) and its value selected after,
+  // so no branch splits the loads of a step.
+  __device__ __forceinline__ void load(T (&rg)[U][VEC], const T *X, int64_t k0, int64_t K,
+                                       int64_t s_k, int64_t mn0, int64_t n_mn, int64_t lo,
+                                       int64_t s_mn, int64_t s_hi) const {
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        int64_t o;
+        bool valid;
+        if (KMAJ) {
+          const int64_t k = k0 + row[e];
+          const int64_t i = mn0 + col[e] + q;
+          valid = k < K && i < n_mn;
+          const int64_t oi = contig[e] ? off[e] + q * s_mn : two_level(i, lo, s_mn, s_hi);
+          o = valid ? oi + k * s_k : 0;
+        } else {
+          const int64_t k = k0 + col[e] + q;
+          valid = ok[e] && k < K;
+          o = valid ? off[e] + k * s_k : 0;
+        }
+        const T x = X[o];
+        rg[e][q] = valid ? x : T(0);
+      }
+    }
+  }
+
+  __device__ __forceinline__ void store(T (*L)[LEN], const T (&rg)[U][VEC]) const {
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      T *dst = &L[row[e]][col[e]];
+      if (sizeof(T) == 4 && KMAJ) {
+        // [k][m] FP32 rows are 8-byte aligned only
+        *reinterpret_cast<f2 *>(dst) = f2{(float)rg[e][0], (float)rg[e][1]};
+        *reinterpret_cast<f2 *>(dst + 2) = f2{(float)rg[e][2], (float)rg[e][3]};
+      } else {
+        typename Tr<T>::v16 v;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) v[q] = rg[e][q];
+        *reinterpret_cast<typename Tr<T>::v16 *>(dst) = v;
+      }
+    }
+  }
+};
+
+// fragment (16 rows, S k-values of group g) of an operand tile in LDS
+template <typename T, int LEN, bool KMAJ>
+__device__ __forceinline__ void frag(T (&f)[Tr<T>::S], const T (*L)[LEN], int mn, int g) {
+  constexpr int S = Tr<T>::S;
+  if (KMAJ) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) f[s] = L[g * S + s][mn];
+  } else {
+    typedef typename Tr<T>::v16 v16;
+    constexpr int VEC = Tr<T>::VEC;
+#pragma unroll
+    for (int h = 0; h < S / VEC; ++h) {
+      const v16 v = *reinterpret_cast<const v16 *>(&L[mn][g * S + h * VEC]);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) f[h * VEC + q] = v[q];
+    }
+  }
+}
+
+// output position of accumulator element e of lane l within a 16x16 fragment
+template <typename T> struct OutMap;
+template <> struct OutMap<float> {
+  static __device__ __forceinline__ int row(int l, int e) { return 4 * (l >> 4) + e; }
+  static __device__ __forceinline__ int col(int l, int) { return l & 15; }
+};
+template <> struct OutMap<double> {
+  static __device__ __forceinline__ int row(int l, int) { return 4 * ((l & 15) >> 2) + (l >> 4); }
+  static __device__ __forceinline__ int col(int l, int r) {
+    return 4 * ((((l & 15) >> 2) + r) & 3) + (l & 3);
+  }
+};
+
+template <typename T, typename TC, int BM, int BN, bool AKM, bool BKN>
+__global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
+  constexpr int S = Tr<T>::S, VEC = Tr<T>::VEC;
+  constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
+  static_assert(FM * 32 == BM && FN * 32 == BN, "tile");
+  typedef Stage<T, BM, AKM> SA;
+  typedef Stage<T, BN, BKN> SB;
+  __shared__ __attribute__((aligned(16))) T As[2][SA::ROWS][SA::LEN];
+  __shared__ __attribute__((aligned(16))) T Bs[2][SB::ROWS][SB::LEN];
+
+  const GemmArgs &p = kp.a;
+  // XCD-aware work index
+  const int64_t L = blockIdx.x;
+  const int64_t w = (L % kXcd) * kp.per_xcd + L / kXcd;
+  if (w >= kp.nwork) return;
+  const int64_t tn = w % kp.tiles_n;
+  const int64_t t2 = w / kp.tiles_n;
+  const int64_t tm = t2 % kp.tiles_m;
+  const int64_t zs = t2 / kp.tiles_m;
+  const int64_t z = zs / kp.splits;
+  const int split = (int)(zs % kp.splits);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, g = lane >> 4, l16 = lane & 15;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t total = p.R * kp.ktiles;
+  const int64_t s_begin = split * kp.steps_per_split;
+  const int64_t s_end = min(total, s_begin + kp.steps_per_split);
+
+  const T *Az = static_cast<const T *>(p.A) + z * p.sAz;
+  const T *Bz = static_cast<const T *>(p.B) + z * p.sBz;
+
+  SA sa;
+  SB sb;
+  sa.init(tid, m0, p.M, p.Mlo, p.sAm, p.sAm_hi, kp.vec_a);
+  sb.init(tid, n0, p.N, p.Nlo, p.sBn, p.sBn_hi, kp.vec_b);
+
+  // FP32: acc[i][j][e] = element e of the 16x16x4 fragment accumulator;
+  // FP64: acc[i][j][r] = the 4x4x4 accumulator of rotation r
+  typedef typename std::conditional<sizeof(T) == 8, double, float>::type acc_t;
+  typedef acc_t acc4 __attribute__((ext_vector_type(4)));
+  acc4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = acc4{0, 0, 0, 0};
+
+  T ra[SA::U][VEC], rb[SB::U][VEC];
+  // position (slice r, k0) of the next k-step to load, advanced step by step
+  constexpr int BK = Tr<T>::BK;
+  int64_t lr = s_begin / kp.ktiles;
+  int64_t lk0 = (s_begin - lr * kp.ktiles) * BK;
+  auto load_next = [&]() {
+    const T *Ar = Az + lr * p.sAr;
+    const T *Br = Bz + lr * p.sBr;
+    const bool kfull = lk0 + BK <= p.K;
+    if (sa.fast && kfull) sa.load_fast(ra, Ar, lk0, p.sAk);
+    else sa.load(ra, Ar, lk0, p.K, p.sAk, m0, p.M, p.Mlo, p.sAm, p.sAm_hi);
+    if (sb.fast && kfull) sb.load_fast(rb, Br, lk0, p.sBk);
+    else sb.load(rb, Br, lk0, p.K, p.sBk, n0, p.N, p.Nlo, p.sBn, p.sBn_hi);
+    lk0 += BK;
+    if (lk0 >= kp.ktiles * BK) {
+      lk0 = 0;
+      ++lr;
+    }
+  };
+
+  int cur = 0;
+  if (s_begin < s_end) {
+    load_next();
+    sa.store(As[0], ra);
+    sb.store(Bs[0], rb);
+  }
+  __syncthreads();
+  for (int64_t step = s_begin; step < s_end; ++step) {
+    const bool more = step + 1 < s_end;
+    if (more) load_next();
+    T af[FM][S];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+      frag<T, SA::LEN, AKM>(af[i], As[cur], wm * WTM + i * 16 + l16, g);
+    if constexpr (sizeof(T) == 4) {
+      T bf[FN][S];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        frag<T, SB::LEN, BKN>(bf[j], Bs[cur], wn * WTN + j * 16 + l16, g);
+#pragma unroll
+      for (int s = 0; s < S; ++s)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          T bf[S];
+          frag<T, SB::LEN, BKN>(bf, Bs[cur], wn * WTN + j * 16 + ((l16 + 4 * r) & 15), g);
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+              acc[i][j][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i][s], bf[s], acc[i][j][r], 0, 0, 0);
+        }
+    }
+    if (more) {
+      sa.store(As[cur ^ 1], ra);
+      sb.store(Bs[cur ^ 1], rb);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+
+  // epilogue
+  int64_t coff[FN][4];
+  bool cok[FN][4];
+#pragma unroll
+  for (int j = 0; j < FN; ++j)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T>::col(lane, e);
+      cok[j][e] = col < p.N;
+      coff[j][e] = cok[j][e] ? two_level(col, p.Nlo, p.sCn, p.sCn_hi) : 0;
+    }
+  if (kp.splits == 1) {
+    TC *C = static_cast<TC *>(p.C) + z * p.sCz;
+    const TC *Cin = static_cast<const TC *>(p.Cin) + z * p.sCz;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T>::row(lane, e);
+        if (row >= p.M) continue;
+        const int64_t roff = two_level(row, p.Mlo, p.sCm, p.sCm_hi);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          if (!cok[j][e]) continue;
+          const int64_t o = roff + coff[j][e];
+          double out = p.alpha * (double)acc[i][j][e];
+          if (p.beta != 0.0) out += p.beta * (double)Cin[o];
+          C[o] = (TC)out;
+        }
+      }
+  } else {
+    acc_t *wk = static_cast<acc_t *>(kp.work) + (((int64_t)split * p.Z + z) * p.M) * p.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T>::row(lane, e);
+        if (row >= p.M) continue;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T>::col(lane, e);
+          if (col < p.N) wk[row * p.N + col] = acc[i][j][e];
+        }
+      }
+  }
+}
+
+template <typename TA, typename TC>
+__global__ void k_split_reduce(KParams kp) {
+  const GemmArgs &p = kp.a;
+  const int64_t MN = p.M * p.N;
+  const int64_t total = p.Z * MN;
+  const TA *w = static_cast<const TA *>(kp.work);
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = t / MN;
+    const int64_t rem = t - z * MN;
+    const int64_t row = rem / p.N, col = rem - row * p.N;
+    double s = 0.0;
+    for (int sp = 0; sp < kp.splits; ++sp) s += (double)w[(int64_t)sp * total + t];
+    const int64_t off = z * p.sCz + two_level(row, p.Mlo, p.sCm, p.sCm_hi) +
+                        two_level(col, p.Nlo, p.sCn, p.sCn_hi);
+    double out = p.alpha * s;
+    if (p.beta != 0.0) out += p.beta * (double)static_cast<const TC *>(p.Cin)[off];
+    static_cast<TC *>(p.C)[off] = (TC)out;
+  }
+}
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// 16-byte loads need a unit-stride contiguous dimension, the other strides
+// that move between k-steps, slices and batches in multiples of VEC, and an
+// aligned base; row alignment is checked per unit in the kernel.
+inline bool vec_ok(const void *base, int64_t s_fast, int64_t s_k_other, int64_t s_r, int64_t s_z,
+                   int vec, bool kmaj) {
+  if (s_fast != 1) return false;
+  if (reinterpret_cast<uintptr_t>(base) % 16 != 0) return false;
+  if (s_r % vec != 0 || s_z % vec != 0) return false;
+  if (kmaj && s_k_other % vec != 0) return false;
+  return true;
+}
+
+template <typename T, typename TC, int BM, int BN>
+void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
+  constexpr int BK = Tr<T>::BK, VEC = Tr<T>::VEC;
+  KParams kp;
+  kp.a = a;
+  kp.splits = splits;
+  kp.ktiles = cdiv(a.K, BK);
+  const int64_t total = a.R * kp.ktiles;
+  kp.steps_per_split = cdiv(total, splits);
+  kp.tiles_m = (int)cdiv(a.M, BM);
+  kp.tiles_n = (int)cdiv(a.N, BN);
+  kp.nwork = (int64_t)kp.tiles_m * kp.tiles_n * a.Z * splits;
+  kp.per_xcd = cdiv(kp.nwork, kXcd);
+  MLCC_REQUIRE(kp.per_xcd * kXcd < (int64_t)1 << 31, MLCC_E_ARG, "gemm: grid too large");
+  typedef typename std::conditional<sizeof(T) == 8, double, float>::type acc_t;
+  kp.work = nullptr;
+  if (splits > 1) kp.work = ex.scratch(sizeof(acc_t) * (size_t)splits * a.Z * a.M * a.N);
+  // layouts: an operand is staged [k][m] when m has the smaller stride
+  const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
+  const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
+  kp.vec_a = vec_ok(a.A, akm ? a.sAm : a.sAk, a.sAk, a.sAr, a.sAz, VEC, akm);
+  kp.vec_b = vec_ok(a.B, bkn ? a.sBn : a.sBk, a.sBk, a.sBr, a.sBz, VEC, bkn);
+  const dim3 grid((unsigned)(kp.per_xcd * kXcd));
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (ex.prof && ex.prof->on) {
+    ev = ex.prof->next();
+    MLCC_HIP(hipEventRecord(ev.first, ex.stream));
+  }
+  if (akm && bkn)
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, true>), grid, dim3(kThreads), 0, ex.stream, kp);
+  else if (akm)
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, false>), grid, dim3(kThreads), 0, ex.stream, kp);
+  else if (bkn)
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, true>), grid, dim3(kThreads), 0, ex.stream, kp);
+  else
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, false>), grid, dim3(kThreads), 0, ex.stream, kp);
+  MLCC_HIP(hipGetLastError());
+  if (ev.first) {
+    MLCC_HIP(hipEventRecord(ev.second, ex.stream));
+    ex.prof->recs.push_back({a.tag, ev.first, ev.second,
+                             2.0 * (double)a.M * a.N * a.K * a.R * a.Z});
+  }
+  if (splits > 1) {
+    const int64_t n = a.Z * a.M * a.N;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_split_reduce<acc_t, TC>), dim3(blocks), dim3(256), 0, ex.stream, kp);
+    MLCC_HIP(hipGetLastError());
+  }
+}
+
+// The tile menu: (BM, BN) multiples of 32.
+#define MLCC_GEMM_TILES(X) \
+  X(128, 128) X(128, 96) X(96, 128) X(128, 64) X(64, 128) X(96, 96) X(96, 64) X(64, 96) \
+  X(64, 64) X(128, 32) X(32, 128) X(96, 32) X(32, 96) X(64, 32) X(32, 64) X(32, 32)    \
+  X(96, 160) X(160, 96) X(64, 160) X(160, 64) X(32, 160) X(160, 32)
+
+typedef void (*LaunchFn)(Exec &, const GemmArgs &, int);
+struct Tile {
+  int bm, bn;
+  LaunchFn fn;
+};
+
+// Pick the tile with the lowest modelled time: padded MACs, an operand-load
+// overhead that grows as the tile shrinks, the number of rounds of ~512
+// resident blocks, and the split reduction's traffic.
+template <typename T, typename TC>
+void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles) {
+  constexpr int BK = Tr<T>::BK;
+  const int64_t steps = a.R * cdiv(a.K, BK);
+  auto splits_for = [&](int64_t blocks) {
+    int s = 1;
+    if (blocks < 512 && steps >= 8) {
+      s = (int)std::min<int64_t>(cdiv(512, blocks), steps / 4);
+      s = std::max(1, std::min(s, 128));
+    }
+    return s;
+  };
+  static const char *forced = std::getenv("MLCC_GEMM_TILE");
+  int fm = 0, fn = 0;
+  if (forced && std::sscanf(forced, "%dx%d", &fm, &fn) != 2) fm = fn = 0;
+  int best = -1;
+  double best_cost = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    const int bm = tiles[t].bm, bn = tiles[t].bn;
+    if (fm > 0 && (bm != fm || bn != fn)) continue;
+    const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
+    const int s = splits_for(blocks);
+    const double rounds = std::ceil((double)(blocks * s) / 512.0);
+    const double f = 1.0 + 16.0 * (1.0 / bm + 1.0 / bn);
+    const double per_block = (double)bm * bn * ((double)cdiv(steps, s) * BK * f + 16.0);
+    double cost = rounds * per_block;
+    if (s > 1) cost += 2.0 * (double)s * a.Z * a.M * a.N;
+    if (best < 0 || cost < best_cost) {
+      best = t;
+      best_cost = cost;
+    }
+  }
+  if (best < 0) best = 0;
+  const int64_t blocks = cdiv(a.M, tiles[best].bm) * cdiv(a.N, tiles[best].bn) * a.Z;
+  tiles[best].fn(ex, a, splits_for(blocks));
+}
+
+}  // namespace gk
+
+// per operand-type entry points (one translation unit each)
+void gemm_f64(Exec &ex, const GemmArgs &a);
+void gemm_f32(Exec &ex, const GemmArgs &a);
+void gemm_f32_out64(Exec &ex, const GemmArgs &a);
+
+}  // namespace mlcc

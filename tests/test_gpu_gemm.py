@@ -124,3 +124,68 @@ def test_gemm_two_level_indices(ctx, prec):
     got = Cd.cpu().numpy().astype(np.float64)
     tol = 1e-12 if prec == "fp64" else 3e-5
     assert np.abs(got - ref).max() < tol * 10
+
+
+MISALIGNED = [
+    # M, N, K, R, A-layout, B-layout, element offset of A and B
+    (70, 45, 37, 3, "k", "n", 1),
+    (70, 45, 37, 3, "m", "k", 1),
+    (37, 61, 43, 2, "m", "n", 0),   # ragged m-contiguous and n-contiguous tiles
+    (129, 97, 30, 2, "k", "k", 0),  # K not a multiple of the vector width
+    (161, 161, 64, 1, "m", "k", 3),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", MISALIGNED)
+def test_gemm_vector_fallbacks(ctx, prec, case):
+    """Operands whose base, stride or extent rule out 16-byte loads take the
+    element-wise path; results must not depend on which path ran."""
+    M, N, K, R, al, bl, shift = case
+    rng = np.random.default_rng(abs(hash(case)) % 2**32)
+    sAm, sAk = (K, 1) if al == "k" else (1, M)
+    sBk, sBn = (N, 1) if bl == "n" else (1, K)
+    sA = [sAm, sAk, M * K, 0]
+    sB = [sBk, sBn, K * N, 0]
+    A = rng.standard_normal(M * K * R + shift)
+    B = rng.standard_normal(K * N * R + shift)
+    ref = ref_gemm(A[shift:], sA, B[shift:], sB, M, N, K, R, 1)[0]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Ad = torch.tensor(A, dtype=dt, device="cuda")[shift:]
+    Bd = torch.tensor(B, dtype=dt, device="cuda")[shift:]
+    Cd = torch.zeros(M * N, dtype=dt, device="cuda")
+    ctx.gemm(mlcc.PREC[prec], M, N, K, R, 1, 1.0, Ad, sA, Bd, sB, 0.0, Cd, [N, 1, 0])
+    got = Cd.cpu().numpy().astype(np.float64).reshape(M, N)
+    tol = 1e-13 if prec == "fp64" else 3e-6
+    assert np.abs(got - ref).max() <= tol * (np.sqrt(K * R) + 1.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("ml", [37, 16])
+def test_gemm_two_level_contiguous_rows(ctx, prec, ml):
+    """m-contiguous A with a two-level row index whose low extent is (37) or
+    is not (16) cut by the 16-byte load units."""
+    import ctypes as C
+    rng = np.random.default_rng(11 + ml)
+    Mh, K, N, R = 5, 23, 40, 3
+    M = Mh * ml
+    sA_hi, sAk, sAr = 64, 400, 400 * K   # A (m=(mh,ml), k) at r*sAr + k*sAk + mh*64 + ml
+    A = rng.standard_normal(R * sAr)
+    B = rng.standard_normal(R * K * N)
+    ref = np.zeros((M, N))
+    for r in range(R):
+        idx = (r * sAr + np.arange(K)[None, :] * sAk
+               + (np.arange(M) // ml)[:, None] * sA_hi + (np.arange(M) % ml)[:, None])
+        ref += A[idx] @ B[r * K * N:(r + 1) * K * N].reshape(K, N)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Ad = torch.tensor(A, dtype=dt, device="cuda")
+    Bd = torch.tensor(B, dtype=dt, device="cuda")
+    Cd = torch.zeros(M * N, dtype=dt, device="cuda")
+    st = ctx.lib.mlcc_gemm2(ctx.h, mlcc.PREC[prec], M, N, K, R, 1, 1.0, C.c_void_p(Ad.data_ptr()),
+                            (C.c_int64 * 4)(1, sAk, sAr, 0), C.c_void_p(Bd.data_ptr()),
+                            (C.c_int64 * 4)(N, 1, K * N, 0), 0.0, C.c_void_p(Cd.data_ptr()),
+                            (C.c_int64 * 3)(N, 1, 0), (C.c_int64 * 6)(ml, sA_hi, ml * N, 0, 0, 0))
+    assert st == 0, ctx.last_error()
+    got = Cd.cpu().numpy().astype(np.float64).reshape(M, N)
+    tol = 1e-13 if prec == "fp64" else 3e-6
+    assert np.abs(got - ref).max() <= tol * (np.sqrt(K * R) + 1.0)
