@@ -37,7 +37,10 @@
  *   the call returns MLCC_OK (MLCC_E_NOCONV also fills best-so-far values).
  * Streams.  All device work of a context is ordered on the stream given at
  *   context creation; every call except mlcc_submit/mlcc_poll has completed
- *   its device work when it returns.
+ *   its device work when it returns.  Device memory passed in must be ready
+ *   when the call is made: work that produces it on another stream (a
+ *   library's own stream is non-blocking) must have completed, or been made
+ *   to precede the call, by the caller.
  * Threading.  One host thread at a time per context (and its problems);
  *   mlcc_submit / mlcc_poll are thread safe.
  * Units.  Hartree.

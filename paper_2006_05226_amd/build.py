@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlcc.so")
-SOURCES = ["gemm_f64.hip", "gemm_f32.hip", "gemm_f32d.hip", "gemm.hip", "kernels.hip", "synth.hip", "problem.cpp", "drivers.cpp", "dense.cpp", "api.cpp",
+SOURCES = ["gemm_f64.hip", "gemm_f32.hip", "gemm_f32d.hip", "gemm_f64g.hip", "gemm_f32g.hip", "gemm_f32dg.hip", "gemm.hip", "kernels.hip", "synth.hip", "problem.cpp", "drivers.cpp", "dense.cpp", "api.cpp",
            "server.cpp"]
 ARCH = os.environ.get("MLCC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

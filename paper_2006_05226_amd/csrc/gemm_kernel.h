@@ -83,7 +83,7 @@ template <> struct Tr<float> {
 // global memory as units of VEC contiguous elements.  KMAJ: the operand's
 // contiguous global dimension is its output dimension (m or n), so LDS holds
 // [k][m]; otherwise LDS holds [m][k].
-template <typename T, int BMN, bool KMAJ> struct Stage {
+template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
   static constexpr int BK = Tr<T>::BK, VEC = Tr<T>::VEC;
   static constexpr int PK = 16 / (int)sizeof(T);      // [m][k] rows: +16 bytes
   static constexpr int PM = sizeof(T) == 8 ? 4 : 2;   // [k][m] rows: see the bank note
@@ -142,6 +142,45 @@ template <typename T, int BMN, bool KMAJ> struct Stage {
 #pragma unroll
     for (int e = 0; e < U; ++e) all = all && vec[e];
     fast = __syncthreads_and(all) != 0;
+  }
+
+  // VONLY: the host has checked that every unit of every tile is a 16-byte
+  // group (unit stride, aligned, no group cut by the extent or by the
+  // two-level index); units outside the operand read the tile's first group
+  // and k beyond K is masked, so every load is unconditional.
+  __device__ __forceinline__ void init_v(int tid, int64_t mn0, int64_t lo, int64_t s_mn,
+                                         int64_t n_mn, int64_t s_hi) {
+    const int64_t off0 = two_level(mn0, lo, s_mn, s_hi);
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      const int u = tid + e * kThreads;
+      int mn;
+      if (KMAJ) {
+        row[e] = u / (BMN / VEC);
+        mn = (u % (BMN / VEC)) * VEC;
+        col[e] = mn;
+      } else {
+        mn = u / (BK / VEC);
+        row[e] = mn;
+        col[e] = (u % (BK / VEC)) * VEC;
+      }
+      const int64_t i = mn0 + mn;
+      off[e] = i < n_mn ? two_level(i, lo, s_mn, s_hi) : off0;
+    }
+  }
+  __device__ __forceinline__ void load_v(T (&rg)[U][VEC], const T *X, int64_t k0, int64_t K,
+                                         int64_t s_k) const {
+    typedef typename Tr<T>::v16 v16;
+#pragma unroll
+    for (int e = 0; e < U; ++e) {
+      const int64_t k = k0 + (KMAJ ? row[e] : col[e]);
+      const bool in = k < K;
+      const int64_t kc = in ? k : 0;
+      const T *src = KMAJ ? X + off[e] + kc * s_k : X + off[e] + kc;
+      const v16 v = *reinterpret_cast<const v16 *>(src);
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) rg[e][q] = in ? v[q] : T(0);
+    }
   }
 
   // a k-step of the block's interior: every unit in range and aligned, so
@@ -238,13 +277,13 @@ template <> struct OutMap<double> {
   }
 };
 
-template <typename T, typename TC, int BM, int BN, bool AKM, bool BKN>
+template <typename T, typename TC, int BM, int BN, bool AKM, bool BKN, bool VONLY>
 __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
   constexpr int S = Tr<T>::S, VEC = Tr<T>::VEC;
   constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
   static_assert(FM * 32 == BM && FN * 32 == BN, "tile");
-  typedef Stage<T, BM, AKM> SA;
-  typedef Stage<T, BN, BKN> SB;
+  typedef Stage<T, BM, AKM, VONLY> SA;
+  typedef Stage<T, BN, BKN, VONLY> SB;
   __shared__ __attribute__((aligned(16))) T As[2][SA::ROWS][SA::LEN];
   __shared__ __attribute__((aligned(16))) T Bs[2][SB::ROWS][SB::LEN];
 
@@ -272,8 +311,13 @@ __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
 
   SA sa;
   SB sb;
-  sa.init(tid, m0, p.M, p.Mlo, p.sAm, p.sAm_hi, kp.vec_a);
-  sb.init(tid, n0, p.N, p.Nlo, p.sBn, p.sBn_hi, kp.vec_b);
+  if constexpr (VONLY) {
+    sa.init_v(tid, m0, p.Mlo, p.sAm, p.M, p.sAm_hi);
+    sb.init_v(tid, n0, p.Nlo, p.sBn, p.N, p.sBn_hi);
+  } else {
+    sa.init(tid, m0, p.M, p.Mlo, p.sAm, p.sAm_hi, kp.vec_a);
+    sb.init(tid, n0, p.N, p.Nlo, p.sBn, p.sBn_hi, kp.vec_b);
+  }
 
   // FP32: acc[i][j][e] = element e of the 16x16x4 fragment accumulator;
   // FP64: acc[i][j][r] = the 4x4x4 accumulator of rotation r
@@ -293,11 +337,16 @@ __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
   auto load_next = [&]() {
     const T *Ar = Az + lr * p.sAr;
     const T *Br = Bz + lr * p.sBr;
-    const bool kfull = lk0 + BK <= p.K;
-    if (sa.fast && kfull) sa.load_fast(ra, Ar, lk0, p.sAk);
-    else sa.load(ra, Ar, lk0, p.K, p.sAk, m0, p.M, p.Mlo, p.sAm, p.sAm_hi);
-    if (sb.fast && kfull) sb.load_fast(rb, Br, lk0, p.sBk);
-    else sb.load(rb, Br, lk0, p.K, p.sBk, n0, p.N, p.Nlo, p.sBn, p.sBn_hi);
+    if constexpr (VONLY) {
+      sa.load_v(ra, Ar, lk0, p.K, p.sAk);
+      sb.load_v(rb, Br, lk0, p.K, p.sBk);
+    } else {
+      const bool kfull = lk0 + BK <= p.K;
+      if (sa.fast && kfull) sa.load_fast(ra, Ar, lk0, p.sAk);
+      else sa.load(ra, Ar, lk0, p.K, p.sAk, m0, p.M, p.Mlo, p.sAm, p.sAm_hi);
+      if (sb.fast && kfull) sb.load_fast(rb, Br, lk0, p.sBk);
+      else sb.load(rb, Br, lk0, p.K, p.sBk, n0, p.N, p.Nlo, p.sBn, p.sBn_hi);
+    }
     lk0 += BK;
     if (lk0 >= kp.ktiles * BK) {
       lk0 = 0;
@@ -435,7 +484,33 @@ inline bool vec_ok(const void *base, int64_t s_fast, int64_t s_k_other, int64_t 
   return true;
 }
 
-template <typename T, typename TC, int BM, int BN>
+// Every unit of one operand is a 16-byte group in range of its row: unit
+// stride along the contiguous dimension, aligned strides and base, and (for
+// an m/n-contiguous operand) an extent and two-level low extent that are
+// multiples of the group; a k-contiguous operand needs K a multiple of it.
+inline bool operand_vec(const void *base, bool kmaj, int64_t s_mn, int64_t s_k, int64_t s_r,
+                        int64_t s_z, int64_t n_mn, int64_t K, int64_t lo, int64_t s_hi, int vec) {
+  if (reinterpret_cast<uintptr_t>(base) % 16 != 0) return false;
+  if (s_r % vec != 0 || s_z % vec != 0) return false;
+  if (kmaj) {
+    if (s_mn != 1 || s_k % vec != 0 || n_mn % vec != 0) return false;
+    if (lo > 0 && (lo % vec != 0 || s_hi % vec != 0)) return false;
+  } else {
+    if (s_k != 1 || s_mn % vec != 0 || K % vec != 0) return false;
+    if (lo > 0 && s_hi % vec != 0) return false;
+  }
+  return true;
+}
+
+inline bool gemm_vonly(const GemmArgs &a, int vec) {
+  const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
+  const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
+  return a.K > 0 &&
+         operand_vec(a.A, akm, a.sAm, a.sAk, a.sAr, a.sAz, a.M, a.K, a.Mlo, a.sAm_hi, vec) &&
+         operand_vec(a.B, bkn, a.sBn, a.sBk, a.sBr, a.sBz, a.N, a.K, a.Nlo, a.sBn_hi, vec);
+}
+
+template <typename T, typename TC, int BM, int BN, bool VONLY>
 void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   constexpr int BK = Tr<T>::BK, VEC = Tr<T>::VEC;
   KParams kp;
@@ -464,13 +539,13 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
     MLCC_HIP(hipEventRecord(ev.first, ex.stream));
   }
   if (akm && bkn)
-    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, true>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, true, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
   else if (akm)
-    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, false>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, false, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
   else if (bkn)
-    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, true>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, true, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
   else
-    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, false>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, false, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
   MLCC_HIP(hipGetLastError());
   if (ev.first) {
     MLCC_HIP(hipEventRecord(ev.second, ex.stream));
@@ -485,7 +560,11 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   }
 }
 
-// The tile menu: (BM, BN) multiples of 32.
+// The tile menus: (BM, BN) multiples of 32; the general (element-wise
+// fallback) kernel is built for fewer shapes.
+#define MLCC_GEMM_TILES_GENERAL(X) \
+  X(128, 128) X(128, 64) X(64, 128) X(64, 64) X(128, 32) X(32, 128) X(64, 32) X(32, 64) X(32, 32) \
+  X(96, 160)
 #define MLCC_GEMM_TILES(X) \
   X(128, 128) X(128, 96) X(96, 128) X(128, 64) X(64, 128) X(96, 96) X(96, 64) X(64, 96) \
   X(64, 64) X(128, 32) X(32, 128) X(96, 32) X(32, 96) X(64, 32) X(32, 64) X(32, 32)    \
@@ -539,9 +618,13 @@ void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles) {
 
 }  // namespace gk
 
-// per operand-type entry points (one translation unit each)
+// per operand-type entry points (one translation unit each for the
+// vector-only and the general kernels)
 void gemm_f64(Exec &ex, const GemmArgs &a);
 void gemm_f32(Exec &ex, const GemmArgs &a);
 void gemm_f32_out64(Exec &ex, const GemmArgs &a);
+void gemm_f64_general(Exec &ex, const GemmArgs &a);
+void gemm_f32_general(Exec &ex, const GemmArgs &a);
+void gemm_f32_out64_general(Exec &ex, const GemmArgs &a);
 
 }  // namespace mlcc

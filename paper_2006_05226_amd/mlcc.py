@@ -134,6 +134,11 @@ def _ptr(a):
         return a.ctypes.data
     if hasattr(a, "data_ptr"):
         assert a.is_contiguous(), "tensors must be contiguous"
+        if getattr(a, "is_cuda", False):
+            # the library's stream does not wait for torch's: finish the work
+            # that produced this tensor (an upload, a fill) first
+            import torch
+            torch.cuda.current_stream(a.device).synchronize()
         return a.data_ptr()
     raise TypeError(type(a))
 

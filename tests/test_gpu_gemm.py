@@ -115,6 +115,7 @@ def test_gemm_two_level_indices(ctx, prec):
     lib = ctx.lib
     # the binding's gemm has no two-level arguments: exercise them through the
     # debug entry point
+    torch.cuda.synchronize()  # the uploads above run on torch's stream
     st = lib.mlcc_gemm2(ctx.h, mlcc.PREC[prec], M, N, K, R, 1, 1.5, C.c_void_p(Ad.data_ptr()),
                         (C.c_int64 * 4)(K, 1, sAr, 0), C.c_void_p(Bd.data_ptr()),
                         (C.c_int64 * 4)(Nl, 1, sBr, 0), 0.5, C.c_void_p(Cd.data_ptr()),
@@ -181,6 +182,7 @@ def test_gemm_two_level_contiguous_rows(ctx, prec, ml):
     Ad = torch.tensor(A, dtype=dt, device="cuda")
     Bd = torch.tensor(B, dtype=dt, device="cuda")
     Cd = torch.zeros(M * N, dtype=dt, device="cuda")
+    torch.cuda.synchronize()  # the uploads above run on torch's stream
     st = ctx.lib.mlcc_gemm2(ctx.h, mlcc.PREC[prec], M, N, K, R, 1, 1.0, C.c_void_p(Ad.data_ptr()),
                             (C.c_int64 * 4)(1, sAk, sAr, 0), C.c_void_p(Bd.data_ptr()),
                             (C.c_int64 * 4)(N, 1, K * N, 0), 0.0, C.c_void_p(Cd.data_ptr()),
