@@ -17,6 +17,14 @@ roots to 1e-6) and a ground-state solve, the dominant contraction's achieved
 TFLOP/s from HIP events on the library stream, and the FP64 oracle timed on the
 host cores for one transform at the same shape.
 
+Serving (extra.serving): a stream of MLCC2 excitation requests of uneven size
+(n_occ uniform in [20, 80], n_vir = 10 n_occ, n_chol = 3 n_vir, active
+0.375 n_occ / 3.75 n_occ, 3 roots, FP32 contractions, effective-singles
+Davidson, Cholesky vectors drawn on the device) through the continuous-
+batching server: first all at once (saturated solves/s), then with Poisson
+arrivals at 0.7 of that rate (p50 / p99 latency from submission to a
+poll-visible result).
+
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
 from __future__ import annotations
@@ -74,6 +82,103 @@ print(json.dumps(dict(seconds=dt, cores=min(cores, threads))))
                 "sample": f"failed: {e}"}
 
 
+def _profiled_traffic(tag: str, config: str, precision: str):
+    """HBM bytes per launch of a contraction from its committed rocprofv3 PMC
+    summary, or None when there is none or the GEMM sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{tag}_{config}_{precision}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source_sha256"):
+            k, v = line.split(":", 1)
+            fields[k] = v.strip()
+    h = hashlib.sha256()
+    for f in ("gemm_kernel.h", "gemm_f64.hip", "gemm_f64g.hip"):
+        with open(os.path.join(ROOT, "paper_2006_05226_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
+def _serving(mlcc, n_req, slots, precision="fp32", rate_frac=0.7, gs_tol=1e-6, es_tol=1e-5):
+    import numpy as np
+    from paper_2006_05226_amd.synth import gen_eps, serving_stream
+
+    reqs, gaps = serving_stream(n_req)
+    ctx = mlcc.Context(0)
+    descs = []
+    for q in reqs:
+        eps = gen_eps(q["n_occ"], q["n_vir"], q["n_occ_act"], q["seed"])
+        descs.append(mlcc.Server.desc(None, eps, q["n_occ"], q["n_vir"], q["n_occ_act"],
+                                      q["n_vir_act"], "mlcc2", precision, n_chol=q["n_chol"],
+                                      seed=q["seed"]))
+
+    def submit(srv, d):
+        return srv.submit(d[0], 3, gs_tol=gs_tol, es_tol=es_tol, effective=True)
+
+    # warm-up: one small request (first launches, allocator)
+    srv = mlcc.Server(ctx, max_slots=slots)
+    small = min(range(n_req), key=lambda r: reqs[r]["n_occ"])
+    srv.wait(submit(srv, descs[small]))
+    srv.close()
+
+    # closed loop: every request queued at once
+    srv = mlcc.Server(ctx, max_slots=slots)
+    t0 = time.perf_counter()
+    tickets = [submit(srv, d) for d in descs]
+    burst = []
+    for i, t in enumerate(tickets):
+        burst.append(srv.wait(t, timeout_s=1200))
+        print(f"  burst {i + 1}/{n_req} done at {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
+    wall = time.perf_counter() - t0
+    srv.close()
+    rate = n_req / wall
+    # open loop: Poisson arrivals at rate_frac of the saturated rate
+    lam = rate_frac * rate
+    srv = mlcc.Server(ctx, max_slots=slots)
+    t0 = time.perf_counter()
+    t_next = 0.0
+    tickets = []
+    for d, g in zip(descs, gaps):
+        t_next += g / lam
+        while time.perf_counter() - t0 < t_next:
+            time.sleep(min(0.002, max(0.0, t_next - (time.perf_counter() - t0))))
+        tickets.append(submit(srv, d))
+    stream = []
+    for i, t in enumerate(tickets):
+        stream.append(srv.wait(t, timeout_s=1200))
+        print(f"  stream {i + 1}/{n_req} done at {time.perf_counter() - t0:.1f} s",
+              file=sys.stderr, flush=True)
+    wall2 = time.perf_counter() - t0
+    srv.close()
+    ctx.close()
+    lat = np.array([r["t_done"] - r["t_submit"] for r in stream])
+    lat_b = np.array([r["t_done"] - r["t_submit"] for r in burst])
+    ok = all(r["status"] == 0 for r in burst + stream)
+    same = all(a["omega"] == b["omega"] and a["e_corr"] == b["e_corr"]
+               for a, b in zip(burst, stream))
+    spans = sorted((r["t_admit"], r["t_done"]) for r in stream)
+    overlap = sum(1 for i in range(len(spans) - 1) if spans[i + 1][0] < spans[i][1])
+    return {
+        "requests": n_req, "slots": slots, "precision": precision, "roots": 3,
+        "solves_per_s": rate, "burst_seconds": wall,
+        "burst_latency_p50_s": float(np.percentile(lat_b, 50)),
+        "arrival_rate_per_s": lam, "stream_seconds": wall2,
+        "solves_per_s_stream": n_req / wall2,
+        "latency_p50_s": float(np.percentile(lat, 50)),
+        "latency_p99_s": float(np.percentile(lat, 99)),
+        "all_ok": ok, "burst_equals_stream": same, "admissions_while_busy": overlap,
+        "sizes_n_occ": [q["n_occ"] for q in reqs],
+        "workload": "MLCC2 excitation requests, n_occ uniform in [20,80], n_vir=10 n_occ, "
+                    "n_chol=3 n_vir, active round(0.375 n_occ)/10x, 3 roots, FP32 contractions, "
+                    "effective-singles Davidson, synthetic device-drawn Cholesky vectors",
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +189,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true", help="skip the Davidson solve timing")
     ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 512 MiB device copy 3 times (reference for HBM counters)")
+    ap.add_argument("--serve", type=int, default=256,
+                    help="requests in the serving stream (0 = skip; 256 = the full stream)")
+    ap.add_argument("--slots", type=int, default=8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -98,6 +208,14 @@ def main():
     from paper_2006_05226_amd import mlcc
     from paper_2006_05226_amd.synth import CONFIGS, gen_inputs, gen_vectors
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")  # 512 MiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     c = CONFIGS[args.config]
     O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
     M = o * v
@@ -107,6 +225,7 @@ def main():
     precs = [p for p in args.precisions.split(",") if p]
     res = {}
     for prec in precs:
+        print(f"transforms: {prec}", file=sys.stderr, flush=True)
         ctx = mlcc.Context(0)
         P = mlcc.Problem(ctx, inp.L, inp.eps, O, V, o, v, model="mlcc2", precision=prec)
         t0 = time.perf_counter()
@@ -149,8 +268,11 @@ def main():
     d = st[dom]
     achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
     total_gemm_ms = sum(s["ms"] for s in st.values())
+    traffic = _profiled_traffic(dom, args.config, main_p)
     roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[main_p],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[main_p], "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[main_p], "traffic": traffic,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
+                                "scaled by a 512 MiB copy)",
                 "kernel": dom, "launches": d["launches"],
                 "avg_launch_ms": d["ms"] / d["launches"],
                 "flops_per_launch": d["flops"] / d["launches"],
@@ -163,6 +285,9 @@ def main():
                                                        key=lambda kv: -kv[1]["ms"])[:8]}
     if "fp32" in res and "fp64" in res:
         extra["speedup_fp32_vs_fp64"] = res["fp32"]["transforms_per_s"] / res["fp64"]["transforms_per_s"]
+    if args.serve > 0:
+        print(f"serving: {args.serve} requests", file=sys.stderr, flush=True)
+        extra["serving"] = _serving(mlcc, args.serve, args.slots)
     cpu = None if args.no_cpu_baseline else _cpu_baseline()
     line = {
         "metric": "Jacobian transforms/s (MLCC2, full space)",

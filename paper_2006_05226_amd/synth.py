@@ -80,6 +80,34 @@ def gen_inputs(n_occ: int, n_vir: int, n_chol: int, n_occ_act: int | None = None
                   n_occ_act=n_occ_act, n_vir_act=n_vir_act, seed=seed)
 
 
+def gen_eps(n_occ: int, n_vir: int, n_occ_act: int | None = None, seed: int = 0) -> np.ndarray:
+    """Orbital energies alone (same distributions and ordering as gen_inputs,
+    own stream), for requests whose Cholesky vectors are drawn on the device."""
+    n_occ_act = n_occ if n_occ_act is None else n_occ_act
+    rng = np.random.default_rng(seed)
+    e_occ = np.sort(rng.uniform(-1.5, -0.3, n_occ))
+    e_vir = np.sort(rng.uniform(0.1, 3.0, n_vir))
+    e_occ = np.concatenate([e_occ[n_occ - n_occ_act:], e_occ[: n_occ - n_occ_act]])
+    return np.concatenate([e_occ, e_vir]).astype(np.float64)
+
+
+def serving_stream(n_req: int, seed_sizes: int = 0, seed_arrivals: int = 1, lo: int = 20,
+                   hi: int = 80):
+    """Sizes of a stream of MLCC2 excitation requests: n_occ uniform in
+    [lo, hi], n_vir = 10 n_occ, n_chol = 3 n_vir, active o = round(0.375 n_occ)
+    occupied and v = 10 o virtual; request r draws its inputs with seed 1000 + r.
+    Also the unit-rate exponential inter-arrival gaps (scaled by 1/rate)."""
+    sizes = np.random.default_rng(seed_sizes).integers(lo, hi + 1, size=n_req)
+    reqs = []
+    for r, no in enumerate(int(x) for x in sizes):
+        nv = 10 * no
+        o = int(round(0.375 * no))
+        reqs.append(dict(n_occ=no, n_vir=nv, n_chol=3 * nv, n_occ_act=o, n_vir_act=10 * o,
+                         seed=1000 + r))
+    gaps = np.random.default_rng(seed_arrivals).exponential(1.0, size=n_req)
+    return reqs, gaps
+
+
 def gen_vectors(n_vec: int, n_occ: int, n_vir: int, m_doubles: int, seed: int):
     """Random trial vectors (singles (n_vec, V, O) and symmetric doubles
     (n_vec, M, M)) for Jacobian-transform parity and timing."""
