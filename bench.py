@@ -103,6 +103,68 @@ def _profiled_traffic(tag: str, config: str, precision: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
+def _mlccsd_leg(mlcc, steps, warmup, precisions, config="mlccsd_60_600_2000", nvec=3):
+    """MLCCSD (CCS/CCSD) at its full-size workload: ground state, Jacobian
+    transforms/s for a batch of nvec trial vectors, and a Davidson solve, per
+    precision; Cholesky vectors drawn on the device (seed 0)."""
+    import torch
+    from paper_2006_05226_amd.synth import CONFIGS, gen_eps, gen_vectors
+
+    c = CONFIGS[config]
+    O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
+    M = o * v
+    eps = gen_eps(O, V, o, seed=0)
+    c1, c2 = gen_vectors(nvec, O, V, M, seed=1)
+    import numpy as np
+    cvec = np.concatenate([c1.reshape(nvec, -1), c2.reshape(nvec, -1)], axis=1)
+    out = {"workload": f"MLCCSD (CCS/CCSD), n_occ={O} n_vir={V} n_chol={J}, CCSD active {o}/{v}, "
+                       f"device-drawn Cholesky vectors, batch of {nvec} trial vectors"}
+    for prec in precisions:
+        print(f"mlccsd: {prec}", file=sys.stderr, flush=True)
+        ctx = mlcc.Context(0)
+        P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlccsd", precision=prec, n_chol=J,
+                         seed=0)
+        t0 = time.perf_counter()
+        gs = P.ground_state(tol=1e-8 if prec == "fp64" else 1e-6)
+        t_gs = time.perf_counter() - t0
+        cd = torch.tensor(cvec, device="cuda")
+        sd = torch.empty_like(cd)
+        P.jacobian_transform(cd, sd)
+        for _ in range(warmup):
+            P.jacobian_transform(cd, sd)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            P.jacobian_transform(cd, sd)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stats = ctx.profile_stats()
+        ctx.profile(False)
+        t0 = time.perf_counter()
+        dav = P.davidson(3, tol=1e-6)
+        t_dav = time.perf_counter() - t0
+        top = sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:6]
+        out[prec] = dict(gs_seconds=t_gs, gs_iterations=gs["iterations"], e_corr=gs["energy"],
+                         gs_converged=gs["converged"],
+                         transforms_per_s=steps * nvec / dt, ms_per_step=1e3 * dt / steps,
+                         davidson_seconds=t_dav, davidson_transforms=dav["transforms"],
+                         omega=list(dav["omega"]), davidson_converged=dav["converged"],
+                         contractions={k: dict(ms_per_step=st["ms"] / steps,
+                                               tflops=st["flops"] / max(st["ms"], 1e-9) / 1e9)
+                                       for k, st in top})
+        P.close()
+        ctx.close()
+        del cd, sd
+        torch.cuda.empty_cache()
+    if "fp64" in out and "fp32" in out:
+        out["speedup_fp32_vs_fp64"] = out["fp32"]["transforms_per_s"] / out["fp64"]["transforms_per_s"]
+        out["fp32_minus_fp64"] = dict(
+            e_corr=out["fp32"]["e_corr"] - out["fp64"]["e_corr"],
+            omega=[a - b for a, b in zip(out["fp32"]["omega"], out["fp64"]["omega"])])
+    return out
+
+
 def _serving(mlcc, n_req, slots, precision="fp32", rate_frac=0.7, gs_tol=1e-6, es_tol=1e-5):
     import numpy as np
     from paper_2006_05226_amd.synth import gen_eps, serving_stream
@@ -189,10 +251,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true", help="skip the Davidson solve timing")
     ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--no-mlccsd", action="store_true", help="skip the MLCCSD leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy 3 times (reference for HBM counters)")
-    ap.add_argument("--serve", type=int, default=256,
-                    help="requests in the serving stream (0 = skip; 256 = the full stream)")
+    ap.add_argument("--serve", type=int, default=64,
+                    help="requests in the serving stream (0 = skip; 256 = the full stream, "
+                         "about 4 minutes)")
     ap.add_argument("--slots", type=int, default=8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -285,6 +349,8 @@ def main():
                                                        key=lambda kv: -kv[1]["ms"])[:8]}
     if "fp32" in res and "fp64" in res:
         extra["speedup_fp32_vs_fp64"] = res["fp32"]["transforms_per_s"] / res["fp64"]["transforms_per_s"]
+    if not args.no_mlccsd:
+        extra["mlccsd"] = _mlccsd_leg(mlcc, max(3, args.steps // 4), 1, precs)
     if args.serve > 0:
         print(f"serving: {args.serve} requests", file=sys.stderr, flush=True)
         extra["serving"] = _serving(mlcc, args.serve, args.slots)
