@@ -22,7 +22,8 @@
 //   contiguous global dimension: [m][k] rows when k is contiguous (fragment
 //   reads are 16-byte vectors along k), [k][m] rows when m is contiguous.
 //   Global loads move 16 bytes per thread along the contiguous dimension when
-//   stride, alignment and bounds allow it, element by element otherwise.
+//   stride and bounds allow it (element alignment suffices: compute queues
+//   run in the unaligned access mode), element by element otherwise.
 //   Row padding keeps fragment reads free of bank conflicts.
 // * The next k-step's global loads are issued before the MFMAs of the current
 //   one; one barrier per k-step.
@@ -47,6 +48,11 @@ namespace gk {
 typedef double d2 __attribute__((ext_vector_type(2)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+// 16-byte global loads at element alignment: compute queues run in the
+// unaligned access mode, so a 16-byte load needs only in-range bytes, not a
+// 16-byte aligned address.
+typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
+typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
 constexpr int kThreads = 256;
 constexpr int kXcd = 8;
@@ -57,7 +63,7 @@ struct KParams {
   int tiles_m, tiles_n;
   int64_t ktiles, steps_per_split, nwork, per_xcd;
   void *work;  // [splits][Z][M][N] accumulators when splits > 1
-  int vec_a, vec_b;  // 16-byte global loads allowed (stride and base alignment)
+  int vec_a, vec_b;  // 16-byte global loads allowed (unit stride)
 };
 
 __device__ __forceinline__ int64_t two_level(int64_t i, int64_t lo_n, int64_t s_lo, int64_t s_hi) {
@@ -72,11 +78,13 @@ template <typename T> struct Tr;
 #endif
 template <> struct Tr<double> {
   static constexpr int BK = MLCC_F64_BK, VEC = 2, S = BK / 4;
-  typedef d2 v16;
+  typedef d2 v16;   // LDS (16-byte aligned)
+  typedef d2u g16;  // global memory (element aligned)
 };
 template <> struct Tr<float> {
   static constexpr int BK = 32, VEC = 4, S = 8;
   typedef f4 v16;
+  typedef f4u g16;
 };
 
 // Operand tile of a block: ROWS x COLS in LDS (COLS contiguous), loaded from
@@ -109,8 +117,8 @@ template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
   __device__ __forceinline__ void init(int tid, int64_t mn0, int64_t n_mn, int64_t lo, int64_t s_mn,
                                        int64_t s_hi, bool vec_ok) {
     const int64_t off0 = two_level(mn0, lo, s_mn, s_hi);
-    bool base_ok = off0 % VEC == 0;
-    if (KMAJ) base_ok = base_ok && mn0 + VEC <= n_mn && (lo <= 0 || (mn0 % lo) + VEC <= lo);
+    bool base_ok = true;
+    if (KMAJ) base_ok = mn0 + VEC <= n_mn && (lo <= 0 || (mn0 % lo) + VEC <= lo);
 #pragma unroll
     for (int e = 0; e < U; ++e) {
       const int u = tid + e * kThreads;
@@ -131,11 +139,11 @@ template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
         bool c = i + VEC <= n_mn;
         if (c && lo > 0) c = (i % lo) + VEC <= lo;
         contig[e] = c;
-        if (c) vec[e] = vec_ok && off[e] % VEC == 0;
+        if (c) vec[e] = vec_ok;
         else vec[e] = vec_ok && !ok[e] && base_ok;  // straddling units are never vectorised
       } else {
         contig[e] = true;
-        vec[e] = vec_ok && off[e] % VEC == 0;
+        vec[e] = vec_ok;
       }
     }
     bool all = true;
@@ -170,7 +178,7 @@ template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
   }
   __device__ __forceinline__ void load_v(T (&rg)[U][VEC], const T *X, int64_t k0, int64_t K,
                                          int64_t s_k) const {
-    typedef typename Tr<T>::v16 v16;
+    typedef typename Tr<T>::g16 v16;
 #pragma unroll
     for (int e = 0; e < U; ++e) {
       const int64_t k = k0 + (KMAJ ? row[e] : col[e]);
@@ -187,7 +195,7 @@ template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
   // the loads are unconditional and issue back to back
   __device__ __forceinline__ void load_fast(T (&rg)[U][VEC], const T *X, int64_t k0,
                                             int64_t s_k) const {
-    typedef typename Tr<T>::v16 v16;
+    typedef typename Tr<T>::g16 v16;
 #pragma unroll
     for (int e = 0; e < U; ++e) {
       const T *src = KMAJ ? X + off[e] + (k0 + row[e]) * s_k : X + off[e] + k0 + col[e];
@@ -472,42 +480,25 @@ __global__ void k_split_reduce(KParams kp) {
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// 16-byte loads need a unit-stride contiguous dimension, the other strides
-// that move between k-steps, slices and batches in multiples of VEC, and an
-// aligned base; row alignment is checked per unit in the kernel.
-inline bool vec_ok(const void *base, int64_t s_fast, int64_t s_k_other, int64_t s_r, int64_t s_z,
-                   int vec, bool kmaj) {
-  if (s_fast != 1) return false;
-  if (reinterpret_cast<uintptr_t>(base) % 16 != 0) return false;
-  if (s_r % vec != 0 || s_z % vec != 0) return false;
-  if (kmaj && s_k_other % vec != 0) return false;
-  return true;
-}
+// 16-byte loads need a unit-stride contiguous dimension (bounds are checked
+// per unit in the kernel).
+inline bool vec_ok(int64_t s_fast) { return s_fast == 1; }
 
-// Every unit of one operand is a 16-byte group in range of its row: unit
-// stride along the contiguous dimension, aligned strides and base, and (for
-// an m/n-contiguous operand) an extent and two-level low extent that are
-// multiples of the group; a k-contiguous operand needs K a multiple of it.
-inline bool operand_vec(const void *base, bool kmaj, int64_t s_mn, int64_t s_k, int64_t s_r,
-                        int64_t s_z, int64_t n_mn, int64_t K, int64_t lo, int64_t s_hi, int vec) {
-  if (reinterpret_cast<uintptr_t>(base) % 16 != 0) return false;
-  if (s_r % vec != 0 || s_z % vec != 0) return false;
-  if (kmaj) {
-    if (s_mn != 1 || s_k % vec != 0 || n_mn % vec != 0) return false;
-    if (lo > 0 && (lo % vec != 0 || s_hi % vec != 0)) return false;
-  } else {
-    if (s_k != 1 || s_mn % vec != 0 || K % vec != 0) return false;
-    if (lo > 0 && s_hi % vec != 0) return false;
-  }
-  return true;
+// Every unit of one operand is a 16-byte group in range: unit stride along
+// the contiguous dimension and, for an m/n-contiguous operand, an extent and
+// two-level low extent that are multiples of the group; a k-contiguous
+// operand needs K a multiple of it.
+inline bool operand_vec(bool kmaj, int64_t s_mn, int64_t s_k, int64_t n_mn, int64_t K, int64_t lo,
+                        int vec) {
+  if (kmaj) return s_mn == 1 && n_mn % vec == 0 && (lo <= 0 || lo % vec == 0);
+  return s_k == 1 && K % vec == 0;
 }
 
 inline bool gemm_vonly(const GemmArgs &a, int vec) {
   const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
   const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
-  return a.K > 0 &&
-         operand_vec(a.A, akm, a.sAm, a.sAk, a.sAr, a.sAz, a.M, a.K, a.Mlo, a.sAm_hi, vec) &&
-         operand_vec(a.B, bkn, a.sBn, a.sBk, a.sBr, a.sBz, a.N, a.K, a.Nlo, a.sBn_hi, vec);
+  return a.K > 0 && operand_vec(akm, a.sAm, a.sAk, a.M, a.K, a.Mlo, vec) &&
+         operand_vec(bkn, a.sBn, a.sBk, a.N, a.K, a.Nlo, vec);
 }
 
 template <typename T, typename TC, int BM, int BN, bool VONLY>
@@ -530,8 +521,8 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   // layouts: an operand is staged [k][m] when m has the smaller stride
   const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
   const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
-  kp.vec_a = vec_ok(a.A, akm ? a.sAm : a.sAk, a.sAk, a.sAr, a.sAz, VEC, akm);
-  kp.vec_b = vec_ok(a.B, bkn ? a.sBn : a.sBk, a.sBk, a.sBr, a.sBz, VEC, bkn);
+  kp.vec_a = vec_ok(akm ? a.sAm : a.sAk);
+  kp.vec_b = vec_ok(bkn ? a.sBn : a.sBk);
   const dim3 grid((unsigned)(kp.per_xcd * kXcd));
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   if (ex.prof && ex.prof->on) {

@@ -401,10 +401,12 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   G(J, b, V, O).A(lt + O, n2, 1, n).B(ct, O, n1, 1).C(Xk.p, b, 1).tag("ccs_Xk").run(x, p, o64);
   G(O, b, J, 1, V).A(lt + O * n, 1, n2, 0, n).B(Xk.p, b, 1).C(sigma, 1, ld, O, 2.0, 1.0)
       .tag("ccs_coul").run(x, p, true);
+  // W^K[vec][i][B] = sum_J c_BJ L~^K_Ji, stored with B innermost so that the
+  // reduction index of ccs_vv is contiguous
   W.ensure(al, (size_t)J * b * V * O * sizeof(T));
-  G(b * V, O, O, 1, J).A(ct, O, 1, 0, 0).B(lt, n, 1, 0, n2).C(W.p, O, 1, b * V * O)
-      .tag("ccs_W").run(x, p, o64);
-  G(V, b * O, V, J).A(lt + O * n + O, n, 1, n2).B(W.p, O, 1, b * V * O).Nhi(O, V * O, ld)
+  G(b * V, O, O, 1, J).A(ct, O, 1, 0, 0).Mhi(V, V * O, V * O).B(lt, n, 1, 0, n2)
+      .C(W.p, 1, V, b * V * O).tag("ccs_W").run(x, p, o64);
+  G(V, b * O, V, J).A(lt + O * n + O, n, 1, n2).B(W.p, 1, V, b * V * O).Nhi(O, V * O, ld)
       .C(sigma, O, 1, 0, -1.0, 1.0).tag("ccs_vv").run(x, p, true);
   if (!has_doubles()) return;
 
@@ -482,10 +484,20 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
 
 static constexpr int kMaxBatch = 8;
 
+// Trial vectors per batch: up to 8, fewer when the doubles scratch of a batch
+// (G in FP64, eliminated doubles in FP64, u(c2) in the operand type; M*M
+// each per vector) would pass 48 GB.
+int mlcc_problem::max_batch() const {
+  if (!has_doubles()) return kMaxBatch;
+  const double per = (double)d.M * (double)d.M * (16.0 + (double)tsize);
+  return (int)std::max(1.0, std::min((double)kMaxBatch, std::floor(48e9 / per)));
+}
+
 void mlcc_problem::transform(int nvec, const double *c, double *sigma) {
   const int64_t dm = dim();
-  for (int i0 = 0; i0 < nvec; i0 += kMaxBatch) {
-    const int nb = std::min(kMaxBatch, nvec - i0);
+  const int mb = max_batch();
+  for (int i0 = 0; i0 < nvec; i0 += mb) {
+    const int nb = std::min(mb, nvec - i0);
     if (prec == MLCC_FP64)
       transform_batch_t<double>(nb, c + i0 * dm, dm, has_doubles(), sigma + i0 * dm, NAN);
     else
@@ -494,8 +506,9 @@ void mlcc_problem::transform(int nvec, const double *c, double *sigma) {
 }
 
 void mlcc_problem::transform_eff(double w, int nvec, const double *c1, double *s1) {
-  for (int i0 = 0; i0 < nvec; i0 += kMaxBatch) {
-    const int nb = std::min(kMaxBatch, nvec - i0);
+  const int mb = max_batch();
+  for (int i0 = 0; i0 < nvec; i0 += mb) {
+    const int nb = std::min(mb, nvec - i0);
     if (prec == MLCC_FP64)
       transform_batch_t<double>(nb, c1 + i0 * d.n1, d.n1, false, s1 + i0 * d.n1, w);
     else

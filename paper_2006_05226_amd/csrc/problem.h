@@ -112,6 +112,7 @@ struct mlcc_problem {
 
   bool has_doubles() const { return model != MLCC_CCS && d.M > 0; }
   int64_t dim() const { return d.n1 + (has_doubles() ? d.M * d.M : 0); }
+  int max_batch() const;  // trial vectors per Jacobian batch
   double *t1() const { return amp.as<double>(); }
   double *x2() const { return amp.as<double>() + d.n1; }
 

@@ -14,6 +14,7 @@
 //   mlcc_poll reads.  The kernels and reductions are deterministic, so a
 //   request gives the same result alone and in a mix.
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -69,8 +70,9 @@ struct mlcc_server {
   void work(Lane *lane);
 };
 
-// Device bytes one request needs at its peak (inputs, X1-transformed vectors,
-// doubles arrays, Davidson subspace, batch scratch), with a 15% margin.
+// Device bytes one request needs at its peak, with a 15% margin: the larger
+// of the set-up peak (L, plus its FP64 staging copy in FP32 mode) and the
+// solve peak (L, L~, doubles arrays, batch scratch, Davidson subspace).
 extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n_roots,
                                            const mlcc_solver_opts *es) {
   if (!d || n_roots < 1) return 0;
@@ -81,24 +83,27 @@ extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n
   const double nL = J * n * n, n1 = O * V, MM = M * M;
   const bool eff = es && es->effective && d->model == MLCC_MLCC2;
   const double dim = n1 + ((dbl && !eff) ? MM : 0.0);
-  const double b = std::min(n_roots + 2, 8);
-  double bytes = 0.0;
-  bytes += nL * ts + nL * ts;                  // L and L~
-  if (ts == 4.0) bytes += nL * 8.0;            // FP64 staging of L at setup
-  bytes += 6.0 * n * n * 8.0;                  // h, h~, F~ and scratch
-  bytes += MM * (8.0 * 4 + ts * 2);            // amplitudes, residual, g~, G, u
-  bytes += MM * b * (ts + 8.0);                // batched u(c2), G
-  if (eff) bytes += MM * b * 8.0;              // eliminated doubles
-  bytes += J * M * ts * (3.0 + 2.0 * b);       // packed L_ai, Z, Zc, dL_ai
-  bytes += J * V * O * b * ts;                 // CCS intermediate
+  // the batch rule of the Jacobian transformation (at most 8 vectors, at most
+  // 48 GB of doubles scratch)
+  double bmax = 8.0;
+  if (dbl && MM > 0) bmax = std::max(1.0, std::min(8.0, std::floor(48e9 / (MM * (16.0 + ts)))));
+  const double b = std::min((double)n_roots + 2.0, bmax);
+  const double setup = nL * ts + (ts == 4.0 ? nL * 8.0 : 0.0) + 6.0 * n * n * 8.0;
+  double run = 2.0 * nL * ts;                 // L and L~
+  run += 6.0 * n * n * 8.0;                   // h, h~, F~ and scratch
+  run += MM * (8.0 * 4 + ts * 2);             // amplitudes, residual, g~, G, u
+  run += MM * b * (ts + 8.0);                 // batched u(c2), G
+  if (eff) run += MM * b * 8.0;               // eliminated doubles
+  run += J * M * ts * (3.0 + 2.0 * b);        // packed L_ai, Z, Zc, dL_ai
+  run += J * V * O * b * ts;                  // CCS intermediate
   const double space = es && es->max_subspace > 0 ? es->max_subspace : 20.0 * n_roots;
-  bytes += dim * 8.0 * (2.0 * space + 3.0 * (n_roots + 2));  // Davidson
-  bytes += 2.0 * 8.0 * (n1 + (d->model == MLCC_MLCCSD ? MM : 0.0)) * 8;  // DIIS
+  run += dim * 8.0 * (2.0 * space + 3.0 * (n_roots + 2));  // Davidson
+  run += 2.0 * 8.0 * (n1 + (d->model == MLCC_MLCCSD ? MM : 0.0)) * 8;  // DIIS
   if (d->model == MLCC_MLCCSD) {
     const double v = d->n_vir_act, o = d->n_occ_act;
-    bytes += (v * v * v * v + O * v * v * v + O * o * M) * ts + 16.0 * MM * ts;
+    run += (v * v * v * v + O * v * v * v + O * o * M) * ts + 16.0 * MM * ts;
   }
-  return (uint64_t)(bytes * 1.15) + (64ull << 20);
+  return (uint64_t)(std::max(setup, run) * 1.15) + (64ull << 20);
 }
 
 void mlcc_server::work(Lane *lane) {

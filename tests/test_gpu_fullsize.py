@@ -1,0 +1,105 @@
+"""Parity at the full benchmark sizes: ground-state energies and excitation
+energies against oracle reference values written by
+tests/golden/make_reference.py (FP64 oracle, same seeded inputs), and one
+Jacobian transformation at 40/400/1200 against the oracle computed here.
+
+Bars: FP64 1e-10 Eh; FP32 (mixed) 1e-6 Eh for energies and 1e-5 eV
+(3.67e-7 Eh) for excitation energies."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from oracle import mlcc as om  # noqa: E402
+from paper_2006_05226_amd import mlcc  # noqa: E402
+from paper_2006_05226_amd.synth import CONFIGS, gen_amplitudes, gen_inputs, gen_vectors  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+EV = 27.211386245988  # Hartree in eV (CODATA 2018)
+TOL = {"fp64": dict(e=1e-10, w=1e-10, gs=1e-10, es=1e-8),
+       "fp32": dict(e=1e-6, w=1e-5 / EV, gs=1e-6, es=1e-6)}
+
+
+def reference(name):
+    with open(os.path.join(GOLDEN, f"reference_{name}.json")) as f:
+        return json.load(f)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return mlcc.Context(0)
+
+
+_inputs = {}
+
+
+def inputs(name):
+    if name not in _inputs:
+        inp = gen_inputs(seed=0, **CONFIGS[name])
+        # the stored values belong to exactly these inputs
+        assert inp.digest() == reference(name)["inputs_sha256_16"]
+        _inputs[name] = inp
+    return _inputs[name]
+
+
+def solve(ctx, name, precision, effective=False):
+    ref = reference(name)
+    c = CONFIGS[name]
+    inp = inputs(name)
+    P = mlcc.Problem(ctx, inp.L, inp.eps, c["n_occ"], c["n_vir"], c["n_occ_act"], c["n_vir_act"],
+                     model=ref["model"], precision=precision)
+    t = TOL[precision]
+    gs = P.ground_state(tol=t["gs"])
+    dav = P.davidson(len(ref["omega"]), tol=t["es"], effective=effective)
+    P.close()
+    return ref, gs, dav
+
+
+@pytest.mark.parametrize("name", ["cc2_5_20_60", "mlcc2_40_400_1200"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_energies_and_roots(ctx, name, precision):
+    ref, gs, dav = solve(ctx, name, precision)
+    t = TOL[precision]
+    assert gs["converged"] and dav["converged"]
+    print(f"{name} {precision}: dE={gs['energy'] - ref['e_corr']:.2e} "
+          f"dw={np.abs(np.array(dav['omega']) - ref['omega']).max():.2e}")
+    assert abs(gs["energy"] - ref["e_corr"]) < t["e"]
+    assert np.abs(np.array(dav["omega"]) - ref["omega"]).max() < t["w"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_effective_singles_roots(ctx, precision):
+    """The effective-singles solver (used by the serving loop) reaches the
+    full-space oracle roots."""
+    ref, gs, dav = solve(ctx, "mlcc2_40_400_1200", precision, effective=True)
+    t = TOL[precision]
+    assert dav["converged"]
+    assert np.abs(np.array(dav["omega"]) - ref["omega"]).max() < max(t["w"], 1e-9)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 3e-5)])
+def test_jacobian_transform_fullsize(ctx, precision, tol):
+    """One trial vector at 40/400/1200 (active 15/150) through the launch
+    configuration the benchmark times (a batch of 4), against the oracle's
+    complex-step transformation of the first vector."""
+    name = "mlcc2_40_400_1200"
+    c = CONFIGS[name]
+    inp = inputs(name)
+    d = om.Dims(c["n_occ"], c["n_vir"], c["n_occ_act"], c["n_vir_act"])
+    t1, x2 = gen_amplitudes(d.O, d.V, d.o, d.v, seed=1, scale1=0.01, scale2=0.001)
+    c1, c2 = gen_vectors(4, d.O, d.V, d.M, seed=2)
+    P = mlcc.Problem(ctx, inp.L, inp.eps, d.O, d.V, d.o, d.v, precision=precision)
+    P.set_amplitudes(t1, x2.reshape(d.M, d.M))
+    cvec = np.concatenate([c1.reshape(4, -1), c2.reshape(4, -1)], axis=1)
+    sig = P.jacobian_transform(cvec)
+    P.close()
+    r1, r2 = om.jacobian_transform(om.Problem(inp.L, inp.eps, d, "mlcc2"), t1, x2, c1[0],
+                                   c2[0].reshape(d.v, d.o, d.v, d.o))
+    ref = np.concatenate([r1.ravel(), r2.ravel()])
+    err = np.linalg.norm(sig[0] - ref) / np.linalg.norm(ref)
+    print(f"{precision}: relative error {err:.2e}")
+    assert err < tol
