@@ -169,7 +169,9 @@ mlcc_status mlcc_ground_state(mlcc_problem *prob, const mlcc_solver_opts *opts,
 
 /* sigma = A c for n_vec vectors [n_vec][dim] (full space, Appendix A.2) at the
  * current amplitudes.  The transformation is the derivative of the Omega
- * vector; for MLCC2 the doubles-doubles block is eps_aibj (Sec. 2.1). */
+ * vector; for MLCC2 the doubles-doubles block is eps_aibj (Sec. 2.1).  The
+ * doubles block of each c must be symmetric (the doubles convention above);
+ * the result for a nonsymmetric block is unspecified. */
 mlcc_status mlcc_jacobian_transform(mlcc_problem *prob, int32_t n_vec, const double *c,
                                     double *sigma);
 

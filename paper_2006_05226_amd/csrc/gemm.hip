@@ -17,9 +17,11 @@ std::pair<hipEvent_t, hipEvent_t> Profiler::next() {
 void gemm(Exec &ex, Prec prec, const GemmArgs &a, bool out_f64) {
   if (a.M <= 0 || a.N <= 0 || a.Z <= 0) return;
   MLCC_REQUIRE(a.Z <= ((int64_t)1 << 24), MLCC_E_ARG, "gemm: batch count too large");
-  if (prec == Prec::F64) gemm_f64(ex, a);
-  else if (out_f64) gemm_f32_out64(ex, a);
-  else gemm_f32(ex, a);
+  GemmArgs b = a;
+  b.slack = ex.al && ex.al->owns(a.A) && ex.al->owns(a.B);
+  if (prec == Prec::F64) gemm_f64(ex, b);
+  else if (out_f64) gemm_f32_out64(ex, b);
+  else gemm_f32(ex, b);
 }
 
 }  // namespace mlcc

@@ -153,9 +153,10 @@ template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
   }
 
   // VONLY: the host has checked that every unit of every tile is a 16-byte
-  // group (unit stride, aligned, no group cut by the extent or by the
-  // two-level index); units outside the operand read the tile's first group
-  // and k beyond K is masked, so every load is unconditional.
+  // group (unit stride, no group cut by the two-level index, and any group
+  // that runs past the operand's end inside a library allocation); units
+  // outside the operand read the tile's first group and k beyond K is
+  // masked, so every load is unconditional.
   __device__ __forceinline__ void init_v(int tid, int64_t mn0, int64_t lo, int64_t s_mn,
                                          int64_t n_mn, int64_t s_hi) {
     const int64_t off0 = two_level(mn0, lo, s_mn, s_hi);
@@ -187,7 +188,7 @@ template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
       const T *src = KMAJ ? X + off[e] + kc * s_k : X + off[e] + kc;
       const v16 v = *reinterpret_cast<const v16 *>(src);
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) rg[e][q] = in ? v[q] : T(0);
+      for (int q = 0; q < VEC; ++q) rg[e][q] = (KMAJ ? in : k + q < K) ? v[q] : T(0);
     }
   }
 
@@ -484,21 +485,24 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // per unit in the kernel).
 inline bool vec_ok(int64_t s_fast) { return s_fast == 1; }
 
-// Every unit of one operand is a 16-byte group in range: unit stride along
-// the contiguous dimension and, for an m/n-contiguous operand, an extent and
-// two-level low extent that are multiples of the group; a k-contiguous
-// operand needs K a multiple of it.
+// Every unit of one operand is a 16-byte group: unit stride along the
+// contiguous dimension and no group cut by a two-level index.  A group may
+// run past the operand's last element (an m/n extent or K not a multiple of
+// the group) only when the operand lies in a library allocation, which has
+// spare bytes past its end: elements past K are masked, elements past M or N
+// reach only outputs that are never written.
 inline bool operand_vec(bool kmaj, int64_t s_mn, int64_t s_k, int64_t n_mn, int64_t K, int64_t lo,
-                        int vec) {
-  if (kmaj) return s_mn == 1 && n_mn % vec == 0 && (lo <= 0 || lo % vec == 0);
-  return s_k == 1 && K % vec == 0;
+                        int vec, bool slack) {
+  if (kmaj)
+    return s_mn == 1 && (lo <= 0 || lo % vec == 0) && (n_mn % vec == 0 || slack);
+  return s_k == 1 && (K % vec == 0 || slack);
 }
 
 inline bool gemm_vonly(const GemmArgs &a, int vec) {
   const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
   const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
-  return a.K > 0 && operand_vec(akm, a.sAm, a.sAk, a.M, a.K, a.Mlo, vec) &&
-         operand_vec(bkn, a.sBn, a.sBk, a.N, a.K, a.Nlo, vec);
+  return a.K > 0 && operand_vec(akm, a.sAm, a.sAk, a.M, a.K, a.Mlo, vec, a.slack) &&
+         operand_vec(bkn, a.sBn, a.sBk, a.N, a.K, a.Nlo, vec, a.slack);
 }
 
 template <typename T, typename TC, int BM, int BN, bool VONLY>

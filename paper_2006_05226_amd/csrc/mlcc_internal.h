@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <cstdio>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -37,13 +38,19 @@ struct Error {
 // ---------------------------------------------------------------------------
 // device memory accounting
 // ---------------------------------------------------------------------------
+// Device allocations of a context.  Every allocation has kSlack readable
+// bytes past its end, so a 16-byte load that runs past a row's last element
+// stays inside it; owns() tells whether a pointer lies in a live allocation.
+constexpr size_t kSlack = 256;
 struct Alloc {
   int device = 0;
   uint64_t budget = 0;  // 0: unlimited
   uint64_t used = 0;
   std::mutex mu;
+  std::map<uintptr_t, size_t> live;  // base -> requested bytes
   void *get(size_t bytes);
   void put(void *p, size_t bytes);
+  bool owns(const void *p);
 };
 
 // RAII device buffer accounted against an Alloc.
@@ -134,6 +141,8 @@ struct GemmArgs {
   // launch cover a batch of trial vectors stored back to back.
   int64_t Mlo = 0, sAm_hi = 0, sCm_hi = 0;
   int64_t Nlo = 0, sBn_hi = 0, sCn_hi = 0;
+  // set by gemm(): A and B lie in library allocations (kSlack bytes past the end)
+  bool slack = false;
 };
 
 // prec selects the operand type (double or float) and the MFMA; out_f64

@@ -21,29 +21,42 @@
 namespace mlcc {
 
 void *Alloc::get(size_t bytes) {
+  const size_t total = bytes + kSlack;
   {
     std::lock_guard<std::mutex> lk(mu);
-    if (budget && used + bytes > budget)
-      throw Error{MLCC_E_OOM, "HBM budget exceeded: need " + std::to_string(bytes) +
+    if (budget && used + total > budget)
+      throw Error{MLCC_E_OOM, "HBM budget exceeded: need " + std::to_string(total) +
                                   " bytes, " + std::to_string(budget - used) + " left"};
-    used += bytes;
+    used += total;
   }
   void *p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
+  hipError_t e = hipMalloc(&p, total);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     std::lock_guard<std::mutex> lk(mu);
-    used -= bytes;
+    used -= total;
     throw Error{e == hipErrorOutOfMemory ? MLCC_E_OOM : MLCC_E_DEVICE,
                 std::string("hipMalloc: ") + hipGetErrorString(e)};
   }
+  std::lock_guard<std::mutex> lk(mu);
+  live[reinterpret_cast<uintptr_t>(p)] = bytes;
   return p;
 }
 
 void Alloc::put(void *p, size_t bytes) {
   (void)hipFree(p);
   std::lock_guard<std::mutex> lk(mu);
-  used -= bytes;
+  live.erase(reinterpret_cast<uintptr_t>(p));
+  used -= bytes + kSlack;
+}
+
+bool Alloc::owns(const void *p) {
+  const uintptr_t a = reinterpret_cast<uintptr_t>(p);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = live.upper_bound(a);
+  if (it == live.begin()) return false;
+  --it;
+  return a < it->first + it->second;
 }
 
 }  // namespace mlcc
@@ -469,7 +482,9 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   Zc.ensure(al, (size_t)J * b * M * sizeof(T));
   for (int64_t vec = 0; vec < b; ++vec)
     k::u_of<T>(x, d.o, d.v, c2base + vec * c2ld, off<T>(ut, vec * M * M));
-  G(J, b * M, M).A(off<T>(Lvo0), M, 1).B(ut.p, M, 1).Nhi(M, M * M, M).C(Zc.p, b * M, 1)
+  // u(c2) is symmetric under (ai) <-> (bj) (so are the doubles), so it is
+  // read with the reduction index bj contiguous
+  G(J, b * M, M).A(off<T>(Lvo0), M, 1).B(ut.p, 1, M).Nhi(M, M * M, M).C(Zc.p, b * M, 1)
       .tag("Zc_uL").run(x, p, o64);
   G(V, b * o, v, J).A(lt + O * n + O, n, 1, n2).B(Zc.p, o, 1, b * M).Nhi(o, M, ld)
       .C(sigma, O, 1, 0, 1.0, 1.0).tag("d2s_A1").run(x, p, true);
