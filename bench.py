@@ -346,7 +346,7 @@ def main():
         extra[p]["contractions"] = {k: dict(ms_per_step=s["ms"] / args.steps,
                                             tflops=s["flops"] / max(s["ms"], 1e-9) / 1e9)
                                     for k, s in sorted(e["stats"].items(),
-                                                       key=lambda kv: -kv[1]["ms"])[:8]}
+                                                       key=lambda kv: -kv[1]["ms"])}
     if "fp32" in res and "fp64" in res:
         extra["speedup_fp32_vs_fp64"] = res["fp32"]["transforms_per_s"] / res["fp64"]["transforms_per_s"]
     if not args.no_mlccsd:

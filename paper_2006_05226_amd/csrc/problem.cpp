@@ -444,10 +444,12 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   // singles -> doubles: dL~_ai = sum_B L~_aB c_Bi - sum_J c_aJ L~_Ji  ([K][vec][ai]),
   // G[ai][vec, bj] = sum_K L~^K_ai dL~^K_bj
   dLai.ensure(al, (size_t)J * b * M * sizeof(T));
-  G(v, b * o, V, 1, J).A(lt + O * n + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).Nhi(o, n1, M)
-      .C(dLai.p, o, 1, b * M).tag("dLai").run(x, p, o64);
-  G(b * v, o, O, 1, J).A(ct, O, 1, 0, 0).Mhi(v, n1, M).B(lt, n, 1, 0, n2)
-      .C(dLai.p, o, 1, b * M, -1.0, 1.0).tag("dLai").run(x, p, o64);
+  // one launch per term: rows (K, a) x columns (vec, i), then rows (vec, a) x
+  // columns (K, i)
+  G(J * v, b * o, V).A(lt + O * n + O, n, 1).Mhi(v, n2, b * M).B(ct, O, 1).Nhi(o, n1, M)
+      .C(dLai.p, o, 1).tag("dLai").run(x, p, o64);
+  G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M).B(lt, n, 1).Nhi(o, n2, b * M)
+      .C(dLai.p, o, 1, 0, -1.0, 1.0).tag("dLai").run(x, p, o64);
   Gm.ensure(al, (size_t)M * b * M * sizeof(double));
   G(M, b * M, J).A(off<T>(Lai), 1, M).B(dLai.p, b * M, 1).C(Gm.p, b * M, 1)
       .tag("sigma2_LdL").run(x, p, true);
