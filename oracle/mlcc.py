@@ -33,6 +33,34 @@ import numpy as np
 _ES = dict(optimize=True)
 
 
+def _einsum(spec, *ops):
+    """numpy.einsum of the given expression, evaluated as a sequence of
+    pairwise products along numpy's optimal contraction path, each product by
+    torch.einsum on the CPU (batched BLAS) when torch is available.  Same
+    arithmetic as the expression up to rounding order; numpy's own fallback
+    for pairwise products that do not map onto BLAS is a single-threaded loop
+    that makes the larger parity cases impractical."""
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        return np.einsum(spec, *ops, **_ES)
+    lhs, out = spec.replace(" ", "").split("->")
+    subs = lhs.split(",")
+    path = np.einsum_path(spec, *ops, optimize="optimal")[0][1:]
+    dt = np.result_type(*ops)
+    terms = [(sb, torch.from_numpy(np.ascontiguousarray(op, dtype=dt))) for sb, op in zip(subs, ops)]
+    for pair in path:
+        pair = sorted(pair, reverse=True)
+        picked = [terms.pop(i) for i in pair]
+        rest = "".join(sb for sb, _ in terms) + out
+        idx = "".join(dict.fromkeys("".join(sb for sb, _ in picked)))
+        keep = "".join(c for c in idx if c in rest)
+        res = torch.einsum(",".join(sb for sb, _ in picked) + "->" + keep, *[t for _, t in picked])
+        terms.append((keep, res))
+    (sb, t), = terms
+    return torch.einsum(sb + "->" + out, t).numpy()
+
+
 @dataclass(frozen=True)
 class Dims:
     O: int  # all occupied
@@ -82,8 +110,8 @@ def two_electron_fock(L, d: Dims):
     electron part of the Fock expression in Appendix A)."""
     occ = d.occ
     dK = np.einsum("Kii->K", L[:, occ, occ])
-    coul = np.einsum("Kpq,K->pq", L, dK, **_ES)
-    exch = np.einsum("Kpi,Kiq->pq", L[:, :, occ], L[:, occ, :], **_ES)
+    coul = _einsum("Kpq,K->pq", L, dK)
+    exch = _einsum("Kpi,Kiq->pq", L[:, :, occ], L[:, occ, :])
     return 2.0 * coul - exch
 
 
@@ -168,7 +196,7 @@ def dress(L, eps, d: Dims, t1, h=None):
 def g_aibj(Lt, d: Dims):
     """g~_aibj = sum_K L~^K_ai L~^K_bj over the active space (v,o,v,o)."""
     Lai = Lt[:, d.avir, d.aocc]
-    return np.einsum("Kai,Kbj->aibj", Lai, Lai, **_ES)
+    return _einsum("Kai,Kbj->aibj", Lai, Lai)
 
 
 def omega_singles(D: Dressed, d: Dims, x2):
@@ -185,9 +213,9 @@ def omega_singles(D: Dressed, d: Dims, x2):
         return om
     u = u_of(x2)
     Ljc = Lt[:, d.aocc, d.avir]                          # L~_jc = L_jc (ov block)
-    om[:, : d.o] += np.einsum("bicj,Kjc,KAb->Ai", u, Ljc, Lt[:, d.vir, d.avir], **_ES)
-    om[: d.v, :] -= np.einsum("ajbk,Kkb,KjI->aI", u, Ljc, Lt[:, d.aocc, d.occ], **_ES)
-    om[: d.v, : d.o] += np.einsum("aibj,jb->ai", u, Ft[d.aocc, d.avir], **_ES)
+    om[:, : d.o] += _einsum("bicj,Kjc,KAb->Ai", u, Ljc, Lt[:, d.vir, d.avir])
+    om[: d.v, :] -= _einsum("ajbk,Kkb,KjI->aI", u, Ljc, Lt[:, d.aocc, d.occ])
+    om[: d.v, : d.o] += _einsum("aibj,jb->ai", u, Ft[d.aocc, d.avir])
     return om
 
 
@@ -225,7 +253,7 @@ def ccsd_doubles(D: Dressed, d: Dims, t2):
     Lt, Ft = D.Lt, D.Ft
     Lvo, Lov = _blk(Lt, d, "v", "o"), _blk(Lt, d, "o", "v")
     Loo, Lvv = _blk(Lt, d, "o", "o"), _blk(Lt, d, "v", "v")
-    E = lambda s, *ops: np.einsum(s, *ops, **_ES)  # noqa: E731
+    E = _einsum
 
     g_vovo = E("Kai,Kbj->aibj", Lvo, Lvo)   # g~_aibj
     g_oooo = E("Kki,Klj->kilj", Loo, Loo)   # g~_kilj
@@ -283,12 +311,12 @@ def correlation_energy(L, d: Dims, t1, x2):
     """E = sum t_AI t_BJ L_IAJB + sum_act x_aibj L_iajb,  L_pqrs = 2g_pqrs - g_psrq,
     with untransformed integrals."""
     Lov = L[:, d.occ, d.vir]  # L^K_IA
-    e = 2.0 * np.einsum("AI,BJ,KIA,KJB->", t1, t1, Lov, Lov, **_ES) \
-        - np.einsum("AI,BJ,KIB,KJA->", t1, t1, Lov, Lov, **_ES)
+    e = 2.0 * _einsum("AI,BJ,KIA,KJB->", t1, t1, Lov, Lov) \
+        - _einsum("AI,BJ,KIB,KJA->", t1, t1, Lov, Lov)
     if x2 is not None and d.M > 0:
         Lia = L[:, d.aocc, d.avir]
-        e = e + 2.0 * np.einsum("aibj,Kia,Kjb->", x2, Lia, Lia, **_ES) \
-            - np.einsum("aibj,Kib,Kja->", x2, Lia, Lia, **_ES)
+        e = e + 2.0 * _einsum("aibj,Kia,Kjb->", x2, Lia, Lia) \
+            - _einsum("aibj,Kib,Kja->", x2, Lia, Lia)
     return e
 
 
