@@ -125,20 +125,36 @@ __global__ void k_mlcc2_s_u(int o, int v, const TG *g, const double *eps_ai, dou
 }
 
 template <typename TU>
-__global__ void k_u_of(int o, int v, const double *x, TU *u) {
-  const int64_t M = (int64_t)o * v;
-  GRID_STRIDE(t, M * M) {
+__global__ void k_u_of(int o, int v, const double *x, TU *u, int nz, int64_t ldx, int64_t ldu) {
+  const int64_t M = (int64_t)o * v, MM = M * M;
+  GRID_STRIDE(tt, MM * nz) {
+    const int64_t z = tt / MM, t = tt - z * MM;
     const int64_t ai = t / M, bj = t - ai * M;
     const int64_t a = ai / o, i = ai - a * o, b = bj / o, j = bj - b * o;
-    u[t] = (TU)(2.0 * x[t] - x[(a * o + j) * M + (b * o + i)]);
+    const double *xz = x + z * ldx;
+    u[z * ldu + t] = (TU)(2.0 * xz[t] - xz[(a * o + j) * M + (b * o + i)]);
+  }
+}
+
+template <typename TS>
+__global__ void k_acc3d(int64_t nz, int64_t rows, int64_t cols, double alpha, const TS *src,
+                        int64_t s_z, int64_t s_r, double *dst, int64_t d_z, int64_t d_r) {
+  const int64_t per = rows * cols;
+  GRID_STRIDE(t, nz * per) {
+    const int64_t z = t / per, rc = t - z * per, r = rc / cols, c = rc - r * cols;
+    dst[z * d_z + r * d_r + c] += alpha * (double)src[z * s_z + r * s_r + c];
   }
 }
 
 // out = G + G^T + eps_aibj * c  through 32x32 LDS tiles (coalesced transpose)
 template <typename TG>
 __global__ void k_sym_plus_diag(int64_t M, const TG *G, int64_t ldg, const double *eps_ai,
-                                const double *c, double *out) {
+                                const double *c, double *out, int64_t sGz, int64_t ldc,
+                                int64_t ldo) {
   __shared__ double tile[32][33];
+  G += blockIdx.z * sGz;
+  if (c) c += blockIdx.z * ldc;
+  out += blockIdx.z * ldo;
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   // load G[c0.., r0..] transposed into tile
@@ -160,8 +176,10 @@ __global__ void k_sym_plus_diag(int64_t M, const TG *G, int64_t ldg, const doubl
 
 template <typename TG, typename TO>
 __global__ void k_sym_div(int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
-                          TO *out) {
+                          TO *out, int64_t sGz, int64_t ldo) {
   __shared__ double tile[32][33];
+  G += blockIdx.z * sGz;
+  out += blockIdx.z * ldo;
   const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int y = ty; y < 32; y += 8) {
@@ -386,30 +404,41 @@ void mlcc2_s_u(Exec &ex, int o, int v, const TG *g, const double *eps_ai, double
   MLCC_HIP(hipGetLastError());
 }
 
-template <typename TU> void u_of(Exec &ex, int o, int v, const double *x, TU *u) {
+template <typename TU>
+void u_of(Exec &ex, int o, int v, const double *x, TU *u, int nz, int64_t ldx, int64_t ldu) {
   const int64_t M = (int64_t)o * v;
-  if (M == 0) return;
-  hipLaunchKernelGGL((k_u_of<TU>), dim3(blocks_for(M * M)), dim3(TPB), 0, ex.stream, o, v, x, u);
+  if (M == 0 || nz <= 0) return;
+  hipLaunchKernelGGL((k_u_of<TU>), dim3(blocks_for(M * M * nz)), dim3(TPB), 0, ex.stream, o, v, x,
+                     u, nz, ldx, ldu);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TS>
+void acc3d(Exec &ex, int64_t nz, int64_t rows, int64_t cols, double alpha, const TS *src,
+           int64_t s_z, int64_t s_r, double *dst, int64_t d_z, int64_t d_r) {
+  if (nz <= 0 || rows <= 0 || cols <= 0) return;
+  hipLaunchKernelGGL((k_acc3d<TS>), dim3(blocks_for(nz * rows * cols)), dim3(TPB), 0, ex.stream,
+                     nz, rows, cols, alpha, src, s_z, s_r, dst, d_z, d_r);
   MLCC_HIP(hipGetLastError());
 }
 
 template <typename TG>
 void sym_plus_diag(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai,
-                   const double *c, double *out) {
-  if (M == 0) return;
-  dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32));
+                   const double *c, double *out, int nz, int64_t sGz, int64_t ldc, int64_t ldo) {
+  if (M == 0 || nz <= 0) return;
+  dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32), (unsigned)nz);
   hipLaunchKernelGGL((k_sym_plus_diag<TG>), grid, dim3(256), 0, ex.stream, M, G, ldg, eps_ai, c,
-                     out);
+                     out, sGz, ldc, ldo);
   MLCC_HIP(hipGetLastError());
 }
 
 template <typename TG, typename TO>
 void sym_div(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
-             TO *out) {
-  if (M == 0) return;
-  dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32));
+             TO *out, int nz, int64_t sGz, int64_t ldo) {
+  if (M == 0 || nz <= 0) return;
+  dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32), (unsigned)nz);
   hipLaunchKernelGGL((k_sym_div<TG, TO>), grid, dim3(256), 0, ex.stream, M, G, ldg, eps_ai, w,
-                     out);
+                     out, sGz, ldo);
   MLCC_HIP(hipGetLastError());
 }
 
@@ -510,16 +539,20 @@ template void mlcc2_s_u<double, double>(Exec &, int, int, const double *, const 
                                         double *);
 template void mlcc2_s_u<double, float>(Exec &, int, int, const double *, const double *, double *,
                                        float *);
-template void u_of<double>(Exec &, int, int, const double *, double *);
-template void u_of<float>(Exec &, int, int, const double *, float *);
+template void u_of<double>(Exec &, int, int, const double *, double *, int, int64_t, int64_t);
+template void u_of<float>(Exec &, int, int, const double *, float *, int, int64_t, int64_t);
+template void acc3d<double>(Exec &, int64_t, int64_t, int64_t, double, const double *, int64_t,
+                            int64_t, double *, int64_t, int64_t);
+template void acc3d<float>(Exec &, int64_t, int64_t, int64_t, double, const float *, int64_t,
+                           int64_t, double *, int64_t, int64_t);
 template void sym_plus_diag<double>(Exec &, int64_t, const double *, int64_t, const double *,
-                                    const double *, double *);
+                                    const double *, double *, int, int64_t, int64_t, int64_t);
 template void sym_plus_diag<float>(Exec &, int64_t, const float *, int64_t, const double *,
-                                   const double *, double *);
+                                   const double *, double *, int, int64_t, int64_t, int64_t);
 template void sym_div<double, double>(Exec &, int64_t, const double *, int64_t, const double *,
-                                      double, double *);
+                                      double, double *, int, int64_t, int64_t);
 template void sym_div<double, float>(Exec &, int64_t, const double *, int64_t, const double *,
-                                     double, float *);
+                                     double, float *, int, int64_t, int64_t);
 template void mlcc2_omega2<double>(Exec &, int64_t, const double *, const double *,
                                    const double *, double *);
 template void occ_trace<double>(Exec &, int64_t, int64_t, int, const double *, double *);

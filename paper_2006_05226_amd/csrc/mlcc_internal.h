@@ -177,17 +177,25 @@ void dot_mixed(Exec &ex, int64_t n, const TA *x, const TB *y, double *res);
 // MLCC2 doubles from g~: s = -g/eps_aibj (f64), u = 2s - s(i<->j) (TU)
 template <typename TG, typename TU>
 void mlcc2_s_u(Exec &ex, int o, int v, const TG *g, const double *eps_ai, double *s, TU *u);
-// u = 2x - x(i<->j) of a full doubles array (TU output), optional scale of x by 1
+// u = 2x - x(i<->j) of full doubles arrays (TU output); nz arrays, x[z] at
+// x + z*ldx and u[z] at u + z*ldu
 template <typename TU>
-void u_of(Exec &ex, int o, int v, const double *x, TU *u);
-// out = G + G^T + d .* c  (M x M, f64 out); G type TG
+void u_of(Exec &ex, int o, int v, const double *x, TU *u, int nz = 1, int64_t ldx = 0,
+          int64_t ldu = 0);
+// out = G + G^T + d .* c  (M x M, f64 out); G type TG; nz arrays with
+// G[z] at G + z*sGz, c[z] at c + z*ldc, out[z] at out + z*ldo
 template <typename TG>
 void sym_plus_diag(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai,
-                   const double *c, double *out);
-// x[ai][bj] /= (w - eps_aibj) after forming G + G^T  (effective singles)
+                   const double *c, double *out, int nz = 1, int64_t sGz = 0, int64_t ldc = 0,
+                   int64_t ldo = 0);
+// x[ai][bj] = (G + G^T)[ai][bj] / (w - eps_aibj)  (effective singles); nz arrays
 template <typename TG, typename TO>
 void sym_div(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
-             TO *out);
+             TO *out, int nz = 1, int64_t sGz = 0, int64_t ldo = 0);
+// dst[z*d_z + r*d_r + c] += alpha * src[z*s_z + r*s_r + c]
+template <typename TS>
+void acc3d(Exec &ex, int64_t nz, int64_t rows, int64_t cols, double alpha, const TS *src,
+           int64_t s_z, int64_t s_r, double *dst, int64_t d_z, int64_t d_r);
 // Delta t = -Omega / denominators
 void qn_step_singles(Exec &ex, int V, int O, const double *eps, const double *om, double *t);
 void qn_step_doubles(Exec &ex, int64_t M, const double *eps_ai, const double *om, double *t);

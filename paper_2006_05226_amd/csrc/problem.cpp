@@ -120,7 +120,9 @@ void mlcc_problem::setup_t(const double *Lsrc, bool dev, const uint64_t *synth_s
   }
   // packed active L_ai (= L_ia): Lvo0[K][a*o+i] = L^K[O+a][i]
   if (d.M > 0) {
-    Lvo0.alloc(al, (size_t)J * d.M * sizeof(T));
+    // one spare row after the J rows: the Jacobian puts F~_jb there, so that
+    // the u(c2) contraction with L_bj also yields sum_bj u_aibj F~_jb
+    Lvo0.alloc(al, (size_t)(J + 1) * d.M * sizeof(T));
     k::pack2d<T, T>(x, off<T>(Lvo0), off<T>(L, (int64_t)O * n), J, n2, d.v, d.o, n);
   }
   MLCC_HIP(hipStreamSynchronize(x.stream));
@@ -461,42 +463,38 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   if (has_c2) {
     c2base = c + n1;
     c2ld = ld;
-    for (int64_t vec = 0; vec < b; ++vec) {
-      double *s2 = sigma + vec * ld + n1;
-      if (model == MLCC_MLCC2)
-        k::sym_plus_diag<double>(x, M, Gm.as<double>() + vec * M, b * M, eps_ai.as<double>(),
-                                 c + vec * ld + n1, s2);
-      else
+    if (model == MLCC_MLCC2) {
+      k::sym_plus_diag<double>(x, M, Gm.as<double>(), b * M, eps_ai.as<double>(), c + n1,
+                               sigma + n1, (int)b, M, ld, ld);
+    } else {
+      for (int64_t vec = 0; vec < b; ++vec)
         ccsd_sigma2_t<T>(c + vec * ld, c + vec * ld + n1, Gm.as<double>() + vec * M, b * M,
-                         off<T>(dLai, vec * M), b * M, s2);
+                         off<T>(dLai, vec * M), b * M, sigma + vec * ld + n1);
     }
   } else if (std::isfinite(w_eff)) {
     c2e.ensure(al, (size_t)b * M * M * sizeof(double));
-    for (int64_t vec = 0; vec < b; ++vec)
-      k::sym_div<double, double>(x, M, Gm.as<double>() + vec * M, b * M, eps_ai.as<double>(),
-                                 w_eff, c2e.as<double>() + vec * M * M);
+    k::sym_div<double, double>(x, M, Gm.as<double>(), b * M, eps_ai.as<double>(), w_eff,
+                               c2e.as<double>(), (int)b, M, M * M);
     c2base = c2e.as<double>();
     c2ld = M * M;
   }
   if (!c2base) return;
   // doubles -> singles: the Omega_1 doubles terms with u = 2 c2 - c2(i<->j)
   ut.ensure(al, (size_t)b * M * M * sizeof(T));
-  Zc.ensure(al, (size_t)J * b * M * sizeof(T));
-  for (int64_t vec = 0; vec < b; ++vec)
-    k::u_of<T>(x, d.o, d.v, c2base + vec * c2ld, off<T>(ut, vec * M * M));
+  Zc.ensure(al, (size_t)(J + 1) * b * M * sizeof(T));
+  k::u_of<T>(x, d.o, d.v, c2base, off<T>(ut), (int)b, c2ld, M * M);
+  // F~_jb in the spare row J of L_vo: row J of Zc is sum_bj u_aibj F~_jb
+  k::pack2d_t<T, double>(x, off<T>(Lvo0, J * M), F + O, 1, 0, o, v, n);
   // u(c2) is symmetric under (ai) <-> (bj) (so are the doubles), so it is
   // read with the reduction index bj contiguous
-  G(J, b * M, M).A(off<T>(Lvo0), M, 1).B(ut.p, 1, M).Nhi(M, M * M, M).C(Zc.p, b * M, 1)
+  G(J + 1, b * M, M).A(off<T>(Lvo0), M, 1).B(ut.p, 1, M).Nhi(M, M * M, M).C(Zc.p, b * M, 1)
       .tag("Zc_uL").run(x, p, o64);
   G(V, b * o, v, J).A(lt + O * n + O, n, 1, n2).B(Zc.p, o, 1, b * M).Nhi(o, M, ld)
       .C(sigma, O, 1, 0, 1.0, 1.0).tag("d2s_A1").run(x, p, true);
   G(b * v, O, o, J).A(Zc.p, o, 1, b * M).Mhi(v, M, ld).B(lt, n, 1, n2)
       .C(sigma, O, 1, 0, -1.0, 1.0).tag("d2s_B1").run(x, p, true);
-  fvec.ensure(al, M * sizeof(T));
-  k::pack2d_t<T, double>(x, off<T>(fvec), F + O, 1, 0, o, v, n);
-  for (int64_t vec = 0; vec < b; ++vec)
-    G(o, 1, M, 1, v).A(off<T>(ut, vec * M * M), M, 1, 0, o * M).B(fvec.p, 1, 0)
-        .C(sigma + vec * ld, 1, 0, O, 1.0, 1.0).tag("d2s_C1").run(x, p, true);
+  // sigma_ai += sum_bj u_aibj F~_jb  (row J of Zc)
+  k::acc3d<T>(x, b, v, o, 1.0, off<T>(Zc, J * b * M), M, o, sigma, ld, O);
 }
 
 static constexpr int kMaxBatch = 8;
