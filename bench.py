@@ -39,7 +39,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 157.3}
 HBM_PEAK_GBS = 8000.0
 
 
@@ -165,6 +165,58 @@ def _mlccsd_leg(mlcc, steps, warmup, precisions, config="mlccsd_60_600_2000", nv
     return out
 
 
+def _c4_leg(mlcc, steps=3, nvec=5):
+    """MLCC2 at 150/1200/3600 (active 50/500), FP32 contractions, FP64
+    updates, effective-singles Davidson for 5 roots; device-drawn Cholesky
+    vectors.  g~ and the doubles live only in HBM (no host copies)."""
+    import torch
+    from paper_2006_05226_amd.synth import CONFIGS, gen_eps
+
+    c = CONFIGS["mlcc2_150_1200_3600"]
+    O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
+    eps = gen_eps(O, V, o, seed=0)
+    print("c4: setup", file=sys.stderr, flush=True)
+    ctx = mlcc.Context(0)
+    t0 = time.perf_counter()
+    P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlcc2", precision="fp32", n_chol=J, seed=0)
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gs = P.ground_state(tol=1e-6)
+    t_gs = time.perf_counter() - t0
+    c1 = torch.randn(nvec, O * V, dtype=torch.float64, device="cuda",
+                     generator=torch.Generator(device="cuda").manual_seed(0)) * 1e-2
+    s1 = torch.empty_like(c1)
+    P.jacobian_transform_eff(0.4, c1, s1)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.jacobian_transform_eff(0.4, c1, s1)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = ctx.profile_stats()
+    ctx.profile(False)
+    print("c4: davidson", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    dav = P.davidson(5, tol=1e-5, effective=True)
+    t_dav = time.perf_counter() - t0
+    peak = ctx.bytes()
+    P.close()
+    ctx.close()
+    del c1, s1
+    torch.cuda.empty_cache()
+    return {"workload": f"MLCC2 n_occ={O} n_vir={V} n_chol={J}, CC2 active {o}/{v}, FP32 "
+                        "contractions, effective-singles Davidson for 5 roots, device-drawn L",
+            "setup_seconds": t_setup, "gs_seconds": t_gs, "gs_iterations": gs["iterations"],
+            "e_corr": gs["energy"], "eff_transforms_per_s": steps * nvec / dt,
+            "davidson_seconds": t_dav, "davidson_transforms": dav["transforms"],
+            "omega": list(dav["omega"]), "davidson_converged": dav["converged"],
+            "hbm_bytes_allocated": peak,
+            "contractions": {k: dict(ms_per_step=st["ms"] / steps,
+                                     tflops=st["flops"] / max(st["ms"], 1e-9) / 1e9)
+                             for k, st in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:8]}}
+
+
 def _serving(mlcc, n_req, slots, precision="fp32", rate_frac=0.7, gs_tol=1e-6, es_tol=1e-5):
     import numpy as np
     from paper_2006_05226_amd.synth import gen_eps, serving_stream
@@ -250,8 +302,10 @@ def main():
     ap.add_argument("--config", default="mlcc2_40_400_1200")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true", help="skip the Davidson solve timing")
-    ap.add_argument("--precisions", default="fp64,fp32")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-mlccsd", action="store_true", help="skip the MLCCSD leg")
+    ap.add_argument("--c4", action="store_true",
+                    help="also run MLCC2 at 150/1200/3600 (active 50/500), ~1 minute")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy 3 times (reference for HBM counters)")
     ap.add_argument("--serve", type=int, default=64,
@@ -293,7 +347,7 @@ def main():
         ctx = mlcc.Context(0)
         P = mlcc.Problem(ctx, inp.L, inp.eps, O, V, o, v, model="mlcc2", precision=prec)
         t0 = time.perf_counter()
-        gs = P.ground_state(tol=1e-8)
+        gs = P.ground_state(tol=1e-8 if prec == "fp64" else 1e-6)
         t_gs = time.perf_counter() - t0
         cd = torch.tensor(cvec, device="cuda")
         sd = torch.empty_like(cd)
@@ -349,6 +403,15 @@ def main():
                                                        key=lambda kv: -kv[1]["ms"])}
     if "fp32" in res and "fp64" in res:
         extra["speedup_fp32_vs_fp64"] = res["fp32"]["transforms_per_s"] / res["fp64"]["transforms_per_s"]
+    for p in ("fp32", "bf16x3"):
+        if p in res and "fp64" in res:
+            extra[f"speedup_{p}_vs_fp64"] = res[p]["transforms_per_s"] / res["fp64"]["transforms_per_s"]
+            if "omega" in res[p] and "omega" in res["fp64"]:
+                extra[f"{p}_minus_fp64"] = dict(
+                    e_corr=res[p]["e_corr"] - res["fp64"]["e_corr"],
+                    omega=[a - b for a, b in zip(res[p]["omega"], res["fp64"]["omega"])])
+    if args.c4:
+        extra["c4"] = _c4_leg(mlcc)
     if not args.no_mlccsd:
         extra["mlccsd"] = _mlccsd_leg(mlcc, max(3, args.steps // 4), 1, precs)
     if args.serve > 0:

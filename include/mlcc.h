@@ -77,6 +77,11 @@ typedef int32_t mlcc_status;
  * and denominator updates, DIIS, Davidson and energies are FP64 always. */
 #define MLCC_FP64 0
 #define MLCC_FP32 1
+/* FP32 storage; the Cholesky-index contractions whose operands are
+ * contiguous along the reduction index run on the BF16 matrix cores as
+ * hi*hi + hi*lo + lo*hi (x = hi + lo, hi = bf16(x), lo = bf16(x - hi); FP32
+ * accumulation), the others on FP32 MFMA; FP64 elsewhere as for MLCC_FP32. */
+#define MLCC_BF16X3 2
 
 typedef struct mlcc_context mlcc_context;
 typedef struct mlcc_problem mlcc_problem;
@@ -86,7 +91,7 @@ typedef struct {
   int32_t n_occ, n_vir, n_chol;   /* N_o, N_v, N_J */
   int32_t n_occ_act, n_vir_act;   /* active prefixes (ignored for MLCC_CCS) */
   int32_t model;                  /* MLCC_CCS | MLCC_MLCC2 | MLCC_MLCCSD */
-  int32_t precision;              /* MLCC_FP64 | MLCC_FP32 */
+  int32_t precision;              /* MLCC_FP64 | MLCC_FP32 | MLCC_BF16X3 */
   const double *L;                /* [n_chol][n][n], symmetric in the last two */
   const double *eps;              /* [n] orbital energies in the order above */
   uint32_t flags;                 /* MLCC_SYNTH_L, or 0 */
@@ -233,7 +238,9 @@ uint64_t mlcc_request_footprint(const mlcc_problem_desc *desc, int32_t n_roots,
  *   C_z[m][n] = alpha * sum_{r<R} sum_{k<K} A_zr[m][k] B_zr[k][n] + beta * C_z[m][n]
  * with A_zr[m][k] at A + z*sA[3] + r*sA[2] + m*sA[0] + k*sA[1] and likewise
  * B (sB = {k, n, r, z}) and C (sC = {m, n, z}).  Device pointers only.
- * prec: MLCC_FP64 (FP64 MFMA) or MLCC_FP32 (A, B, C float; FP32 MFMA). */
+ * prec: MLCC_FP64 (FP64 MFMA), MLCC_FP32 (A, B, C float; FP32 MFMA) or
+ * MLCC_BF16X3 (A, B, C float; split BF16 products when A and B are both
+ * contiguous along k and laid out for 16-byte loads, FP32 MFMA otherwise). */
 mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int64_t K,
                       int64_t R, int64_t Z, double alpha, const void *A, const int64_t sA[4],
                       const void *B, const int64_t sB[4], double beta, void *C,

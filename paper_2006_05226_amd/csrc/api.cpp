@@ -95,8 +95,9 @@ void check_desc(const mlcc_problem_desc *d) {
                "n_occ, n_vir and n_chol must be >= 1");
   MLCC_REQUIRE(d->model == MLCC_CCS || d->model == MLCC_MLCC2 || d->model == MLCC_MLCCSD,
                MLCC_E_ARG, "unknown model");
-  MLCC_REQUIRE(d->precision == MLCC_FP64 || d->precision == MLCC_FP32, MLCC_E_ARG,
-               "unknown precision");
+  MLCC_REQUIRE(d->precision == MLCC_FP64 || d->precision == MLCC_FP32 ||
+                   d->precision == MLCC_BF16X3,
+               MLCC_E_ARG, "unknown precision");
   if (d->model != MLCC_CCS) {
     MLCC_REQUIRE(d->n_occ_act >= 0 && d->n_occ_act <= d->n_occ && d->n_vir_act >= 0 &&
                      d->n_vir_act <= d->n_vir,
@@ -467,7 +468,8 @@ mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int
                       const int64_t sB[4], double beta, void *C, const int64_t sC[3]) {
   if (!ctx) return MLCC_E_ARG;
   return guarded(ctx, [&]() -> mlcc_status {
-    MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32, MLCC_E_ARG, "bad precision");
+    MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32 || prec == MLCC_BF16X3, MLCC_E_ARG,
+                 "bad precision");
     MLCC_REQUIRE(M >= 0 && N >= 0 && K >= 0 && R >= 1 && Z >= 1, MLCC_E_ARG, "bad sizes");
     MLCC_REQUIRE(A && B && C && sA && sB && sC, MLCC_E_ARG, "NULL argument");
     MLCC_REQUIRE(is_device_ptr(A) && is_device_ptr(B) && is_device_ptr(C), MLCC_E_ARG,
@@ -479,7 +481,8 @@ mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int
     a.C = C; a.Cin = C; a.sCm = sC[0]; a.sCn = sC[1]; a.sCz = sC[2];
     a.alpha = alpha; a.beta = beta;
     MLCC_HIP(hipSetDevice(ctx->device));
-    gemm(ctx->ex, prec == MLCC_FP64 ? Prec::F64 : Prec::F32, a, prec == MLCC_FP64);
+    gemm(ctx->ex, prec == MLCC_FP64 ? Prec::F64 : prec == MLCC_FP32 ? Prec::F32 : Prec::BF16X3, a,
+         prec == MLCC_FP64);
     MLCC_HIP(hipStreamSynchronize(ctx->ex.stream));
     return MLCC_OK;
   });
@@ -491,7 +494,8 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
                        const int64_t sC[3], const int64_t lvl[6]) {
   if (!ctx) return MLCC_E_ARG;
   return guarded(ctx, [&]() -> mlcc_status {
-    MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32, MLCC_E_ARG, "bad precision");
+    MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32 || prec == MLCC_BF16X3, MLCC_E_ARG,
+                 "bad precision");
     MLCC_REQUIRE(M >= 0 && N >= 0 && K >= 0 && R >= 1 && Z >= 1, MLCC_E_ARG, "bad sizes");
     MLCC_REQUIRE(A && B && C && sA && sB && sC && lvl, MLCC_E_ARG, "NULL argument");
     MLCC_REQUIRE(lvl[0] >= 0 && lvl[3] >= 0, MLCC_E_ARG, "bad two-level sizes");
@@ -506,7 +510,8 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
     a.Mlo = lvl[0]; a.sAm_hi = lvl[1]; a.sCm_hi = lvl[2];
     a.Nlo = lvl[3]; a.sBn_hi = lvl[4]; a.sCn_hi = lvl[5];
     MLCC_HIP(hipSetDevice(ctx->device));
-    gemm(ctx->ex, prec == MLCC_FP64 ? Prec::F64 : Prec::F32, a, prec == MLCC_FP64);
+    gemm(ctx->ex, prec == MLCC_FP64 ? Prec::F64 : prec == MLCC_FP32 ? Prec::F32 : Prec::BF16X3, a,
+         prec == MLCC_FP64);
     MLCC_HIP(hipStreamSynchronize(ctx->ex.stream));
     return MLCC_OK;
   });
@@ -561,7 +566,7 @@ mlcc_status mlcc_debug_get(mlcc_problem *P, int32_t which, double *out) {
       MLCC_HIP(hipMemcpyAsync(out, tmp.p, n * 8, hipMemcpyDeviceToHost, ex.stream));
       MLCC_HIP(hipStreamSynchronize(ex.stream));
     };
-    const bool f32 = P->prec == MLCC_FP32;
+    const bool f32 = P->prec != MLCC_FP64;
     switch (which) {
       case 0: MLCC_REQUIRE(P->Ft.p, MLCC_E_STATE, "no state"); get(P->Ft.p, n2, false); break;
       case 1: MLCC_REQUIRE(P->Lt.p, MLCC_E_STATE, "no state"); get(P->Lt.p, J * n2, f32); break;

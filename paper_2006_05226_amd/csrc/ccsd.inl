@@ -55,7 +55,7 @@ template <typename T> void mlcc_problem::ccsd_integrals_t() {
   if (!cc) cc = new CcsdState();
   CcsdState &s = *cc;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, o = d.o, v = d.v, M = d.M;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;
   const T *lt = off<T>(Lt);
   s.Loo.ensure(al, J * o * o * sizeof(T));
@@ -103,7 +103,7 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
   Alloc *al = &ctx->al;
   CcsdState &s = *cc;
   const int64_t o = d.o, v = d.v, M = d.M;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;
   if (!blk[CB_OVOV]) incQ = false;
   const bool any = incB || incQ;
@@ -226,7 +226,7 @@ template <typename T> void mlcc_problem::ccsd_prepare_t() {
   Alloc *al = &ctx->al;
   CcsdState &s = *cc;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, o = d.o, v = d.v, M = d.M;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;
   s.LKc.ensure(al, J * O * v * sizeof(T));
   k::pack2d<T, T>(x, off<T>(s.LKc), off<T>(Lt, O), J, n2, O, v, n);
@@ -247,7 +247,7 @@ void mlcc_problem::ccsd_sigma2_t(const double *c1, const double *c2, const doubl
   CcsdState &s = *cc;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
   const int64_t n1 = d.n1;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;
   const T *lt = off<T>(Lt);
   const double *F = Ft.as<double>();

@@ -286,6 +286,60 @@ template <> struct OutMap<double> {
   }
 };
 
+// Write a block's accumulators: alpha * acc + beta * Cin into C, or the raw
+// partial sums into the split workspace.
+template <typename T, typename TC, int FM, int FN, int WTM, int WTN, typename Acc4>
+__device__ __forceinline__ void epilogue(const KParams &kp, const Acc4 (&acc)[FM][FN], int64_t m0,
+                                         int64_t n0, int64_t z, int split, int lane, int wm,
+                                         int wn) {
+  typedef typename std::conditional<sizeof(T) == 8, double, float>::type acc_t;
+  const GemmArgs &p = kp.a;
+  int64_t coff[FN][4];
+  bool cok[FN][4];
+#pragma unroll
+  for (int j = 0; j < FN; ++j)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T>::col(lane, e);
+      cok[j][e] = col < p.N;
+      coff[j][e] = cok[j][e] ? two_level(col, p.Nlo, p.sCn, p.sCn_hi) : 0;
+    }
+  if (kp.splits == 1) {
+    TC *C = static_cast<TC *>(p.C) + z * p.sCz;
+    const TC *Cin = static_cast<const TC *>(p.Cin) + z * p.sCz;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T>::row(lane, e);
+        if (row >= p.M) continue;
+        const int64_t roff = two_level(row, p.Mlo, p.sCm, p.sCm_hi);
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          if (!cok[j][e]) continue;
+          const int64_t o = roff + coff[j][e];
+          double out = p.alpha * (double)acc[i][j][e];
+          if (p.beta != 0.0) out += p.beta * (double)Cin[o];
+          C[o] = (TC)out;
+        }
+      }
+  } else {
+    acc_t *wk = static_cast<acc_t *>(kp.work) + (((int64_t)split * p.Z + z) * p.M) * p.N;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T>::row(lane, e);
+        if (row >= p.M) continue;
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+          const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T>::col(lane, e);
+          if (col < p.N) wk[row * p.N + col] = acc[i][j][e];
+        }
+      }
+  }
+}
+
 template <typename T, typename TC, int BM, int BN, bool AKM, bool BKN, bool VONLY>
 __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
   constexpr int S = Tr<T>::S, VEC = Tr<T>::VEC;
@@ -411,51 +465,135 @@ __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
     cur ^= 1;
   }
 
-  // epilogue
-  int64_t coff[FN][4];
-  bool cok[FN][4];
+  epilogue<T, TC, FM, FN, WTM, WTN>(kp, acc, m0, n0, z, split, lane, wm, wn);
+}
+
+
+// FP32 operands on the BF16 matrix cores: each element x is split into
+// hi = bf16(x) and lo = bf16(x - hi) when it is staged, and a fragment
+// product is hi*hi + hi*lo + lo*hi (three v_mfma_f32_16x16x32_bf16, FP32
+// accumulation; the dropped lo*lo term is below 2^-16 of the product).
+// Both operands k-contiguous, vector-only loads.  Lane l of the bf16 MFMA
+// holds A[l%16][8*(l/16) + e] and B[8*(l/16) + e][l%16], e < 8 (measured), so
+// a lane's fragment is one 16-byte read of a [m][k] LDS row.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
+
+template <typename TC, int BM, int BN>
+__global__ __launch_bounds__(kThreads) void k_gemm_split(KParams kp) {
+  constexpr int BK = Tr<float>::BK, VEC = Tr<float>::VEC, LEN = BK + 8;  // 80-byte rows
+  constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
+  static_assert(FM * 32 == BM && FN * 32 == BN && BK == 32 && VEC == 4, "tile");
+  typedef Stage<float, BM, false, true> SA;
+  typedef Stage<float, BN, false, true> SB;
+  __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][LEN];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][LEN];
+  __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][LEN];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN][LEN];
+
+  const GemmArgs &p = kp.a;
+  const int64_t L = blockIdx.x;
+  const int64_t w = (L % kXcd) * kp.per_xcd + L / kXcd;
+  if (w >= kp.nwork) return;
+  const int64_t tn = w % kp.tiles_n;
+  const int64_t t2 = w / kp.tiles_n;
+  const int64_t tm = t2 % kp.tiles_m;
+  const int64_t zs = t2 / kp.tiles_m;
+  const int64_t z = zs / kp.splits;
+  const int split = (int)(zs % kp.splits);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1, g = lane >> 4, l16 = lane & 15;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t total = p.R * kp.ktiles;
+  const int64_t s_begin = split * kp.steps_per_split;
+  const int64_t s_end = min(total, s_begin + kp.steps_per_split);
+  const float *Az = static_cast<const float *>(p.A) + z * p.sAz;
+  const float *Bz = static_cast<const float *>(p.B) + z * p.sBz;
+
+  SA sa;
+  SB sb;
+  sa.init_v(tid, m0, p.Mlo, p.sAm, p.M, p.sAm_hi);
+  sb.init_v(tid, n0, p.Nlo, p.sBn, p.N, p.sBn_hi);
+
+  f4 acc[FM][FN];
 #pragma unroll
-  for (int j = 0; j < FN; ++j)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T>::col(lane, e);
-      cok[j][e] = col < p.N;
-      coff[j][e] = cok[j][e] ? two_level(col, p.Nlo, p.sCn, p.sCn_hi) : 0;
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  float ra[SA::U][VEC], rb[SB::U][VEC];
+  int64_t lr = s_begin / kp.ktiles;
+  int64_t lk0 = (s_begin - lr * kp.ktiles) * BK;
+  auto load_next = [&]() {
+    sa.load_v(ra, Az + lr * p.sAr, lk0, p.K, p.sAk);
+    sb.load_v(rb, Bz + lr * p.sBr, lk0, p.K, p.sBk);
+    lk0 += BK;
+    if (lk0 >= kp.ktiles * BK) {
+      lk0 = 0;
+      ++lr;
     }
-  if (kp.splits == 1) {
-    TC *C = static_cast<TC *>(p.C) + z * p.sCz;
-    const TC *Cin = static_cast<const TC *>(p.Cin) + z * p.sCz;
+  };
+  auto split_store = [](const float (&x)[VEC], __bf16 *hi, __bf16 *lo) {
+    bf4v h, l;
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int q = 0; q < VEC; ++q) {
+      h[q] = (__bf16)x[q];
+      l[q] = (__bf16)(x[q] - (float)h[q]);
+    }
+    *reinterpret_cast<bf4v *>(hi) = h;
+    *reinterpret_cast<bf4v *>(lo) = l;
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T>::row(lane, e);
-        if (row >= p.M) continue;
-        const int64_t roff = two_level(row, p.Mlo, p.sCm, p.sCm_hi);
+    for (int e = 0; e < SA::U; ++e)
+      split_store(ra[e], &Ah[buf][sa.row[e]][sa.col[e]], &Al[buf][sa.row[e]][sa.col[e]]);
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          if (!cok[j][e]) continue;
-          const int64_t o = roff + coff[j][e];
-          double out = p.alpha * (double)acc[i][j][e];
-          if (p.beta != 0.0) out += p.beta * (double)Cin[o];
-          C[o] = (TC)out;
-        }
-      }
-  } else {
-    acc_t *wk = static_cast<acc_t *>(kp.work) + (((int64_t)split * p.Z + z) * p.M) * p.N;
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T>::row(lane, e);
-        if (row >= p.M) continue;
-#pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T>::col(lane, e);
-          if (col < p.N) wk[row * p.N + col] = acc[i][j][e];
-        }
-      }
+    for (int e = 0; e < SB::U; ++e)
+      split_store(rb[e], &Bh[buf][sb.row[e]][sb.col[e]], &Bl[buf][sb.row[e]][sb.col[e]]);
+  };
+
+  int cur = 0;
+  if (s_begin < s_end) {
+    load_next();
+    store(0);
   }
+  __syncthreads();
+  for (int64_t step = s_begin; step < s_end; ++step) {
+    const bool more = step + 1 < s_end;
+    if (more) load_next();
+    bf8v ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int r = wm * WTM + i * 16 + l16;
+      ah[i] = *reinterpret_cast<const bf8v *>(&Ah[cur][r][g * 8]);
+      al[i] = *reinterpret_cast<const bf8v *>(&Al[cur][r][g * 8]);
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int r = wn * WTN + j * 16 + l16;
+      bh[j] = *reinterpret_cast<const bf8v *>(&Bh[cur][r][g * 8]);
+      bl[j] = *reinterpret_cast<const bf8v *>(&Bl[cur][r][g * 8]);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+    if (more) store(cur ^ 1);
+    __syncthreads();
+    cur ^= 1;
+  }
+  epilogue<float, TC, FM, FN, WTM, WTN>(kp, acc, m0, n0, z, split, lane, wm, wn);
 }
 
 template <typename TA, typename TC>
@@ -505,7 +643,14 @@ inline bool gemm_vonly(const GemmArgs &a, int vec) {
          operand_vec(bkn, a.sBn, a.sBk, a.N, a.K, a.Nlo, vec, a.slack);
 }
 
-template <typename T, typename TC, int BM, int BN, bool VONLY>
+// The split BF16 kernel: vector-only operands that are both k-contiguous.
+inline bool gemm_split_ok(const GemmArgs &a) {
+  const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
+  const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
+  return a.bf16x3 && !akm && !bkn && gemm_vonly(a, Tr<float>::VEC);
+}
+
+template <typename T, typename TC, int BM, int BN, bool VONLY, bool SPLIT = false>
 void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   constexpr int BK = Tr<T>::BK, VEC = Tr<T>::VEC;
   KParams kp;
@@ -533,7 +678,11 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
     ev = ex.prof->next();
     MLCC_HIP(hipEventRecord(ev.first, ex.stream));
   }
-  if (akm && bkn)
+  if constexpr (SPLIT) {
+    static_assert(sizeof(T) == 4, "split products take FP32 operands");
+    MLCC_REQUIRE(!akm && !bkn, MLCC_E_ARG, "gemm: split products need k-contiguous operands");
+    hipLaunchKernelGGL((k_gemm_split<TC, BM, BN>), grid, dim3(kThreads), 0, ex.stream, kp);
+  } else if (akm && bkn)
     hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, true, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
   else if (akm)
     hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, false, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
@@ -560,6 +709,9 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
 #define MLCC_GEMM_TILES_GENERAL(X) \
   X(128, 128) X(128, 64) X(64, 128) X(64, 64) X(128, 32) X(32, 128) X(64, 32) X(32, 64) X(32, 32) \
   X(96, 160)
+#define MLCC_GEMM_TILES_SPLIT(X) \
+  X(128, 128) X(128, 96) X(96, 128) X(128, 64) X(64, 128) X(96, 96) X(64, 64) X(128, 32) X(32, 128) \
+  X(64, 32) X(32, 64) X(32, 32) X(96, 160) X(160, 96)
 #define MLCC_GEMM_TILES(X) \
   X(128, 128) X(128, 96) X(96, 128) X(128, 64) X(64, 128) X(96, 96) X(96, 64) X(64, 96) \
   X(64, 64) X(128, 32) X(32, 128) X(96, 32) X(32, 96) X(64, 32) X(32, 64) X(32, 32)    \

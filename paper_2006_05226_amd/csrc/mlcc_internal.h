@@ -121,7 +121,10 @@ struct Exec {
 // ---------------------------------------------------------------------------
 // GEMM engine (gemm.hip)
 // ---------------------------------------------------------------------------
-enum class Prec : int { F64 = 0, F32 = 1 };
+// F32: FP32 operands on FP32 MFMA; BF16X3: FP32 operands on the BF16 matrix
+// cores as hi*hi + hi*lo + lo*hi where the operand layout allows it, FP32
+// MFMA elsewhere.
+enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2 };
 
 struct GemmArgs {
   int64_t M = 0, N = 0, K = 0, R = 1, Z = 1;
@@ -143,6 +146,8 @@ struct GemmArgs {
   int64_t Nlo = 0, sBn_hi = 0, sCn_hi = 0;
   // set by gemm(): A and B lie in library allocations (kSlack bytes past the end)
   bool slack = false;
+  // set by gemm(): FP32 operands may run on the BF16 matrix cores (split products)
+  bool bf16x3 = false;
 };
 
 // prec selects the operand type (double or float) and the MFMA; out_f64

@@ -2,7 +2,7 @@
 // transformation, each written as a sequence of GEMM-engine calls and a few
 // element-wise kernels (Sec. 2.1 and Appendix A of Folkestad et al.).
 //
-// Operand type T is double (MLCC_FP64) or float (MLCC_FP32) for everything
+// Operand type T is double (MLCC_FP64) or float (MLCC_FP32, MLCC_BF16X3) for everything
 // contracted over Cholesky vectors; Fock matrices, amplitudes, residuals,
 // transformed vectors and energies are FP64.
 //
@@ -208,9 +208,8 @@ void mlcc_problem::setup(const mlcc_problem_desc &desc) {
 // ---------------------------------------------------------------------------
 namespace {
 template <typename T>
-void x1_blocks(Exec &x, const Dims &d, const T *src, T *dst, int64_t Z, const T *t) {
+void x1_blocks(Exec &x, Prec p, const Dims &d, const T *src, T *dst, int64_t Z, const T *t) {
   const int64_t n = d.n, n2 = d.n2, O = d.O, V = d.V;
-  const Prec p = prec_of<T>();
   const bool o64 = sizeof(T) == 8;
   // ov copy: C = 1 * Cin with an empty reduction
   G(O, V, 0, 1, Z).C(dst + O, n, 1, n2, 0.0, 1.0, src + O).run(x, p, o64);
@@ -229,14 +228,14 @@ template <typename T> void mlcc_problem::dress_t(bool full_fock) {
   Exec &x = *ex;
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   t1T.ensure(al, d.n1 * sizeof(T));
   if (sizeof(T) == 8) MLCC_HIP(hipMemcpyAsync(t1T.p, t1(), d.n1 * 8, hipMemcpyDeviceToDevice, x.stream));
   else k::convert<float, double>(x, t1T.as<float>(), t1(), d.n1);
   Lt.ensure(al, (size_t)J * n2 * sizeof(T));
-  x1_blocks<T>(x, d, off<T>(L), off<T>(Lt), J, off<T>(t1T));
+  x1_blocks<T>(x, gemm_prec<T>(), d, off<T>(L), off<T>(Lt), J, off<T>(t1T));
   ht.ensure(al, n2 * sizeof(double));
-  x1_blocks<double>(x, d, h.as<double>(), ht.as<double>(), 1, t1());
+  x1_blocks<double>(x, Prec::F64, d, h.as<double>(), ht.as<double>(), 1, t1());
   // F~ = h~ + 2 sum_K L~^K d~^K - sum_{K,I} L~^K_pI L~^K_Iq
   Ft.ensure(al, n2 * sizeof(double));
   MLCC_HIP(hipMemcpyAsync(Ft.p, ht.p, n2 * sizeof(double), hipMemcpyDeviceToDevice, x.stream));
@@ -273,7 +272,7 @@ template <typename T> void mlcc_problem::doubles_mlcc2_t() {
   Exec &x = *ex;
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, M = d.M;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   Lai.ensure(al, (size_t)J * M * sizeof(T));
   k::pack2d<T, T>(x, off<T>(Lai), off<T>(Lt, O * n), J, n2, d.v, d.o, n);
   u.ensure(al, (size_t)M * M * sizeof(T));
@@ -301,7 +300,7 @@ void mlcc_problem::omega_singles_t(const void *Zb, const void *ub, double *om1, 
   Exec &x = *ex;
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   if (add_fock) k::pack2d<double, double>(x, om1, Ft.as<double>() + O * n, 1, 0, V, O, n);
   if (M == 0 || Zb == nullptr) return;
   const T *lt = off<T>(Lt);
@@ -370,7 +369,7 @@ template <typename T> void mlcc_problem::prepare_jacobian_t() {
   Exec &x = *ex;
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   compute_state_t<T>(true);
   if (has_doubles()) {
     Xint.ensure(al, O * o * sizeof(T));
@@ -399,7 +398,7 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
   const int64_t n1 = d.n1, b = nb;
-  const Prec p = prec_of<T>();
+  const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;
   const T *lt = off<T>(Lt);
   const double *F = Ft.as<double>();

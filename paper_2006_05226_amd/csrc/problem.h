@@ -113,6 +113,12 @@ struct mlcc_problem {
   bool has_doubles() const { return model != MLCC_CCS && d.M > 0; }
   int64_t dim() const { return d.n1 + (has_doubles() ? d.M * d.M : 0); }
   int max_batch() const;  // trial vectors per Jacobian batch
+  // contraction precision for operand type T (FP32 storage may run split
+  // BF16 products)
+  template <typename T> mlcc::Prec gemm_prec() const {
+    return sizeof(T) == 8 ? mlcc::Prec::F64
+                          : (prec == MLCC_BF16X3 ? mlcc::Prec::BF16X3 : mlcc::Prec::F32);
+  }
   double *t1() const { return amp.as<double>(); }
   double *x2() const { return amp.as<double>() + d.n1; }
 

@@ -21,7 +21,8 @@ E_ARG, E_OOM, E_NOCONV, E_NUMERIC, E_DEVICE, E_BUSY, E_STATE = -1, -2, -3, -4, -
 CCS, MLCC2, MLCCSD = 0, 1, 2
 FP64, FP32 = 0, 1
 MODEL = {"ccs": CCS, "mlcc2": MLCC2, "mlccsd": MLCCSD}
-PREC = {"fp64": FP64, "fp32": FP32}
+BF16X3 = 2
+PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 
 _STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_ARG", -2: "E_OOM", -3: "E_NOCONV",
                  -4: "E_NUMERIC", -5: "E_DEVICE", -6: "E_BUSY", -7: "E_STATE"}

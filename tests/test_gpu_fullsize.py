@@ -3,8 +3,8 @@ energies against oracle reference values written by
 tests/golden/make_reference.py (FP64 oracle, same seeded inputs), and one
 Jacobian transformation at 40/400/1200 against the oracle computed here.
 
-Bars: FP64 1e-10 Eh; FP32 (mixed) 1e-6 Eh for energies and 1e-5 eV
-(3.67e-7 Eh) for excitation energies."""
+Bars: FP64 1e-10 Eh; FP32 and split-BF16 (mixed) 1e-6 Eh for energies and
+1e-5 eV (3.67e-7 Eh) for excitation energies."""
 import json
 import os
 
@@ -21,7 +21,8 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 EV = 27.211386245988  # Hartree in eV (CODATA 2018)
 TOL = {"fp64": dict(e=1e-10, w=1e-10, gs=1e-10, es=1e-8),
-       "fp32": dict(e=1e-6, w=1e-5 / EV, gs=1e-6, es=1e-6)}
+       "fp32": dict(e=1e-6, w=1e-5 / EV, gs=1e-6, es=1e-6),
+       "bf16x3": dict(e=1e-6, w=1e-5 / EV, gs=1e-6, es=1e-6)}
 
 
 def reference(name):
@@ -60,7 +61,7 @@ def solve(ctx, name, precision, effective=False):
 
 
 @pytest.mark.parametrize("name", ["cc2_5_20_60", "mlcc2_40_400_1200"])
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_energies_and_roots(ctx, name, precision):
     ref, gs, dav = solve(ctx, name, precision)
     t = TOL[precision]
@@ -81,7 +82,7 @@ def test_effective_singles_roots(ctx, precision):
     assert np.abs(np.array(dav["omega"]) - ref["omega"]).max() < max(t["w"], 1e-9)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 3e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 3e-5), ("bf16x3", 5e-4)])
 def test_jacobian_transform_fullsize(ctx, precision, tol):
     """One trial vector at 40/400/1200 (active 15/150) through the launch
     configuration the benchmark times (a batch of 4), against the oracle's

@@ -31,6 +31,8 @@ CASES = [
     (37, 45, 19, 1, 1, "k", "n"),
     (130, 129, 70, 1, 1, "m", "n"),
     (300, 260, 200, 1, 1, "k", "k"),
+    (200, 130, 64, 3, 2, "k", "k"),       # batched and batch-reduced, both k-contiguous
+    (64, 64, 4096, 1, 1, "k", "k"),       # long reduction -> split, both k-contiguous
     (64, 64, 64, 1, 1, "m", "k"),
     (17, 3, 5, 40, 1, "k", "n"),        # batch-reduce with tiny tiles -> split
     (40, 15, 150, 12, 1, "k", "n"),
@@ -47,7 +49,13 @@ def strides(layout, rows, cols):
     return (cols, 1) if layout in ("k",) else (1, rows)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+# per-element error bound, in units of sqrt(K*R) + 1 (unit-variance inputs):
+# FP32 rounding, and for split BF16 products the ~2^-16 error of hi*hi +
+# hi*lo + lo*hi
+TOL = {"fp64": 1e-13, "fp32": 3e-6, "bf16x3": 4e-5}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("case", CASES)
 def test_gemm(ctx, prec, case):
     M, N, K, R, Z, al, bl = case
@@ -64,12 +72,18 @@ def test_gemm(ctx, prec, case):
     dt = torch.float64 if prec == "fp64" else torch.float32
     Ad = torch.tensor(A, dtype=dt, device="cuda")
     Bd = torch.tensor(B, dtype=dt, device="cuda")
-    Cd = torch.tensor(C0, dtype=torch.float64 if prec == "fp64" else torch.float32, device="cuda")
-    ctx.gemm(mlcc.PREC[prec], M, N, K, R, Z, 0.7, Ad, sA, Bd, sB, -0.3, Cd, [N, 1, M * N])
-    got = Cd.cpu().numpy().astype(np.float64).reshape(Z, M, N)
+
+    def run(p):
+        Cd = torch.tensor(C0, dtype=dt, device="cuda")
+        ctx.gemm(mlcc.PREC[p], M, N, K, R, Z, 0.7, Ad, sA, Bd, sB, -0.3, Cd, [N, 1, M * N])
+        return Cd.cpu().numpy().astype(np.float64).reshape(Z, M, N)
+
+    got = run(prec)
     scale = np.sqrt(K * R) * 1.0 + 1.0
-    tol = 1e-13 if prec == "fp64" else 3e-6
-    assert np.abs(got - ref).max() <= tol * scale, np.abs(got - ref).max()
+    assert np.abs(got - ref).max() <= TOL[prec] * scale, np.abs(got - ref).max()
+    if prec == "bf16x3" and al == "k" and bl == "k" and K % 4 == 0 and K * R >= 64:
+        # both operands k-contiguous: the split BF16 kernel ran, not FP32 MFMA
+        assert np.abs(got - run("fp32")).max() > 0
 
 
 def test_gemm_rejects_host_pointers(ctx):
@@ -137,7 +151,7 @@ MISALIGNED = [
 ]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("case", MISALIGNED)
 def test_gemm_vector_fallbacks(ctx, prec, case):
     """Operands whose base, stride or extent rule out 16-byte loads take the
@@ -157,8 +171,7 @@ def test_gemm_vector_fallbacks(ctx, prec, case):
     Cd = torch.zeros(M * N, dtype=dt, device="cuda")
     ctx.gemm(mlcc.PREC[prec], M, N, K, R, 1, 1.0, Ad, sA, Bd, sB, 0.0, Cd, [N, 1, 0])
     got = Cd.cpu().numpy().astype(np.float64).reshape(M, N)
-    tol = 1e-13 if prec == "fp64" else 3e-6
-    assert np.abs(got - ref).max() <= tol * (np.sqrt(K * R) + 1.0)
+    assert np.abs(got - ref).max() <= TOL[prec] * (np.sqrt(K * R) + 1.0)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
