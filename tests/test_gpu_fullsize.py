@@ -1,5 +1,6 @@
-"""Parity at the full benchmark sizes: ground-state energies and excitation
-energies against oracle reference values written by
+"""Parity at the full benchmark sizes (CC2 5/20/60, MLCC2 40/400/1200 with
+15/150 active, MLCCSD 60/600/2000 with 12/120 CCSD): ground-state energies and
+excitation energies against oracle reference values written by
 tests/golden/make_reference.py (FP64 oracle, same seeded inputs), and one
 Jacobian transformation at 40/400/1200 against the oracle computed here.
 
@@ -60,7 +61,7 @@ def solve(ctx, name, precision, effective=False):
     return ref, gs, dav
 
 
-@pytest.mark.parametrize("name", ["cc2_5_20_60", "mlcc2_40_400_1200"])
+@pytest.mark.parametrize("name", ["cc2_5_20_60", "mlcc2_40_400_1200", "mlccsd_60_600_2000"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_energies_and_roots(ctx, name, precision):
     ref, gs, dav = solve(ctx, name, precision)
