@@ -8,7 +8,8 @@
 //
 // Layout in HBM (n = O + V, J Cholesky vectors, M = o*v active pairs):
 //   L, Lt      [J][n][n]   Cholesky vectors and their X1 transform
-//   Lvo0, Lai  [J][M]      packed active L_ai (untransformed) and L~_ai
+//   Lvo0, Lai  [J][M]      packed active L_ai (untransformed) and L~_ai (MLCCSD)
+//   LaiT       [M][J]      L~_ai pair-major (MLCC2)
 //   Z          [J][M]      Z^K_ai = sum_bj u_ai,bj L^K_bj  (shared by Omega_1
 //                          and the energy)
 //   g, u       [M][M]      g~_aibj and u = 2x - x(i<->j)
@@ -273,18 +274,25 @@ template <typename T> void mlcc_problem::doubles_mlcc2_t() {
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, M = d.M;
   const Prec p = gemm_prec<T>();
-  Lai.ensure(al, (size_t)J * M * sizeof(T));
-  k::pack2d<T, T>(x, off<T>(Lai), off<T>(Lt, O * n), J, n2, d.v, d.o, n);
   u.ensure(al, (size_t)M * M * sizeof(T));
   if (model == MLCC_MLCC2) {
+    // L~_ai pair-major, LaiT[ai][K]: the reduction index of g~ and of the
+    // Jacobian's doubles block is contiguous (split BF16 products need it)
+    LaiT.ensure(al, (size_t)J * M * sizeof(T));
+    const int64_t nn[4] = {1, d.v, d.o, J}, ss[4] = {0, n, 1, n2};
+    k::permute4<T, T>(x, off<T>(LaiT), off<T>(Lt, O * n), nn, ss, 1.0, 0.0);
     g.ensure(al, (size_t)M * M * sizeof(double));
     // g~_ai,bj = sum_K L~^K_ai L~^K_bj
-    G(M, M, J).A(off<T>(Lai), 1, M).B(off<T>(Lai), M, 1).C(g.p, M, 1).tag("g_aibj").run(x, p, true);
+    G(M, M, J).A(off<T>(LaiT), J, 1).B(off<T>(LaiT), 1, J).C(g.p, M, 1).tag("g_aibj")
+        .run(x, p, true);
     if (!x2_set)
       k::mlcc2_s_u<double, T>(x, d.o, d.v, g.as<double>(), eps_ai.as<double>(), x2(), off<T>(u));
     else
       k::u_of<T>(x, d.o, d.v, x2(), off<T>(u));
   } else {
+    // MLCCSD: L~_ai K-major, Lai[K][ai] (its integral blocks read it so)
+    Lai.ensure(al, (size_t)J * M * sizeof(T));
+    k::pack2d<T, T>(x, off<T>(Lai), off<T>(Lt, O * n), J, n2, d.v, d.o, n);
     k::u_of<T>(x, d.o, d.v, x2(), off<T>(u));
   }
   Z.ensure(al, (size_t)J * M * sizeof(T));
@@ -445,15 +453,26 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   // singles -> doubles: dL~_ai = sum_B L~_aB c_Bi - sum_J c_aJ L~_Ji  ([K][vec][ai]),
   // G[ai][vec, bj] = sum_K L~^K_ai dL~^K_bj
   dLai.ensure(al, (size_t)J * b * M * sizeof(T));
+  Gm.ensure(al, (size_t)M * b * M * sizeof(double));
   // one launch per term: rows (K, a) x columns (vec, i), then rows (vec, a) x
   // columns (K, i)
-  G(J * v, b * o, V).A(lt + O * n + O, n, 1).Mhi(v, n2, b * M).B(ct, O, 1).Nhi(o, n1, M)
-      .C(dLai.p, o, 1).tag("dLai").run(x, p, o64);
-  G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M).B(lt, n, 1).Nhi(o, n2, b * M)
-      .C(dLai.p, o, 1, 0, -1.0, 1.0).tag("dLai").run(x, p, o64);
-  Gm.ensure(al, (size_t)M * b * M * sizeof(double));
-  G(M, b * M, J).A(off<T>(Lai), 1, M).B(dLai.p, b * M, 1).C(Gm.p, b * M, 1)
-      .tag("sigma2_LdL").run(x, p, true);
+  if (model == MLCC_MLCC2) {
+    // pair-major dL~: dLai[vec][ai][K]
+    G(J * v, b * o, V).A(lt + O * n + O, n, 1).Mhi(v, n2, 1).B(ct, O, 1).Nhi(o, n1, M * J)
+        .C(dLai.p, o * J, J).tag("dLai").run(x, p, o64);
+    G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M * J).B(lt, n, 1).Nhi(o, n2, 1)
+        .C(dLai.p, o * J, J, 0, -1.0, 1.0).tag("dLai").run(x, p, o64);
+    G(M, b * M, J).A(off<T>(LaiT), J, 1).B(dLai.p, 1, J).C(Gm.p, b * M, 1)
+        .tag("sigma2_LdL").run(x, p, true);
+  } else {
+    // K-major dL~: dLai[K][vec][ai] (read so by the MLCCSD doubles terms)
+    G(J * v, b * o, V).A(lt + O * n + O, n, 1).Mhi(v, n2, b * M).B(ct, O, 1).Nhi(o, n1, M)
+        .C(dLai.p, o, 1).tag("dLai").run(x, p, o64);
+    G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M).B(lt, n, 1).Nhi(o, n2, b * M)
+        .C(dLai.p, o, 1, 0, -1.0, 1.0).tag("dLai").run(x, p, o64);
+    G(M, b * M, J).A(off<T>(Lai), 1, M).B(dLai.p, b * M, 1).C(Gm.p, b * M, 1)
+        .tag("sigma2_LdL").run(x, p, true);
+  }
 
   // the doubles used by doubles -> singles: the trial doubles, or the
   // eliminated ones of the effective transformation

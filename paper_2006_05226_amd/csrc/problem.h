@@ -92,7 +92,7 @@ struct mlcc_problem {
   mlcc::DBuf amp;      // f64 [n1 + M*M]: t1 then doubles
   mlcc::DBuf t1T;      // op [n1]
   mlcc::DBuf Lt, ht, Ft, dK, dKT;
-  mlcc::DBuf Lai, g, u, Z;
+  mlcc::DBuf Lai, LaiT, g, u, Z;
   mlcc::DBuf om;       // f64 [n1 + M*M]
   mlcc::DBuf res;      // f64 device scalars
   // Jacobian intermediates
