@@ -379,6 +379,13 @@ template <typename T> void mlcc_problem::prepare_jacobian_t() {
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
   const Prec p = gemm_prec<T>();
   compute_state_t<T>(true);
+  {
+    // LooT[K][i][J] = L~^K_Ji: the occupied reduction index J contiguous for
+    // the c L~_oo products of the transformation
+    LooT.ensure(al, (size_t)J * O * O * sizeof(T));
+    const int64_t nn[4] = {1, J, O, O}, ss[4] = {0, n2, 1, n};
+    k::permute4<T, T>(x, off<T>(LooT), off<T>(Lt), nn, ss, 1.0, 0.0);
+  }
   if (has_doubles()) {
     Xint.ensure(al, O * o * sizeof(T));
     Yint.ensure(al, v * V * sizeof(T));
@@ -411,8 +418,13 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   const T *lt = off<T>(Lt);
   const double *F = Ft.as<double>();
   cT.ensure(al, b * n1 * sizeof(T));
+  cTt.ensure(al, b * n1 * sizeof(T));
   T *ct = off<T>(cT);
   k::pack2d<T, double>(x, ct, c, b, ld, 1, n1, 0);
+  // and transposed, ctt[vec][I][A] (the virtual index contiguous)
+  T *ctt = off<T>(cTt);
+  k::pack2d_t<T, double>(x, ctt, c, b, ld, V, O, O);
+  const T *loot = off<T>(LooT);
 
   // CCS terms: F~_AB c_BI - c_AJ F~_JI + 2 (L~^K_JB c_BJ) L~^K_AI - (L~^K_AB c_BJ) L~^K_JI
   G(V, O, V, 1, b).A(F + O * n + O, n, 1, 0, 0).B(c, O, 1, 0, ld).C(sigma, O, 1, ld)
@@ -426,7 +438,7 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   // W^K[vec][i][B] = sum_J c_BJ L~^K_Ji, stored with B innermost so that the
   // reduction index of ccs_vv is contiguous
   W.ensure(al, (size_t)J * b * V * O * sizeof(T));
-  G(b * V, O, O, 1, J).A(ct, O, 1, 0, 0).Mhi(V, V * O, V * O).B(lt, n, 1, 0, n2)
+  G(b * V, O, O, 1, J).A(ct, O, 1, 0, 0).Mhi(V, V * O, V * O).B(loot, 1, O, 0, O * O)
       .C(W.p, 1, V, b * V * O).tag("ccs_W").run(x, p, o64);
   G(V, b * O, V, J).A(lt + O * n + O, n, 1, n2).B(W.p, 1, V, b * V * O).Nhi(O, V * O, ld)
       .C(sigma, O, 1, 0, -1.0, 1.0).tag("ccs_vv").run(x, p, true);
@@ -458,9 +470,9 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   // columns (K, i)
   if (model == MLCC_MLCC2) {
     // pair-major dL~: dLai[vec][ai][K]
-    G(J * v, b * o, V).A(lt + O * n + O, n, 1).Mhi(v, n2, 1).B(ct, O, 1).Nhi(o, n1, M * J)
+    G(J * v, b * o, V).A(lt + O * n + O, n, 1).Mhi(v, n2, 1).B(ctt, 1, V).Nhi(o, n1, M * J)
         .C(dLai.p, o * J, J).tag("dLai").run(x, p, o64);
-    G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M * J).B(lt, n, 1).Nhi(o, n2, 1)
+    G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M * J).B(loot, 1, O).Nhi(o, O * O, 1)
         .C(dLai.p, o * J, J, 0, -1.0, 1.0).tag("dLai").run(x, p, o64);
     G(M, b * M, J).A(off<T>(LaiT), J, 1).B(dLai.p, 1, J).C(Gm.p, b * M, 1)
         .tag("sigma2_LdL").run(x, p, true);

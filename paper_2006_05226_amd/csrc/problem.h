@@ -96,11 +96,11 @@ struct mlcc_problem {
   mlcc::DBuf om;       // f64 [n1 + M*M]
   mlcc::DBuf res;      // f64 device scalars
   // Jacobian intermediates
-  mlcc::DBuf Xint, Yint, fvec;
+  mlcc::DBuf Xint, Yint, fvec, LooT;
   // MLCCSD intermediates and scratch
   mlcc::DBuf cc_work;
   // transform scratch
-  mlcc::DBuf cT, Xk, W, P, qv, rv, wv, ut, Zc, dLai, Gm, c2e;
+  mlcc::DBuf cT, cTt, Xk, W, P, qv, rv, wv, ut, Zc, dLai, Gm, c2e;
 
   bool have_amp = false;
   bool x2_set = false;     // MLCC2: an independent s2 was given
