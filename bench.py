@@ -19,7 +19,7 @@ host cores for one transform at the same shape.
 
 Serving (extra.serving): a stream of MLCC2 excitation requests of uneven size
 (n_occ uniform in [20, 80], n_vir = 10 n_occ, n_chol = 3 n_vir, active
-0.375 n_occ / 3.75 n_occ, 3 roots, FP32 contractions, effective-singles
+0.375 n_occ / 3.75 n_occ, 3 roots, split-BF16 contractions, effective-singles
 Davidson, Cholesky vectors drawn on the device) through the continuous-
 batching server: first all at once (saturated solves/s), then with Poisson
 arrivals at 0.7 of that rate (p50 / p99 latency from submission to a
@@ -165,48 +165,50 @@ def _mlccsd_leg(mlcc, steps, warmup, precisions, config="mlccsd_60_600_2000", nv
     return out
 
 
-def _c4_leg(mlcc, steps=3, nvec=5):
-    """MLCC2 at 150/1200/3600 (active 50/500), FP32 contractions, FP64
-    updates, effective-singles Davidson for 5 roots; device-drawn Cholesky
-    vectors.  g~ and the doubles live only in HBM (no host copies)."""
+def _c4_leg(mlcc, steps=3, nvec=5, precisions=("fp32", "bf16x3")):
+    """MLCC2 at 150/1200/3600 (active 50/500), FP32 or split-BF16 contractions,
+    FP64 updates, effective-singles Davidson for 5 roots; device-drawn
+    Cholesky vectors.  g~ and the doubles live only in HBM (no host copies)."""
     import torch
     from paper_2006_05226_amd.synth import CONFIGS, gen_eps
 
     c = CONFIGS["mlcc2_150_1200_3600"]
     O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
     eps = gen_eps(O, V, o, seed=0)
-    print("c4: setup", file=sys.stderr, flush=True)
-    ctx = mlcc.Context(0)
-    t0 = time.perf_counter()
-    P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlcc2", precision="fp32", n_chol=J, seed=0)
-    t_setup = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    gs = P.ground_state(tol=1e-6)
-    t_gs = time.perf_counter() - t0
-    c1 = torch.randn(nvec, O * V, dtype=torch.float64, device="cuda",
-                     generator=torch.Generator(device="cuda").manual_seed(0)) * 1e-2
-    s1 = torch.empty_like(c1)
-    P.jacobian_transform_eff(0.4, c1, s1)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
+    out = {"workload": f"MLCC2 n_occ={O} n_vir={V} n_chol={J}, CC2 active {o}/{v}, effective-singles "
+                       "Davidson for 5 roots, device-drawn L, FP64 amplitudes/DIIS/Davidson"}
+    for prec in precisions:
+        print(f"c4: {prec}", file=sys.stderr, flush=True)
+        ctx = mlcc.Context(0)
+        t0 = time.perf_counter()
+        P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlcc2", precision=prec, n_chol=J,
+                         seed=0)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        gs = P.ground_state(tol=1e-6)
+        t_gs = time.perf_counter() - t0
+        c1 = torch.randn(nvec, O * V, dtype=torch.float64, device="cuda",
+                         generator=torch.Generator(device="cuda").manual_seed(0)) * 1e-2
+        s1 = torch.empty_like(c1)
         P.jacobian_transform_eff(0.4, c1, s1)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    stats = ctx.profile_stats()
-    ctx.profile(False)
-    print("c4: davidson", file=sys.stderr, flush=True)
-    t0 = time.perf_counter()
-    dav = P.davidson(5, tol=1e-5, effective=True)
-    t_dav = time.perf_counter() - t0
-    peak = ctx.bytes()
-    P.close()
-    ctx.close()
-    del c1, s1
-    torch.cuda.empty_cache()
-    return {"workload": f"MLCC2 n_occ={O} n_vir={V} n_chol={J}, CC2 active {o}/{v}, FP32 "
-                        "contractions, effective-singles Davidson for 5 roots, device-drawn L",
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            P.jacobian_transform_eff(0.4, c1, s1)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stats = ctx.profile_stats()
+        ctx.profile(False)
+        t0 = time.perf_counter()
+        dav = P.davidson(5, tol=1e-5, effective=True)
+        t_dav = time.perf_counter() - t0
+        peak = ctx.bytes()
+        P.close()
+        ctx.close()
+        del c1, s1
+        torch.cuda.empty_cache()
+        out[prec] = {
             "setup_seconds": t_setup, "gs_seconds": t_gs, "gs_iterations": gs["iterations"],
             "e_corr": gs["energy"], "eff_transforms_per_s": steps * nvec / dt,
             "davidson_seconds": t_dav, "davidson_transforms": dav["transforms"],
@@ -215,9 +217,14 @@ def _c4_leg(mlcc, steps=3, nvec=5):
             "contractions": {k: dict(ms_per_step=st["ms"] / steps,
                                      tflops=st["flops"] / max(st["ms"], 1e-9) / 1e9)
                              for k, st in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:8]}}
+    if len(precisions) == 2:
+        a, b = (out[p] for p in precisions)
+        out["difference"] = dict(e_corr=b["e_corr"] - a["e_corr"],
+                                 omega=[y - x for x, y in zip(a["omega"], b["omega"])])
+    return out
 
 
-def _serving(mlcc, n_req, slots, precision="fp32", rate_frac=0.7, gs_tol=1e-6, es_tol=1e-5):
+def _serving(mlcc, n_req, slots, precision="bf16x3", rate_frac=0.7, gs_tol=1e-6, es_tol=1e-5):
     import numpy as np
     from paper_2006_05226_amd.synth import gen_eps, serving_stream
 
@@ -288,7 +295,7 @@ def _serving(mlcc, n_req, slots, precision="fp32", rate_frac=0.7, gs_tol=1e-6, e
         "all_ok": ok, "burst_equals_stream": same, "admissions_while_busy": overlap,
         "sizes_n_occ": [q["n_occ"] for q in reqs],
         "workload": "MLCC2 excitation requests, n_occ uniform in [20,80], n_vir=10 n_occ, "
-                    "n_chol=3 n_vir, active round(0.375 n_occ)/10x, 3 roots, FP32 contractions, "
+                    f"n_chol=3 n_vir, active round(0.375 n_occ)/10x, 3 roots, {precision} contractions, "
                     "effective-singles Davidson, synthetic device-drawn Cholesky vectors",
     }
 
