@@ -22,7 +22,7 @@ def ctx():
 
 
 @pytest.mark.parametrize("o,v", [(0, 13), (4, 0)])
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_empty_active_space_is_ccs(ctx, o, v, precision):
     """With no active pairs MLCC2 is CCS: the canonical reference already
     satisfies it (t1 = 0, E = 0) and the roots are the CIS eigenvalues."""
@@ -40,7 +40,7 @@ def test_empty_active_space_is_ccs(ctx, o, v, precision):
 
 
 @pytest.mark.parametrize("model", ["mlcc2", "mlccsd"])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 5e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 5e-5), ("bf16x3", 5e-4)])
 def test_prime_dimensions(ctx, model, precision, tol):
     """O=7, V=37, n_chol=53, active 3/13: every extent is prime, so every
     tile is ragged and no row is 16-byte aligned."""

@@ -73,7 +73,7 @@ def test_energies_and_roots(ctx, name, precision):
     assert np.abs(np.array(dav["omega"]) - ref["omega"]).max() < t["w"]
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_effective_singles_roots(ctx, precision):
     """The effective-singles solver (used by the serving loop) reaches the
     full-space oracle roots."""

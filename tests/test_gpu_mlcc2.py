@@ -29,7 +29,7 @@ def small(ctx, model="mlcc2", precision="fp64", seed=0, **kw):
                 precision=precision, ctx=ctx)
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5), ("bf16x3", 5e-4)])
 def test_x1_basis_and_fock(ctx, precision, tol):
     inp, _, P, OP, d = small(ctx, precision=precision)
     t1, s = gen_amplitudes(d.O, d.V, d.o, d.v, seed=1, scale1=0.05, scale2=0.02)
@@ -46,7 +46,7 @@ def test_x1_basis_and_fock(ctx, precision, tol):
     assert rel(g, om.g_aibj(D.Lt, d).reshape(d.M, d.M)) < tol
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5), ("bf16x3", 5e-4)])
 def test_residual_independent_s(ctx, precision, tol):
     inp, _, P, OP, d = small(ctx, precision=precision)
     t1, s = gen_amplitudes(d.O, d.V, d.o, d.v, seed=2, scale1=0.05, scale2=0.02)
@@ -59,7 +59,7 @@ def test_residual_independent_s(ctx, precision, tol):
     assert abs(e - OP.energy(t1, s)) < tol * abs(OP.energy(t1, s)) + 1e-15
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 2e-5), ("bf16x3", 5e-4)])
 def test_residual_analytic_s(ctx, precision, tol):
     inp, _, P, OP, d = small(ctx, precision=precision)
     t1, _ = gen_amplitudes(d.O, d.V, d.o, d.v, seed=3, scale1=0.05)
@@ -101,7 +101,7 @@ def test_ground_state_mlcc2_partial_active(ctx):
     assert abs(r["energy"] - ref["energy"]) < 1e-10
 
 
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 3e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 3e-5), ("bf16x3", 5e-4)])
 def test_jacobian_transform_parity(ctx, precision, tol):
     inp, _, P, OP, d = small(ctx, precision=precision)
     t1, s = gen_amplitudes(d.O, d.V, d.o, d.v, seed=4, scale1=0.05, scale2=0.02)

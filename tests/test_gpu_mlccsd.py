@@ -24,7 +24,7 @@ def ctx():
 
 
 @pytest.mark.parametrize("sz", SIZES)
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 5e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-11), ("fp32", 5e-5), ("bf16x3", 5e-4)])
 def test_residual_parity(ctx, sz, precision, tol):
     inp, _, P, OP, d = make(sz["O"], sz["V"], sz["J"], sz["o"], sz["v"], seed=2, model="mlccsd",
                             precision=precision, ctx=ctx)
@@ -38,7 +38,7 @@ def test_residual_parity(ctx, sz, precision, tol):
 
 
 @pytest.mark.parametrize("sz", SIZES)
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 5e-5)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 5e-5), ("bf16x3", 5e-4)])
 def test_jacobian_parity(ctx, sz, precision, tol):
     inp, _, P, OP, d = make(sz["O"], sz["V"], sz["J"], sz["o"], sz["v"], seed=4, model="mlccsd",
                             precision=precision, ctx=ctx)
