@@ -254,6 +254,13 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
                        const void *B, const int64_t sB[4], double beta, void *C,
                        const int64_t sC[3], const int64_t lvl[6]);
 
+/* Tile override of the contraction engine, process-wide, for parity tests
+ * and tuning: later engine calls whose tile menu lists the bm x bn output tile
+ * use it (with the split count the cost model gives it); bm = bn = 0 restores
+ * the cost model.  last (may be NULL) receives the tile of the previous
+ * engine call.  MLCC_E_ARG for negative sizes. */
+mlcc_status mlcc_gemm_tile(int32_t bm, int32_t bn, int32_t last[2]);
+
 /* Per-contraction timing: when enabled, every GEMM-engine launch is bracketed
  * by HIP events on the context stream and accumulated under the name of the
  * contraction it computes (e.g. "g_aibj", "ccs_vv").  flops counts the

@@ -517,6 +517,17 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
   });
 }
 
+mlcc_status mlcc_gemm_tile(int32_t bm, int32_t bn, int32_t last[2]) {
+  if (bm < 0 || bn < 0) return MLCC_E_ARG;
+  if (last) {
+    last[0] = gk::g_last_bm.load();
+    last[1] = gk::g_last_bn.load();
+  }
+  gk::g_force_bm.store(bm);
+  gk::g_force_bn.store(bn);
+  return MLCC_OK;
+}
+
 mlcc_status mlcc_profile_enable(mlcc_context *ctx, int32_t on) {
   if (!ctx) return MLCC_E_ARG;
   return guarded(ctx, [&]() -> mlcc_status {

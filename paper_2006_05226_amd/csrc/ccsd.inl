@@ -33,15 +33,18 @@
 
 namespace mlcc {
 struct CcsdState {
-  DBuf Loo, Lvv, LKc;                             // packed L~ blocks [J][..]
+  DBuf Loo, Lvv, LKc, Lkc;                        // packed L~ blocks [J][..]
   DBuf g_vovo, g_oooo, g_ovov, g_oovv, g_voov;    // integral blocks (op type)
+  DBuf gX;                                        // gX[(c,k)][(d,l)] = g_kdlc
+  DBuf xA, xB;                                    // occupied-exchanged amplitudes
+  DBuf tL;                                        // tL[c][i][j][d] = t_cidj (slot A)
   DBuf g_vvvv;                                    // [(a,c)][(b,d)]
   DBuf Fvv, Foo;                                  // dressed Fock blocks (op type)
   DBuf tT;                                        // t2 in the op type
   DBuf Q, Y, Z, X, Rb, Lld, g2, g3, Wvv, Woo;     // term scratch
   DBuf Gk, Y3;                                    // ladder-derivative intermediate
   // per-vector Jacobian scratch
-  DBuf c1T, c2T, cu2, dLoo, dLvv, dg_oooo, dg_oovv, dg_voov, dF64, dFvv, dFoo, dXk, Pv, Po;
+  DBuf c1T, c1tt, c2T, cu2, dLoo, dLvv, dg_oooo, dg_oovv, dg_voov, dF64, dFvv, dFoo, dXk, Pv, Po;
   DBuf S, Rs;
 };
 }  // namespace mlcc
@@ -62,8 +65,11 @@ template <typename T> void mlcc_problem::ccsd_integrals_t() {
   s.Lvv.ensure(al, J * v * v * sizeof(T));
   k::pack2d<T, T>(x, off<T>(s.Loo), lt, J, n2, o, o, n);
   k::pack2d<T, T>(x, off<T>(s.Lvv), lt + O * n + O, J, n2, v, v, n);
-  // Lai (L~_ai) and Lvo0 (L_ai = L_ia, the unchanged ov block) are packed already
-  const T *Lvo = off<T>(Lai), *Lov0 = off<T>(Lvo0);
+  // Lai (L~_ai) is packed already; Lkc[J][k][c] = L~_kc = L_kc (the ov block
+  // does not depend on t1) with the pair index k*v + c contiguous
+  const T *Lvo = off<T>(Lai);
+  s.Lkc.ensure(al, J * o * v * sizeof(T));
+  k::pack2d<T, T>(x, off<T>(s.Lkc), lt + O, J, n2, o, v, n);
   s.g_vovo.ensure(al, M * M * sizeof(T));
   s.g_oooo.ensure(al, o * o * o * o * sizeof(T));
   s.g_ovov.ensure(al, M * M * sizeof(T));
@@ -73,15 +79,20 @@ template <typename T> void mlcc_problem::ccsd_integrals_t() {
   G(M, M, J).A(Lvo, 1, M).B(Lvo, M, 1).C(s.g_vovo.p, M, 1).tag("cc_g").run(x, p, o64);
   G(o * o, o * o, J).A(s.Loo.p, 1, o * o).B(s.Loo.p, o * o, 1).C(s.g_oooo.p, o * o, 1)
       .tag("cc_g").run(x, p, o64);
-  // g_ovov[(k,c)][(l,d)]: rows/cols (k,c) read from Lvo0[J][c*o + k]
-  G(M, M, J).A(Lov0, o, M).Mhi(v, 1, v * M).B(Lov0, M, o).Nhi(v, 1, v).C(s.g_ovov.p, M, 1)
-      .tag("cc_g").run(x, p, o64);
+  // g_ovov[(k,c)][(l,d)] = g_kcld
+  G(M, M, J).A(s.Lkc.p, 1, M).B(s.Lkc.p, M, 1).C(s.g_ovov.p, M, 1).tag("cc_g").run(x, p, o64);
   G(o * o, v * v, J).A(s.Loo.p, 1, o * o).B(s.Lvv.p, v * v, 1).C(s.g_oovv.p, v * v, 1)
       .tag("cc_g").run(x, p, o64);
-  G(M, M, J).A(Lvo, 1, M).B(Lov0, M, o).Nhi(v, 1, v).C(s.g_voov.p, M, 1).tag("cc_g")
-      .run(x, p, o64);
+  G(M, M, J).A(Lvo, 1, M).B(s.Lkc.p, M, 1).C(s.g_voov.p, M, 1).tag("cc_g").run(x, p, o64);
   G(v * v, v * v, J).A(s.Lvv.p, 1, v * v).B(s.Lvv.p, v * v, 1).C(s.g_vvvv.p, v * v, 1)
       .tag("cc_g_vvvv").run(x, p, o64);
+  // gX[(c,k)][(d,l)] = g_kdlc = g_ovov[(k,d)][(l,c)], the C2 integral with
+  // its reduction pair (d,l) contiguous (symmetric under (c,k) <-> (d,l))
+  s.gX.ensure(al, M * M * sizeof(T));
+  {
+    const int64_t nn[4] = {v, o, v, o}, ss[4] = {1, v * M, M, v};
+    k::permute4<T, T>(x, off<T>(s.gX), off<T>(s.g_ovov), nn, ss, 1.0, 0.0);
+  }
   s.Fvv.ensure(al, v * v * sizeof(T));
   s.Foo.ensure(al, o * o * sizeof(T));
   k::pack2d<T, double>(x, off<T>(s.Fvv), Ft.as<double>() + O * n + O, 1, 0, v, v, n);
@@ -112,9 +123,15 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
     const int64_t nn[4] = {1, 1, M, M}, ss[4] = {0, 0, M, 1};
     k::permute4<double, T>(x, sym, static_cast<const T *>(blk[CB_VOVO]), nn, ss, 1.0, 1.0);
   }
+  // tL[c][i][j][d] = tA_cidj: the ladder and E2 reduce over its contiguous d
+  if ((ladder && incB) || any) {
+    const int64_t nn[4] = {v, o, o, v}, sl[4] = {o * M, M, 1, o};
+    s.tL.ensure(al, M * M * sizeof(T));
+    k::permute4<T, T>(x, off<T>(s.tL), static_cast<const T *>(tA), nn, sl, 1.0, 0.0);
+  }
   if (ladder && incB) {
     G(v * v, o * o, v, v).A(blk[CB_VVVV], v, 1, v * v).Mhi(v, v * v * v, o * M)
-        .B(tA, o, 1, o * M).Nhi(o, M, M).C(sym, o, 1, 0, 1.0, 1.0).tag("cc_ladder")
+        .B(s.tL.p, 1, v, o * o * v).Nhi(o, o * v, M).C(sym, o, 1, 0, 1.0, 1.0).tag("cc_ladder")
         .run(x, p, true);
   }
   if (!any) return;
@@ -132,7 +149,10 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
   G(v * v, o * o, o, o).A(tA, o, 1, M).Mhi(v, o * M, o * M).B(s.Q.p, o * o, 1, o * o * o)
       .Nhi(o, o, M).C(sym, o, 1, 0, 1.0, 1.0).tag("cc_B2").run(x, p, true);
   // --- C2: Y[(a,i)][(c,k)] = g_kiac - 1/2 sum_dl tB_aldi g_kdlc ;
-  //         X = Y tA' ; R += -1/2 X - X(i<->j)
+  //         X[(a,i)][(b,j)] = sum_ck Y[(a,i)][(c,k)] tA_bkcj ; R += -1/2 X - X(i<->j)
+  // Both sums run over one contiguous pair index through the occupied-
+  // exchanged amplitudes x[(a,i)][(b,j)] = t_ajbi: tB_aldi = xB[(a,i)][(d,l)],
+  // tA_bkcj = xA[(b,j)][(c,k)].
   s.Y.ensure(al, M * M * sizeof(T));
   s.X.ensure(al, M * M * sizeof(double));
   {
@@ -140,11 +160,23 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
     k::permute4<T, T>(x, off<T>(s.Y), static_cast<const T *>(blk[CB_OOVV]), nn, ss,
                       incB ? 1.0 : 0.0, 0.0);
   }
-  if (incQ)
-    G(M, M, o, v).A(tB, 1, M, o).Mhi(o, o * M, o * M).B(blk[CB_OVOV], v, v * M, M)
-        .Nhi(o, 1, o).C(s.Y.p, M, 1, 0, -0.5, 1.0).tag("cc_C2").run(x, p, o64);
-  G(M, M, o, v).A(s.Y.p, M, 1, o).B(tA, M, 1, o).Nhi(o, o * M, o).C(s.X.p, M, 1)
-      .tag("cc_C2").run(x, p, true);
+  {
+    const int64_t nn[4] = {v, o, v, o}, sx[4] = {o * M, 1, o, M};
+    s.xA.ensure(al, M * M * sizeof(T));
+    k::permute4<T, T>(x, off<T>(s.xA), static_cast<const T *>(tA), nn, sx, 1.0, 0.0);
+    if (incQ) {
+      MLCC_REQUIRE(blk[CB_OVOV] == s.g_ovov.p, MLCC_E_STATE, "C2: gX belongs to g_ovov");
+      const void *xB = s.xA.p;
+      if (tB != tA) {
+        s.xB.ensure(al, M * M * sizeof(T));
+        k::permute4<T, T>(x, off<T>(s.xB), static_cast<const T *>(tB), nn, sx, 1.0, 0.0);
+        xB = s.xB.p;
+      }
+      G(M, M, M).A(xB, M, 1).B(s.gX.p, 1, M).C(s.Y.p, M, 1, 0, -0.5, 1.0).tag("cc_C2")
+          .run(x, p, o64);
+    }
+  }
+  G(M, M, M).A(s.Y.p, M, 1).B(s.xA.p, 1, M).C(s.X.p, M, 1).tag("cc_C2").run(x, p, true);
   {
     const int64_t nn[4] = {v, o, v, o};
     const int64_t sx[4] = {o * M, 1, o, M}, sid[4] = {o * M, M, o, 1};
@@ -152,6 +184,8 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
     k::permute4<double, double>(x, R, s.X.as<double>(), nn, sid, -0.5, 1.0);
   }
   // --- D2: Z[(a,i)][(c,k)] = L_aikc + 1/2 sum_dl uB_aidl L_ldkc ; R += 1/2 Z uA
+  // (Lld and uA are symmetric under the exchange of their pair indices, so
+  // both are read with the reduction pair contiguous)
   s.Z.ensure(al, M * M * sizeof(T));
   {
     const int64_t nn[4] = {v, o, v, o};
@@ -168,10 +202,10 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
     const int64_t s1[4] = {M, v * M, 1, v}, s2[4] = {1, v * M, M, v};
     k::permute4<T, T>(x, off<T>(s.Lld), static_cast<const T *>(blk[CB_OVOV]), nn, s1, 2.0, 0.0);
     k::permute4<T, T>(x, off<T>(s.Lld), static_cast<const T *>(blk[CB_OVOV]), nn, s2, -1.0, 1.0);
-    G(M, M, M).A(uB, M, 1).B(s.Lld.p, M, 1).C(s.Z.p, M, 1, 0, 0.5, 1.0).tag("cc_D2")
+    G(M, M, M).A(uB, M, 1).B(s.Lld.p, 1, M).C(s.Z.p, M, 1, 0, 0.5, 1.0).tag("cc_D2")
         .run(x, p, o64);
   }
-  G(M, M, M).A(s.Z.p, M, 1).B(uA, M, 1).C(R, M, 1, 0, 0.5, 1.0).tag("cc_D2").run(x, p, true);
+  G(M, M, M).A(s.Z.p, M, 1).B(uA, 1, M).C(R, M, 1, 0, 0.5, 1.0).tag("cc_D2").run(x, p, true);
   // --- E2: Wvv = F_bc - sum uB_bkdl g_ldkc, Woo = F_kj + sum uB_cldj g_kdlc
   s.Wvv.ensure(al, v * v * sizeof(T));
   s.Woo.ensure(al, o * o * sizeof(T));
@@ -186,16 +220,17 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
   if (incQ) {
     s.g2.ensure(al, M * M * sizeof(T));
     s.g3.ensure(al, M * M * sizeof(T));
-    const int64_t nn2[4] = {o, v, o, v}, s2[4] = {v, M, v * M, 1};   // g2[k][d][l][c]
+    const int64_t nn2[4] = {v, o, v, o}, s2[4] = {1, v, M, v * M};   // g2[c][k][d][l]
     const int64_t nn3[4] = {v, o, v, o}, s3[4] = {1, v, M, v * M};   // g3[c][l][d][k]
     k::permute4<T, T>(x, off<T>(s.g2), static_cast<const T *>(blk[CB_OVOV]), nn2, s2, 1.0, 0.0);
     k::permute4<T, T>(x, off<T>(s.g3), static_cast<const T *>(blk[CB_OVOV]), nn3, s3, 1.0, 0.0);
-    G(v, v, o * M).A(uB, o * M, 1).B(s.g2.p, v, 1).C(s.Wvv.p, v, 1, 0, -1.0, 1.0).tag("cc_E2")
-        .run(x, p, o64);
+    G(v, v, o * M).A(uB, o * M, 1).B(s.g2.p, 1, o * M).C(s.Wvv.p, v, 1, 0, -1.0, 1.0)
+        .tag("cc_E2").run(x, p, o64);
     G(o, o, v * o * v).A(s.g3.p, 1, o).B(uB, o, 1).C(s.Woo.p, o, 1, 0, 1.0, 1.0).tag("cc_E2")
         .run(x, p, o64);
   }
-  G(M, v, v, 1, o).A(tA, M, o, 0, 1).B(s.Wvv.p, 1, v, 0, 0).C(R, M, o, 1, 1.0, 1.0)
+  // rows (a,i,j) of tL: R[(a,i)][(b,j)] += sum_c tA_aicj Wvv[b][c]
+  G(M * o, v, v).A(s.tL.p, v, 1).Mhi(o, o * v, M).B(s.Wvv.p, 1, v).C(R, 1, o, 0, 1.0, 1.0)
       .tag("cc_E2").run(x, p, true);
   G(M * v, o, o).A(tA, o, 1).B(s.Woo.p, o, 1).C(R, o, 1, 0, -1.0, 1.0).tag("cc_E2")
       .run(x, p, true);
@@ -234,8 +269,13 @@ template <typename T> void mlcc_problem::ccsd_prepare_t() {
   G(O * v, v * v, J).A(s.LKc.p, 1, O * v).B(s.Lvv.p, v * v, 1).C(s.Gk.p, v * v, 1)
       .tag("cc_Gk").run(x, p, o64);
   s.Y3.ensure(al, (size_t)O * o * M * sizeof(T));
-  G(O * v, o * o, v, v).A(s.Gk.p, v, 1, v * v).Mhi(v, v * v * v, o * M).B(s.tT.p, o, 1, o * M)
-      .Nhi(o, M, M).C(s.Y3.p, o, 1).tag("cc_Y3").run(x, p, o64);
+  {
+    const int64_t nn[4] = {v, o, o, v}, sl[4] = {o * M, M, 1, o};
+    s.tL.ensure(al, M * M * sizeof(T));
+    k::permute4<T, T>(x, off<T>(s.tL), off<T>(s.tT), nn, sl, 1.0, 0.0);
+  }
+  G(O * v, o * o, v, v).A(s.Gk.p, v, 1, v * v).Mhi(v, v * v * v, o * M)
+      .B(s.tL.p, 1, v, o * o * v).Nhi(o, o * v, M).C(s.Y3.p, o, 1).tag("cc_Y3").run(x, p, o64);
   s.Gk.release();
 }
 
@@ -256,6 +296,9 @@ void mlcc_problem::ccsd_sigma2_t(const double *c1, const double *c2, const doubl
   s.cu2.ensure(al, M * M * sizeof(T));
   T *c1t = off<T>(s.c1T);
   k::convert<T, double>(x, c1t, c1, n1);
+  s.c1tt.ensure(al, n1 * sizeof(T));  // c1tt[I][B] = c_BI
+  T *c1tt = off<T>(s.c1tt);
+  k::pack2d_t<T, double>(x, c1tt, c1, 1, 0, V, O, O);
   k::convert<T, double>(x, off<T>(s.c2T), c2, M * M);
   k::u_of<T>(x, d.o, d.v, c2, off<T>(s.cu2));
 
@@ -279,8 +322,7 @@ void mlcc_problem::ccsd_sigma2_t(const double *c1, const double *c2, const doubl
       .tag("cc_dg").run(x, p, o64);
   G(o * o, v * v, J).A(s.Loo.p, 1, o * o).B(s.dLvv.p, v * v, 1)
       .C(s.dg_oovv.p, v * v, 1, 0, 1.0, 1.0).tag("cc_dg").run(x, p, o64);
-  G(M, M, J).A(dLvo, 1, ldl).B(off<T>(Lvo0), M, o).Nhi(v, 1, v).C(s.dg_voov.p, M, 1)
-      .tag("cc_dg").run(x, p, o64);
+  G(M, M, J).A(dLvo, 1, ldl).B(s.Lkc.p, M, 1).C(s.dg_voov.p, M, 1).tag("cc_dg").run(x, p, o64);
   // derivative Fock blocks:
   //   dF = F~C - CF~ + 2 sum_K L~^K dX^K - sum_K sum_I (L~^K C)_pI L~^K_Iq,
   //   dX^K = sum_IB L~^K_IB c_BI
@@ -296,11 +338,12 @@ void mlcc_problem::ccsd_sigma2_t(const double *c1, const double *c2, const doubl
       .tag("cc_dF").run(x, p, true);
   s.Pv.ensure(al, J * v * O * sizeof(T));
   s.Po.ensure(al, J * o * O * sizeof(T));
-  G(v, O, V, 1, J).A(lt + O * n + O, n, 1, 0, n2).B(c1t, O, 1, 0, 0).C(s.Pv.p, O, 1, v * O)
+  G(v, O, V, 1, J).A(lt + O * n + O, n, 1, 0, n2).B(c1tt, 1, V, 0, 0).C(s.Pv.p, O, 1, v * O)
       .tag("cc_dF").run(x, p, o64);
-  G(v, v, O, J).A(s.Pv.p, O, 1, v * O).B(lt + O, n, 1, n2).C(dFvv64, v, 1, 0, -1.0, 1.0)
-      .tag("cc_dF").run(x, p, true);
-  G(o, O, V, 1, J).A(lt + O, n, 1, 0, n2).B(c1t, O, 1, 0, 0).C(s.Po.p, O, 1, o * O)
+  // L~_Ib = L_Ib = L_bI (the ov block does not depend on t1), read with I contiguous
+  G(v, v, O, J).A(s.Pv.p, O, 1, v * O).B(off<T>(L, O * n), 1, n, n2)
+      .C(dFvv64, v, 1, 0, -1.0, 1.0).tag("cc_dF").run(x, p, true);
+  G(o, O, V, 1, J).A(lt + O, n, 1, 0, n2).B(c1tt, 1, V, 0, 0).C(s.Po.p, O, 1, o * O)
       .tag("cc_dF").run(x, p, o64);
   G(o, o, O, J).A(s.Po.p, O, 1, o * O).B(lt, n, 1, n2).C(dFoo64, o, 1, 0, -1.0, 1.0)
       .tag("cc_dF").run(x, p, true);

@@ -4,8 +4,10 @@
 //   C_z[m][n] = alpha * sum_{r<R} sum_{k<K} A_zr[m][k] * B_zr[k][n] + beta * Cin_z[m][n]
 //
 // Design
-// * 256 threads = 4 waves in a 2x2 grid; a block owns a BM x BN tile of C,
-//   each wave a (BM/2) x (BN/2) sub-tile of 16 x 16 fragments.
+// * A block owns a BM x BN tile of C.  Its waves form a WM x WN grid, two
+//   waves along a tile dimension that is a multiple of 32 and one along any
+//   other multiple of 16 (the menus below hold only the former); each wave
+//   owns a (BM/WM) x (BN/WN) sub-tile of 16 x 16 fragments.
 // * FP32: v_mfma_f32_16x16x4f32, one instruction per 16x16x4 fragment product.
 //   Lane l holds A[i = l%16][k], B[k][j = l%16] with k-group l/16; output
 //   element e of lane l is D[4*(l/16) + e][l%16].
@@ -14,7 +16,9 @@
 //   A_b[i][k] and B_b[k][i]; lane 16*i + 4*b + j receives D_b[i][j] (measured
 //   with a one-wave probe).  A 16x16x4 fragment product is four instructions:
 //   in instruction r the B fragment is read with its 16 columns rotated by 4r,
-//   so block b multiplies rows 4b..4b+3 with columns 4((b+r)%4)..+3.
+//   so block b multiplies rows 4b..4b+3 with columns 4((b+r)%4)..+3.  When a
+//   wave has fewer A fragments than B fragments the roles swap (A is read
+//   rotated), so the rotated reads are the fewer ones.
 // * Within one k-step of BK, k-group g of a fragment covers k = g*S .. g*S+S-1
 //   (S = BK/4), the same assignment for A and B, so a lane's k-values are
 //   contiguous.
@@ -35,6 +39,7 @@
 //   tiles, which share operand rows in that XCD's L2.
 #pragma once
 
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -54,8 +59,14 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d2u __attribute__((ext_vector_type(2), aligned(8)));
 typedef float f4u __attribute__((ext_vector_type(4), aligned(4)));
 
-constexpr int kThreads = 256;
 constexpr int kXcd = 8;
+
+// wave grid and thread count of a BM x BN tile
+template <int BM, int BN> struct WaveGrid {
+  static constexpr int WM = BM % 32 == 0 ? 2 : 1, WN = BN % 32 == 0 ? 2 : 1;
+  static constexpr int NT = 64 * WM * WN;
+  static_assert(BM % (16 * WM) == 0 && BN % (16 * WN) == 0, "tile");
+};
 
 struct KParams {
   GemmArgs a;
@@ -91,17 +102,18 @@ template <> struct Tr<float> {
 // global memory as units of VEC contiguous elements.  KMAJ: the operand's
 // contiguous global dimension is its output dimension (m or n), so LDS holds
 // [k][m]; otherwise LDS holds [m][k].
-template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
+template <typename T, int BMN, bool KMAJ, bool VONLY, int NT> struct Stage {
   static constexpr int BK = Tr<T>::BK, VEC = Tr<T>::VEC;
   static constexpr int PK = 16 / (int)sizeof(T);      // [m][k] rows: +16 bytes
   static constexpr int PM = sizeof(T) == 8 ? 4 : 2;   // [k][m] rows: see the bank note
   static constexpr int ROWS = KMAJ ? BK : BMN;
   static constexpr int LEN = KMAJ ? BMN + PM : BK + PK;
-  static constexpr int U = BMN * BK / VEC / kThreads;  // units per thread
-  static_assert(U * VEC * kThreads == BMN * BK, "tile");
+  static constexpr int U = BMN * BK / VEC / NT;  // units per thread
+  static_assert(U * VEC * NT == BMN * BK, "tile");
   // Bank note: with k = g*S + s, the four k-groups of a [k][m] fragment read
   // sit S rows apart; S * LEN * sizeof(T) is 64 mod 256 (FP32) or 128 mod 256
-  // (FP64), so one pass of a ds_read touches disjoint banks.
+  // (FP64) for every BMN that is a multiple of 8, so one pass of a ds_read
+  // touches disjoint banks.
 
   int64_t off[U];   // element offset of the unit's first element (valid rows)
   int row[U], col[U];
@@ -121,7 +133,7 @@ template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
     if (KMAJ) base_ok = mn0 + VEC <= n_mn && (lo <= 0 || (mn0 % lo) + VEC <= lo);
 #pragma unroll
     for (int e = 0; e < U; ++e) {
-      const int u = tid + e * kThreads;
+      const int u = tid + e * NT;
       int mn;
       if (KMAJ) {
         row[e] = u / (BMN / VEC);
@@ -162,7 +174,7 @@ template <typename T, int BMN, bool KMAJ, bool VONLY> struct Stage {
     const int64_t off0 = two_level(mn0, lo, s_mn, s_hi);
 #pragma unroll
     for (int e = 0; e < U; ++e) {
-      const int u = tid + e * kThreads;
+      const int u = tid + e * NT;
       int mn;
       if (KMAJ) {
         row[e] = u / (BMN / VEC);
@@ -274,21 +286,29 @@ __device__ __forceinline__ void frag(T (&f)[Tr<T>::S], const T (*L)[LEN], int mn
 }
 
 // output position of accumulator element e of lane l within a 16x16 fragment
-template <typename T> struct OutMap;
-template <> struct OutMap<float> {
+template <typename T, bool ROTA> struct OutMap;
+template <> struct OutMap<float, false> {
   static __device__ __forceinline__ int row(int l, int e) { return 4 * (l >> 4) + e; }
   static __device__ __forceinline__ int col(int l, int) { return l & 15; }
 };
-template <> struct OutMap<double> {
+template <> struct OutMap<double, false> {
   static __device__ __forceinline__ int row(int l, int) { return 4 * ((l & 15) >> 2) + (l >> 4); }
   static __device__ __forceinline__ int col(int l, int r) {
     return 4 * ((((l & 15) >> 2) + r) & 3) + (l & 3);
   }
 };
+// A read rotated: block b of instruction r multiplies rows 4((b+r)%4)..+3
+// with columns 4b..4b+3
+template <> struct OutMap<double, true> {
+  static __device__ __forceinline__ int row(int l, int r) {
+    return 4 * ((((l & 15) >> 2) + r) & 3) + (l >> 4);
+  }
+  static __device__ __forceinline__ int col(int l, int) { return 4 * ((l & 15) >> 2) + (l & 3); }
+};
 
 // Write a block's accumulators: alpha * acc + beta * Cin into C, or the raw
 // partial sums into the split workspace.
-template <typename T, typename TC, int FM, int FN, int WTM, int WTN, typename Acc4>
+template <typename T, typename TC, int FM, int FN, int WTM, int WTN, bool ROTA, typename Acc4>
 __device__ __forceinline__ void epilogue(const KParams &kp, const Acc4 (&acc)[FM][FN], int64_t m0,
                                          int64_t n0, int64_t z, int split, int lane, int wm,
                                          int wn) {
@@ -300,7 +320,7 @@ __device__ __forceinline__ void epilogue(const KParams &kp, const Acc4 (&acc)[FM
   for (int j = 0; j < FN; ++j)
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T>::col(lane, e);
+      const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T, ROTA>::col(lane, e);
       cok[j][e] = col < p.N;
       coff[j][e] = cok[j][e] ? two_level(col, p.Nlo, p.sCn, p.sCn_hi) : 0;
     }
@@ -311,7 +331,7 @@ __device__ __forceinline__ void epilogue(const KParams &kp, const Acc4 (&acc)[FM
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T>::row(lane, e);
+        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T, ROTA>::row(lane, e);
         if (row >= p.M) continue;
         const int64_t roff = two_level(row, p.Mlo, p.sCm, p.sCm_hi);
 #pragma unroll
@@ -329,11 +349,11 @@ __device__ __forceinline__ void epilogue(const KParams &kp, const Acc4 (&acc)[FM
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T>::row(lane, e);
+        const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T, ROTA>::row(lane, e);
         if (row >= p.M) continue;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
-          const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T>::col(lane, e);
+          const int64_t col = n0 + wn * WTN + j * 16 + OutMap<T, ROTA>::col(lane, e);
           if (col < p.N) wk[row * p.N + col] = acc[i][j][e];
         }
       }
@@ -341,12 +361,13 @@ __device__ __forceinline__ void epilogue(const KParams &kp, const Acc4 (&acc)[FM
 }
 
 template <typename T, typename TC, int BM, int BN, bool AKM, bool BKN, bool VONLY>
-__global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
-  constexpr int S = Tr<T>::S, VEC = Tr<T>::VEC;
-  constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
-  static_assert(FM * 32 == BM && FN * 32 == BN, "tile");
-  typedef Stage<T, BM, AKM, VONLY> SA;
-  typedef Stage<T, BN, BKN, VONLY> SB;
+__global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm(KParams kp) {
+  typedef WaveGrid<BM, BN> WG;
+  constexpr int S = Tr<T>::S, VEC = Tr<T>::VEC, NT = WG::NT;
+  constexpr int WTM = BM / WG::WM, WTN = BN / WG::WN, FM = WTM / 16, FN = WTN / 16;
+  constexpr bool ROTA = sizeof(T) == 8 && FM < FN;
+  typedef Stage<T, BM, AKM, VONLY, NT> SA;
+  typedef Stage<T, BN, BKN, VONLY, NT> SB;
   __shared__ __attribute__((aligned(16))) T As[2][SA::ROWS][SA::LEN];
   __shared__ __attribute__((aligned(16))) T Bs[2][SB::ROWS][SB::LEN];
 
@@ -363,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
   const int split = (int)(zs % kp.splits);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1, g = lane >> 4, l16 = lane & 15;
+  const int wm = wave / WG::WN, wn = wave % WG::WN, g = lane >> 4, l16 = lane & 15;
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t total = p.R * kp.ktiles;
   const int64_t s_begin = split * kp.steps_per_split;
@@ -427,11 +448,11 @@ __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
   for (int64_t step = s_begin; step < s_end; ++step) {
     const bool more = step + 1 < s_end;
     if (more) load_next();
-    T af[FM][S];
-#pragma unroll
-    for (int i = 0; i < FM; ++i)
-      frag<T, SA::LEN, AKM>(af[i], As[cur], wm * WTM + i * 16 + l16, g);
     if constexpr (sizeof(T) == 4) {
+      T af[FM][S];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        frag<T, SA::LEN, AKM>(af[i], As[cur], wm * WTM + i * 16 + l16, g);
       T bf[FN][S];
 #pragma unroll
       for (int j = 0; j < FN; ++j)
@@ -443,7 +464,28 @@ __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
 #pragma unroll
           for (int j = 0; j < FN; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][s], bf[j][s], acc[i][j], 0, 0, 0);
+    } else if constexpr (ROTA) {
+      T bf[FN][S];
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        frag<T, SB::LEN, BKN>(bf[j], Bs[cur], wn * WTN + j * 16 + l16, g);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          T af[S];
+          frag<T, SA::LEN, AKM>(af, As[cur], wm * WTM + i * 16 + ((l16 + 4 * r) & 15), g);
+#pragma unroll
+          for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[s], bf[j][s], acc[i][j][r], 0, 0, 0);
+        }
     } else {
+      T af[FM][S];
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+        frag<T, SA::LEN, AKM>(af[i], As[cur], wm * WTM + i * 16 + l16, g);
 #pragma unroll
       for (int j = 0; j < FN; ++j)
 #pragma unroll
@@ -465,7 +507,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm(KParams kp) {
     cur ^= 1;
   }
 
-  epilogue<T, TC, FM, FN, WTM, WTN>(kp, acc, m0, n0, z, split, lane, wm, wn);
+  epilogue<T, TC, FM, FN, WTM, WTN, ROTA>(kp, acc, m0, n0, z, split, lane, wm, wn);
 }
 
 
@@ -480,12 +522,13 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 
 template <typename TC, int BM, int BN>
-__global__ __launch_bounds__(kThreads) void k_gemm_split(KParams kp) {
+__global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams kp) {
+  typedef WaveGrid<BM, BN> WG;
   constexpr int BK = Tr<float>::BK, VEC = Tr<float>::VEC, LEN = BK + 8;  // 80-byte rows
-  constexpr int WTM = BM / 2, WTN = BN / 2, FM = WTM / 16, FN = WTN / 16;
-  static_assert(FM * 32 == BM && FN * 32 == BN && BK == 32 && VEC == 4, "tile");
-  typedef Stage<float, BM, false, true> SA;
-  typedef Stage<float, BN, false, true> SB;
+  constexpr int WTM = BM / WG::WM, WTN = BN / WG::WN, FM = WTM / 16, FN = WTN / 16;
+  static_assert(BK == 32 && VEC == 4, "tile");
+  typedef Stage<float, BM, false, true, WG::NT> SA;
+  typedef Stage<float, BN, false, true, WG::NT> SB;
   __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][LEN];
   __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][LEN];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][LEN];
@@ -502,7 +545,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_split(KParams kp) {
   const int64_t z = zs / kp.splits;
   const int split = (int)(zs % kp.splits);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1, g = lane >> 4, l16 = lane & 15;
+  const int wm = wave / WG::WN, wn = wave % WG::WN, g = lane >> 4, l16 = lane & 15;
   const int64_t m0 = tm * BM, n0 = tn * BN;
   const int64_t total = p.R * kp.ktiles;
   const int64_t s_begin = split * kp.steps_per_split;
@@ -593,7 +636,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_split(KParams kp) {
     __syncthreads();
     cur ^= 1;
   }
-  epilogue<float, TC, FM, FN, WTM, WTN>(kp, acc, m0, n0, z, split, lane, wm, wn);
+  epilogue<float, TC, FM, FN, WTM, WTN, false>(kp, acc, m0, n0, z, split, lane, wm, wn);
 }
 
 template <typename TA, typename TC>
@@ -672,7 +715,7 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
   kp.vec_a = vec_ok(akm ? a.sAm : a.sAk);
   kp.vec_b = vec_ok(bkn ? a.sBn : a.sBk);
-  const dim3 grid((unsigned)(kp.per_xcd * kXcd));
+  const dim3 grid((unsigned)(kp.per_xcd * kXcd)), block(WaveGrid<BM, BN>::NT);
   std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
   if (ex.prof && ex.prof->on) {
     ev = ex.prof->next();
@@ -681,15 +724,15 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   if constexpr (SPLIT) {
     static_assert(sizeof(T) == 4, "split products take FP32 operands");
     MLCC_REQUIRE(!akm && !bkn, MLCC_E_ARG, "gemm: split products need k-contiguous operands");
-    hipLaunchKernelGGL((k_gemm_split<TC, BM, BN>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm_split<TC, BM, BN>), grid, block, 0, ex.stream, kp);
   } else if (akm && bkn)
-    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, true, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, true, VONLY>), grid, block, 0, ex.stream, kp);
   else if (akm)
-    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, false, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, false, VONLY>), grid, block, 0, ex.stream, kp);
   else if (bkn)
-    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, true, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, true, VONLY>), grid, block, 0, ex.stream, kp);
   else
-    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, false, VONLY>), grid, dim3(kThreads), 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, false, false, VONLY>), grid, block, 0, ex.stream, kp);
   MLCC_HIP(hipGetLastError());
   if (ev.first) {
     MLCC_HIP(hipEventRecord(ev.second, ex.stream));
@@ -704,8 +747,11 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   }
 }
 
-// The tile menus: (BM, BN) multiples of 32; the general (element-wise
-// fallback) kernel is built for fewer shapes.
+// The tile menus: (BM, BN) multiples of 32 (two waves along each
+// dimension); the general (element-wise fallback) kernel is built for fewer
+// shapes.  Tiles of 80 (one wave along that dimension, FM or FN = 5) were
+// measured slower on every contraction here: at one wave per SIMD the MFMA
+// pipeline idles more than the padding they save.
 #define MLCC_GEMM_TILES_GENERAL(X) \
   X(128, 128) X(128, 64) X(64, 128) X(64, 64) X(128, 32) X(32, 128) X(64, 32) X(32, 64) X(32, 32) \
   X(96, 160)
@@ -724,43 +770,49 @@ struct Tile {
 };
 
 // Pick the tile with the lowest modelled time: padded MACs, an operand-load
-// overhead that grows as the tile shrinks, the number of rounds of ~512
-// resident blocks, and the split reduction's traffic.
+// overhead that grows as the tile shrinks, the number of rounds of ~2048
+// resident waves, and the split reduction's traffic.
 template <typename T, typename TC>
 void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles) {
   constexpr int BK = Tr<T>::BK;
   const int64_t steps = a.R * cdiv(a.K, BK);
-  auto splits_for = [&](int64_t blocks) {
+  auto waves_of = [](int bm, int bn) { return (bm % 32 == 0 ? 2 : 1) * (bn % 32 == 0 ? 2 : 1); };
+  auto splits_for = [&](int64_t blocks, int nw) {
+    const int64_t target = 2048 / nw;
     int s = 1;
-    if (blocks < 512 && steps >= 8) {
-      s = (int)std::min<int64_t>(cdiv(512, blocks), steps / 4);
+    if (blocks < target && steps >= 8) {
+      s = (int)std::min<int64_t>(cdiv(target, blocks), steps / 4);
       s = std::max(1, std::min(s, 128));
     }
     return s;
   };
-  static const char *forced = std::getenv("MLCC_GEMM_TILE");
-  int fm = 0, fn = 0;
-  if (forced && std::sscanf(forced, "%dx%d", &fm, &fn) != 2) fm = fn = 0;
+  int fm = g_force_bm.load(std::memory_order_relaxed);
+  int fn = g_force_bn.load(std::memory_order_relaxed);
+  bool listed = false;
+  for (int t = 0; t < ntiles; ++t) listed = listed || (tiles[t].bm == fm && tiles[t].bn == fn);
+  if (!listed) fm = fn = 0;  // a forced tile this menu lacks: the cost model decides
   int best = -1;
   double best_cost = 0.0;
   for (int t = 0; t < ntiles; ++t) {
-    const int bm = tiles[t].bm, bn = tiles[t].bn;
+    const int bm = tiles[t].bm, bn = tiles[t].bn, nw = waves_of(bm, bn);
     if (fm > 0 && (bm != fm || bn != fn)) continue;
     const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
-    const int s = splits_for(blocks);
-    const double rounds = std::ceil((double)(blocks * s) / 512.0);
+    const int s = splits_for(blocks, nw);
+    const double rounds = std::ceil((double)(blocks * s * nw) / 2048.0);
     const double f = 1.0 + 16.0 * (1.0 / bm + 1.0 / bn);
     const double per_block = (double)bm * bn * ((double)cdiv(steps, s) * BK * f + 16.0);
-    double cost = rounds * per_block;
+    double cost = rounds * per_block * 4.0 / nw;
     if (s > 1) cost += 2.0 * (double)s * a.Z * a.M * a.N;
     if (best < 0 || cost < best_cost) {
       best = t;
       best_cost = cost;
     }
   }
-  if (best < 0) best = 0;
-  const int64_t blocks = cdiv(a.M, tiles[best].bm) * cdiv(a.N, tiles[best].bn) * a.Z;
-  tiles[best].fn(ex, a, splits_for(blocks));
+  const int bm = tiles[best].bm, bn = tiles[best].bn;
+  g_last_bm.store(bm, std::memory_order_relaxed);
+  g_last_bn.store(bn, std::memory_order_relaxed);
+  const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
+  tiles[best].fn(ex, a, splits_for(blocks, waves_of(bm, bn)));
 }
 
 }  // namespace gk

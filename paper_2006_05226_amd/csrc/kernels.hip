@@ -125,24 +125,27 @@ __global__ void k_mlcc2_s_u(int o, int v, const TG *g, const double *eps_ai, dou
 }
 
 template <typename TU>
-__global__ void k_u_of(int o, int v, const double *x, TU *u, int nz, int64_t ldx, int64_t ldu) {
+__global__ void k_u_of(int o, int v, const double *x, TU *u, int nz, int64_t ldx, int64_t ldu,
+                       bool occ_rows) {
   const int64_t M = (int64_t)o * v, MM = M * M;
   GRID_STRIDE(tt, MM * nz) {
     const int64_t z = tt / MM, t = tt - z * MM;
     const int64_t ai = t / M, bj = t - ai * M;
     const int64_t a = ai / o, i = ai - a * o, b = bj / o, j = bj - b * o;
     const double *xz = x + z * ldx;
-    u[z * ldu + t] = (TU)(2.0 * xz[t] - xz[(a * o + j) * M + (b * o + i)]);
+    const int64_t row = occ_rows ? i * v + a : ai;
+    u[z * ldu + row * M + bj] = (TU)(2.0 * xz[t] - xz[(a * o + j) * M + (b * o + i)]);
   }
 }
 
 template <typename TS>
 __global__ void k_acc3d(int64_t nz, int64_t rows, int64_t cols, double alpha, const TS *src,
-                        int64_t s_z, int64_t s_r, double *dst, int64_t d_z, int64_t d_r) {
+                        int64_t s_z, int64_t s_r, int64_t s_c, double *dst, int64_t d_z,
+                        int64_t d_r) {
   const int64_t per = rows * cols;
   GRID_STRIDE(t, nz * per) {
     const int64_t z = t / per, rc = t - z * per, r = rc / cols, c = rc - r * cols;
-    dst[z * d_z + r * d_r + c] += alpha * (double)src[z * s_z + r * s_r + c];
+    dst[z * d_z + r * d_r + c] += alpha * (double)src[z * s_z + r * s_r + c * s_c];
   }
 }
 
@@ -405,20 +408,21 @@ void mlcc2_s_u(Exec &ex, int o, int v, const TG *g, const double *eps_ai, double
 }
 
 template <typename TU>
-void u_of(Exec &ex, int o, int v, const double *x, TU *u, int nz, int64_t ldx, int64_t ldu) {
+void u_of(Exec &ex, int o, int v, const double *x, TU *u, int nz, int64_t ldx, int64_t ldu,
+          bool occ_rows) {
   const int64_t M = (int64_t)o * v;
   if (M == 0 || nz <= 0) return;
   hipLaunchKernelGGL((k_u_of<TU>), dim3(blocks_for(M * M * nz)), dim3(TPB), 0, ex.stream, o, v, x,
-                     u, nz, ldx, ldu);
+                     u, nz, ldx, ldu, occ_rows);
   MLCC_HIP(hipGetLastError());
 }
 
 template <typename TS>
 void acc3d(Exec &ex, int64_t nz, int64_t rows, int64_t cols, double alpha, const TS *src,
-           int64_t s_z, int64_t s_r, double *dst, int64_t d_z, int64_t d_r) {
+           int64_t s_z, int64_t s_r, int64_t s_c, double *dst, int64_t d_z, int64_t d_r) {
   if (nz <= 0 || rows <= 0 || cols <= 0) return;
   hipLaunchKernelGGL((k_acc3d<TS>), dim3(blocks_for(nz * rows * cols)), dim3(TPB), 0, ex.stream,
-                     nz, rows, cols, alpha, src, s_z, s_r, dst, d_z, d_r);
+                     nz, rows, cols, alpha, src, s_z, s_r, s_c, dst, d_z, d_r);
   MLCC_HIP(hipGetLastError());
 }
 
@@ -539,12 +543,13 @@ template void mlcc2_s_u<double, double>(Exec &, int, int, const double *, const 
                                         double *);
 template void mlcc2_s_u<double, float>(Exec &, int, int, const double *, const double *, double *,
                                        float *);
-template void u_of<double>(Exec &, int, int, const double *, double *, int, int64_t, int64_t);
-template void u_of<float>(Exec &, int, int, const double *, float *, int, int64_t, int64_t);
+template void u_of<double>(Exec &, int, int, const double *, double *, int, int64_t, int64_t,
+                           bool);
+template void u_of<float>(Exec &, int, int, const double *, float *, int, int64_t, int64_t, bool);
 template void acc3d<double>(Exec &, int64_t, int64_t, int64_t, double, const double *, int64_t,
-                            int64_t, double *, int64_t, int64_t);
+                            int64_t, int64_t, double *, int64_t, int64_t);
 template void acc3d<float>(Exec &, int64_t, int64_t, int64_t, double, const float *, int64_t,
-                           int64_t, double *, int64_t, int64_t);
+                           int64_t, int64_t, double *, int64_t, int64_t);
 template void sym_plus_diag<double>(Exec &, int64_t, const double *, int64_t, const double *,
                                     const double *, double *, int, int64_t, int64_t, int64_t);
 template void sym_plus_diag<float>(Exec &, int64_t, const float *, int64_t, const double *,

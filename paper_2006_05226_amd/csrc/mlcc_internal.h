@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
 #include <cstdio>
 #include <map>
@@ -155,6 +156,12 @@ struct GemmArgs {
 // accumulator written out as double).
 void gemm(Exec &ex, Prec prec, const GemmArgs &a, bool out_f64);
 
+namespace gk {
+// Tile override (parity tests, tuning): a forced bm x bn is used by every
+// call whose menu has it; the tile of the last dispatched call is kept.
+extern std::atomic<int> g_force_bm, g_force_bn, g_last_bm, g_last_bn;
+}
+
 // ---------------------------------------------------------------------------
 // element-wise and reduction kernels (kernels.hip)
 // ---------------------------------------------------------------------------
@@ -183,10 +190,11 @@ void dot_mixed(Exec &ex, int64_t n, const TA *x, const TB *y, double *res);
 template <typename TG, typename TU>
 void mlcc2_s_u(Exec &ex, int o, int v, const TG *g, const double *eps_ai, double *s, TU *u);
 // u = 2x - x(i<->j) of full doubles arrays (TU output); nz arrays, x[z] at
-// x + z*ldx and u[z] at u + z*ldu
+// x + z*ldx and u[z] at u + z*ldu.  occ_rows: row (a,i) of u is stored at
+// row index i*v + a (columns keep the pair order b*o + j).
 template <typename TU>
 void u_of(Exec &ex, int o, int v, const double *x, TU *u, int nz = 1, int64_t ldx = 0,
-          int64_t ldu = 0);
+          int64_t ldu = 0, bool occ_rows = false);
 // out = G + G^T + d .* c  (M x M, f64 out); G type TG; nz arrays with
 // G[z] at G + z*sGz, c[z] at c + z*ldc, out[z] at out + z*ldo
 template <typename TG>
@@ -197,10 +205,10 @@ void sym_plus_diag(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *
 template <typename TG, typename TO>
 void sym_div(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
              TO *out, int nz = 1, int64_t sGz = 0, int64_t ldo = 0);
-// dst[z*d_z + r*d_r + c] += alpha * src[z*s_z + r*s_r + c]
+// dst[z*d_z + r*d_r + c] += alpha * src[z*s_z + r*s_r + c*s_c]
 template <typename TS>
 void acc3d(Exec &ex, int64_t nz, int64_t rows, int64_t cols, double alpha, const TS *src,
-           int64_t s_z, int64_t s_r, double *dst, int64_t d_z, int64_t d_r);
+           int64_t s_z, int64_t s_r, int64_t s_c, double *dst, int64_t d_z, int64_t d_r);
 // Delta t = -Omega / denominators
 void qn_step_singles(Exec &ex, int V, int O, const double *eps, const double *om, double *t);
 void qn_step_doubles(Exec &ex, int64_t M, const double *eps_ai, const double *om, double *t);

@@ -467,13 +467,14 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   dLai.ensure(al, (size_t)J * b * M * sizeof(T));
   Gm.ensure(al, (size_t)M * b * M * sizeof(double));
   // one launch per term: rows (K, a) x columns (vec, i), then rows (vec, a) x
-  // columns (K, i)
+  // columns (K, i) (MLCC2: K the low part of the two-level index)
   if (model == MLCC_MLCC2) {
-    // pair-major dL~: dLai[vec][ai][K]
-    G(J * v, b * o, V).A(lt + O * n + O, n, 1).Mhi(v, n2, 1).B(ctt, 1, V).Nhi(o, n1, M * J)
-        .C(dLai.p, o * J, J).tag("dLai").run(x, p, o64);
-    G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M * J).B(loot, 1, O).Nhi(o, O * O, 1)
-        .C(dLai.p, o * J, J, 0, -1.0, 1.0).tag("dLai").run(x, p, o64);
+    // pair-major dL~: dLai[vec][ai][K]; K is the low part of the two-level
+    // output index, so the output rows / columns of a tile are contiguous
+    G(J * v, b * o, V).A(lt + O * n + O, n2, 1).Mhi(J, n, o * J).B(ctt, 1, V).Nhi(o, n1, M * J)
+        .C(dLai.p, 1, J).tag("dLai").run(x, p, o64);
+    G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M * J).B(loot, 1, O * O).Nhi(J, O, J)
+        .C(dLai.p, o * J, 1, 0, -1.0, 1.0).tag("dLai").run(x, p, o64);
     G(M, b * M, J).A(off<T>(LaiT), J, 1).B(dLai.p, 1, J).C(Gm.p, b * M, 1)
         .tag("sigma2_LdL").run(x, p, true);
   } else {
@@ -509,22 +510,23 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
     c2ld = M * M;
   }
   if (!c2base) return;
-  // doubles -> singles: the Omega_1 doubles terms with u = 2 c2 - c2(i<->j)
+  // doubles -> singles: the Omega_1 doubles terms with u = 2 c2 - c2(i<->j).
+  // The rows of u(c2) are stored occupied-major (row (c,j) at j*v + c), so
+  // Zc^K[vec][j][c] = sum_bk L_bk^K u_cj,bk has c contiguous, the reduction
+  // index of the A1 term.
   ut.ensure(al, (size_t)b * M * M * sizeof(T));
   Zc.ensure(al, (size_t)(J + 1) * b * M * sizeof(T));
-  k::u_of<T>(x, d.o, d.v, c2base, off<T>(ut), (int)b, c2ld, M * M);
+  k::u_of<T>(x, d.o, d.v, c2base, off<T>(ut), (int)b, c2ld, M * M, true);
   // F~_jb in the spare row J of L_vo: row J of Zc is sum_bj u_aibj F~_jb
   k::pack2d_t<T, double>(x, off<T>(Lvo0, J * M), F + O, 1, 0, o, v, n);
-  // u(c2) is symmetric under (ai) <-> (bj) (so are the doubles), so it is
-  // read with the reduction index bj contiguous
   G(J + 1, b * M, M).A(off<T>(Lvo0), M, 1).B(ut.p, 1, M).Nhi(M, M * M, M).C(Zc.p, b * M, 1)
       .tag("Zc_uL").run(x, p, o64);
-  G(V, b * o, v, J).A(lt + O * n + O, n, 1, n2).B(Zc.p, o, 1, b * M).Nhi(o, M, ld)
+  G(V, b * o, v, J).A(lt + O * n + O, n, 1, n2).B(Zc.p, 1, v, b * M).Nhi(o, M, ld)
       .C(sigma, O, 1, 0, 1.0, 1.0).tag("d2s_A1").run(x, p, true);
-  G(b * v, O, o, J).A(Zc.p, o, 1, b * M).Mhi(v, M, ld).B(lt, n, 1, n2)
-      .C(sigma, O, 1, 0, -1.0, 1.0).tag("d2s_B1").run(x, p, true);
+  G(O, v, o, J, b).A(lt, 1, n, n2, 0).B(Zc.p, v, 1, b * M, M).C(sigma, 1, O, ld, -1.0, 1.0)
+      .tag("d2s_B1").run(x, p, true);
   // sigma_ai += sum_bj u_aibj F~_jb  (row J of Zc)
-  k::acc3d<T>(x, b, v, o, 1.0, off<T>(Zc, J * b * M), M, o, sigma, ld, O);
+  k::acc3d<T>(x, b, v, o, 1.0, off<T>(Zc, J * b * M), M, 1, v, sigma, ld, O);
 }
 
 static constexpr int kMaxBatch = 8;

@@ -70,7 +70,7 @@ EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "ml
            "mlcc_jacobian_transform", "mlcc_jacobian_transform_eff", "mlcc_davidson_solve",
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
            "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_debug_get", "mlcc_profile_enable",
-           "mlcc_profile_get"]
+           "mlcc_profile_get", "mlcc_gemm_tile"]
 
 _lib = None
 
@@ -111,6 +111,7 @@ def load(path: str = LIB_PATH):
         "mlcc_debug_get": (i32, [vp, i32, vp]),
         "mlcc_profile_enable": (i32, [vp, i32]),
         "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
+        "mlcc_gemm_tile": (i32, [i32, i32, P(i32)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -182,6 +183,14 @@ class Context:
         c3 = (C.c_int64 * 3)(*sC)
         return self.check(self.lib.mlcc_gemm(self.h, prec, M, N, K, R, Z, alpha, _ptr(A), a4,
                                              _ptr(B), b4, beta, _ptr(Cm), c3))
+
+    def gemm_tile(self, bm=0, bn=0):
+        """Force the bm x bn output tile on later engine calls whose tile menu
+        has it (0, 0: the cost model picks); returns the tile of the previous
+        engine call."""
+        last = (C.c_int32 * 2)()
+        self.check(self.lib.mlcc_gemm_tile(bm, bn, last))
+        return (last[0], last[1])
 
     def profile(self, on=True):
         self.check(self.lib.mlcc_profile_enable(self.h, 1 if on else 0))

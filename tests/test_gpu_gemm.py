@@ -204,3 +204,57 @@ def test_gemm_two_level_contiguous_rows(ctx, prec, ml):
     got = Cd.cpu().numpy().astype(np.float64).reshape(M, N)
     tol = 1e-13 if prec == "fp64" else 3e-6
     assert np.abs(got - ref).max() <= tol * (np.sqrt(K * R) + 1.0)
+
+
+# the engine's tile menus: vector-only kernel, general (element-wise) kernel,
+# split BF16 kernel
+VONLY_TILES = [(128, 128), (128, 96), (96, 128), (128, 64), (64, 128), (96, 96), (96, 64),
+               (64, 96), (64, 64), (128, 32), (32, 128), (96, 32), (32, 96), (64, 32), (32, 64),
+               (32, 32), (96, 160), (160, 96), (64, 160), (160, 64), (32, 160), (160, 32)]
+GENERAL_TILES = [(128, 128), (128, 64), (64, 128), (64, 64), (128, 32), (32, 128), (64, 32),
+                 (32, 64), (32, 32), (96, 160)]
+SPLIT_TILES = [(128, 128), (128, 96), (96, 128), (128, 64), (64, 128), (96, 96), (64, 64),
+               (128, 32), (32, 128), (64, 32), (32, 64), (32, 32), (96, 160), (160, 96)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("vector", [True, False])
+def test_every_tile(ctx, prec, vector):
+    """Each tile of the menus, forced, on every operand layout: ragged edges
+    in m, n (and k for the general kernel), a batch-reduced reduction split
+    over blocks.  In FP64 this covers both rotation sides of the 4x4x4
+    products (A rotated when a wave has fewer A than B fragments)."""
+    M, N, K, R = (204, 188, 76, 2) if vector else (203, 187, 77, 2)
+    rng = np.random.default_rng(5 if vector else 6)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    A = rng.standard_normal(M * K * R)
+    B = rng.standard_normal(K * N * R)
+    layouts = [("k", "k"), ("k", "n"), ("m", "k"), ("m", "n")]
+    if prec == "bf16x3":
+        layouts = [("k", "k")]
+        menu = SPLIT_TILES if vector else GENERAL_TILES
+    else:
+        menu = VONLY_TILES if vector else GENERAL_TILES
+    applied = set()
+    try:
+        for al, bl in layouts:
+            sAm, sAk = (K, 1) if al == "k" else (1, M)
+            sBk, sBn = (N, 1) if bl == "n" else (1, K)
+            sA = [sAm, sAk, M * K, 0]
+            sB = [sBk, sBn, K * N, 0]
+            ref = ref_gemm(A, sA, B, sB, M, N, K, R, 1)[0]
+            Ad = torch.tensor(A, dtype=dt, device="cuda")
+            Bd = torch.tensor(B, dtype=dt, device="cuda")
+            for bm, bn in menu:
+                ctx.gemm_tile(bm, bn)
+                Cd = torch.zeros(M * N, dtype=dt, device="cuda")
+                ctx.gemm(mlcc.PREC[prec], M, N, K, R, 1, 1.0, Ad, sA, Bd, sB, 0.0, Cd, [N, 1, 0])
+                used = ctx.gemm_tile(bm, bn)
+                if used == (bm, bn):
+                    applied.add(used)
+                got = Cd.cpu().numpy().astype(np.float64).reshape(M, N)
+                err = np.abs(got - ref).max()
+                assert err <= TOL[prec] * (np.sqrt(K * R) + 1.0), (al, bl, bm, bn, used, err)
+    finally:
+        ctx.gemm_tile(0, 0)
+    assert applied == set(menu), sorted(set(menu) - applied)
