@@ -115,10 +115,12 @@ def two_electron_fock(L, d: Dims):
     return 2.0 * coul - exch
 
 
-def core_hamiltonian(L, eps, d: Dims):
-    """One-electron integrals h implied by a canonical reference:
-    F = h + G(D_HF) = diag(eps)  =>  h = diag(eps) - G."""
-    return np.diag(eps).astype(L.dtype) - two_electron_fock(L, d)
+def core_hamiltonian(L, eps, d: Dims, fock=None):
+    """One-electron integrals h implied by the reference: F = h + G(D_HF), so
+    h = F - G with F = diag(eps) (canonical) or a given Fock matrix (e.g. the
+    semicanonical basis of Sec. 2.3, whose active-inactive blocks couple)."""
+    F = np.diag(eps).astype(L.dtype) if fock is None else np.asarray(fock, dtype=L.dtype)
+    return F - two_electron_fock(L, d)
 
 
 def hf_energy(L, eps, d: Dims):
@@ -335,9 +337,11 @@ MODELS = ("ccs", "mlcc2", "mlccsd")
 
 
 class Problem:
-    """Inputs plus the model; caches h."""
+    """Inputs plus the model; caches h.  fock: the full Fock matrix when the
+    basis is semicanonical rather than canonical (eps is then its diagonal,
+    which the denominators use)."""
 
-    def __init__(self, L, eps, d: Dims, model: str):
+    def __init__(self, L, eps, d: Dims, model: str, fock=None):
         assert model in MODELS
         self.L = np.asarray(L, dtype=np.float64)
         self.eps = np.asarray(eps, dtype=np.float64)
@@ -345,7 +349,7 @@ class Problem:
         self.model = model
         if model == "ccs":
             self.d = Dims(d.O, d.V, 0, 0)
-        self.h = core_hamiltonian(self.L, self.eps, self.d)
+        self.h = core_hamiltonian(self.L, self.eps, self.d, fock=fock)
 
     # residual in the independent variables (t1, x2)
     def omega(self, t1, x2):
