@@ -16,9 +16,9 @@
  *   block the active orbitals come first: active occupied 0..n_occ_act-1,
  *   active virtual n_occ..n_occ+n_vir_act-1.  The active-active Fock blocks are
  *   diagonal (semicanonical basis, Sec. 2.1); the library takes the MO Fock
- *   matrix to be diag(eps) and the one-electron integrals to be
- *   h = diag(eps) - G(D_HF), so that the reference is a canonical
- *   Hartree-Fock state of the Hamiltonian defined by (h, L).
+ *   matrix F to be diag(eps), or the matrix given in mlcc_problem_desc.fock,
+ *   and the one-electron integrals to be h = F - G(D_HF), so that the
+ *   reference is the Hartree-Fock state of the Hamiltonian defined by (h, L).
  * Cholesky vectors.  L[J][p][q], row major, J < n_chol, L[J][p][q] == L[J][q][p],
  *   g_pqrs = sum_J L[J][p][q] L[J][r][s] (Appendix A).
  * Singles.  t1 / omega1 / c1 / sigma1 are [n_vir][n_occ] (all orbitals).
@@ -96,6 +96,13 @@ typedef struct {
   const double *eps;              /* [n] orbital energies in the order above */
   uint32_t flags;                 /* MLCC_SYNTH_L, or 0 */
   uint64_t seed;                  /* seed of MLCC_SYNTH_L */
+  const double *fock;             /* [n][n] symmetric Fock matrix (host or device), or
+                                     NULL for diag(eps).  For a semicanonical basis
+                                     (Sec. 2.3: the Fock matrix diagonal within the
+                                     active and within the inactive orbitals, as
+                                     mlcc_cnto returns it); eps must be its diagonal,
+                                     which the denominators use.  The occupied-virtual
+                                     block must vanish (a Hartree-Fock reference). */
 } mlcc_problem_desc;
 
 /* flags: L is not read; the library draws synthetic Cholesky vectors on the
@@ -253,6 +260,40 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
                        int64_t R, int64_t Z, double alpha, const void *A, const int64_t sA[4],
                        const void *B, const int64_t sB[4], double beta, void *C,
                        const int64_t sC[3], const int64_t lvl[6]);
+
+/* ---- orbital selection ------------------------------------------------------
+ * Correlated natural transition orbitals from CCS excitation vectors (Sec. 2.3:
+ * eqs. M, N, approx_double_1, approx_double_2, select_CNTOs).  prob: a problem
+ * in the canonical (or semicanonical) basis of the full space; its L, Fock
+ * matrix and precision are used, whatever its model.  R [n_states][n_vir][n_occ]
+ * and omega [n_states]: excitation vectors and energies (for instance the r1 and
+ * omega of mlcc_davidson_solve on an MLCC_CCS problem); host or device.
+ * For each state the approximate doubles R_aibj = -gbar_aibj / ((1 +
+ * d_ai,bj)(e_a + e_b - e_i - e_j - omega)) are built over the full space;
+ * M (n_occ x n_occ) and N (n_vir x n_vir) of eqs. M and N are summed over the
+ * states.  The eigenvectors of the n_occ_act largest eigenvalues of M span the
+ * active occupied space, those of the n_vir_act largest of N the active
+ * virtual space (eq. select_CNTOs gives n_vir_act = n_vir n_occ_act / n_occ when
+ * the caller wants the paper's rule).  The active and inactive blocks are
+ * then made semicanonical: the Fock matrix diagonal within each, energies
+ * ascending.
+ * Outputs, each optional (NULL to skip):
+ *   m_eig [n_occ], n_eig [n_vir]: eigenvalues of M and N, descending (host);
+ *   C [n][n]: the rotation (row major; column p is new orbital p in the order
+ *     active occupied, inactive occupied, active virtual, inactive virtual;
+ *     block diagonal; in each column the entry of largest magnitude, the first
+ *     of equals, is positive) (host);
+ *   eps_out [n] and fock_out [n][n]: the Fock matrix in the new basis (host);
+ *   L_out [n_chol][n][n]: C^T L C in FP64 (host or device).
+ * (L_out, eps_out, fock_out) are the inputs of a multilevel problem on the new
+ * orbitals with n_occ_act / n_vir_act active (mlcc_problem_desc.fock).
+ * Device scratch: (n_vir n_occ)^2 elements of the problem's operand type, plus
+ * 3 n_chol n_vir n_occ, plus 2 n_chol n^2 when L_out is requested.
+ * MLCC_E_ARG for bad sizes or NULL R / omega; MLCC_E_OOM if the scratch does
+ * not fit; MLCC_E_NUMERIC if an eigensolver fails. */
+mlcc_status mlcc_cnto(mlcc_problem *prob, int32_t n_states, const double *R, const double *omega,
+                      int32_t n_occ_act, int32_t n_vir_act, double *m_eig, double *n_eig,
+                      double *C, double *eps_out, double *fock_out, double *L_out);
 
 /* Tile override of the contraction engine, process-wide, for parity tests
  * and tuning: later engine calls whose tile menu lists the bm x bn output tile

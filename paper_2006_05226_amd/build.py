@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmlcc.so")
 SOURCES = ["gemm_f64.hip", "gemm_f32.hip", "gemm_f32d.hip", "gemm_f64g.hip", "gemm_f32g.hip", "gemm_f32dg.hip", "gemm.hip", "kernels.hip", "synth.hip", "problem.cpp", "drivers.cpp", "dense.cpp", "api.cpp",
-           "server.cpp"]
+           "server.cpp", "cnto.cpp"]
 ARCH = os.environ.get("MLCC_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed FP32 instructions in device code
@@ -43,7 +43,9 @@ def build(verbose=True) -> str:
     with ThreadPoolExecutor(jobs) as pool:
         objs = list(pool.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    # rocSOLVER (symmetric eigenproblems of the orbital selection) and rocBLAS
+    cmd = [_hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-L/opt/rocm/lib",
+           "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

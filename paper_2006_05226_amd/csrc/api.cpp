@@ -517,6 +517,31 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
   });
 }
 
+mlcc_status mlcc_cnto(mlcc_problem *P, int32_t n_states, const double *R, const double *omega,
+                      int32_t n_occ_act, int32_t n_vir_act, double *m_eig, double *n_eig,
+                      double *C, double *eps_out, double *fock_out, double *L_out) {
+  if (!P) return MLCC_E_ARG;
+  return guarded(P->ctx, [&]() -> mlcc_status {
+    MLCC_REQUIRE(R && omega, MLCC_E_ARG, "NULL argument");
+    MLCC_REQUIRE(n_states >= 1 && n_states <= P->d.n1, MLCC_E_ARG, "bad number of states");
+    MLCC_REQUIRE(n_occ_act >= 0 && n_occ_act <= P->d.O && n_vir_act >= 0 && n_vir_act <= P->d.V,
+                 MLCC_E_ARG, "bad active sizes");
+    MLCC_HIP(hipSetDevice(P->ctx->device));
+    const int64_t n1 = P->d.n1;
+    In Rin(*P, R, n_states * n1);
+    std::vector<double> w(n_states);
+    if (is_device_ptr(omega)) {
+      MLCC_HIP(hipMemcpy(w.data(), omega, n_states * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+      std::copy(omega, omega + n_states, w.begin());
+    }
+    for (double x : w) MLCC_REQUIRE(std::isfinite(x), MLCC_E_NUMERIC, "non-finite omega");
+    P->cnto(n_states, Rin.p, w.data(), n_occ_act, n_vir_act, m_eig, n_eig, C, eps_out, fock_out,
+            L_out, L_out && is_device_ptr(L_out));
+    return MLCC_OK;
+  });
+}
+
 mlcc_status mlcc_gemm_tile(int32_t bm, int32_t bn, int32_t last[2]) {
   if (bm < 0 || bn < 0) return MLCC_E_ARG;
   if (last) {

@@ -185,10 +185,21 @@ void mlcc_problem::setup(const mlcc_problem_desc &desc) {
   const uint64_t *sp = synth ? &desc.seed : nullptr;
   if (prec == MLCC_FP64) setup_t<double>(desc.L, ldev, sp);
   else setup_t<float>(desc.L, ldev, sp);
-  // h += diag(eps)  (the setup above accumulated -G into a zeroed h)
-  hipLaunchKernelGGL(k_add_diag, dim3(64), dim3(256), 0, x.stream, (int64_t)d.n,
-                     eps.as<double>(), h.as<double>());
-  MLCC_HIP(hipGetLastError());
+  // h += F  (the setup above accumulated -G into a zeroed h): diag(eps), or
+  // the given Fock matrix (kept for mlcc_cnto)
+  if (desc.fock) {
+    fock.alloc(al, d.n2 * sizeof(double));
+    MLCC_HIP(hipMemcpyAsync(fock.p, desc.fock, d.n2 * sizeof(double),
+                            is_dev(desc.fock) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                            x.stream));
+    k::nonfinite(x, d.n2, fock.as<double>(), res.as<double>());
+    MLCC_REQUIRE(fetch(res.as<double>()) == 0.0, MLCC_E_NUMERIC, "non-finite Fock matrix");
+    k::lincomb<double>(x, d.n2, 1.0, h.as<double>(), 1.0, fock.as<double>(), h.as<double>());
+  } else {
+    hipLaunchKernelGGL(k_add_diag, dim3(64), dim3(256), 0, x.stream, (int64_t)d.n,
+                       eps.as<double>(), h.as<double>());
+    MLCC_HIP(hipGetLastError());
+  }
   // NaN/Inf in L shows up in h
   k::nonfinite(x, d.n2, h.as<double>(), res.as<double>());
   MLCC_REQUIRE(fetch(res.as<double>()) == 0.0, MLCC_E_NUMERIC, "non-finite Cholesky vectors");

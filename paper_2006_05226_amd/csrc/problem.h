@@ -88,6 +88,7 @@ struct mlcc_problem {
 
   // inputs and derived constants
   mlcc::DBuf L, eps, h, eps_ai, eps_vo, Lvo0;
+  mlcc::DBuf fock;     // f64 [n][n] when the desc gave a Fock matrix (else diag(eps))
   // state at the current amplitudes
   mlcc::DBuf amp;      // f64 [n1 + M*M]: t1 then doubles
   mlcc::DBuf t1T;      // op [n1]
@@ -130,6 +131,10 @@ struct mlcc_problem {
   void transform_eff(double w, int nvec, const double *c1, double *s1);
   double fetch(const double *dev);
   void fetch_n(const double *dev, double *host, int n);
+  // CNTOs from excitation vectors (cnto.cpp); R [ns][V][O] device, w [ns] host
+  void cnto(int ns, const double *R, const double *w, int o_act, int v_act, double *m_eig,
+            double *n_eig, double *C, double *eps_out, double *fock_out, double *L_out,
+            bool L_out_dev);
 
  private:
   template <typename T> void setup_t(const double *Lhost_or_dev, bool dev,
@@ -142,6 +147,9 @@ struct mlcc_problem {
   template <typename T> void prepare_jacobian_t();
   template <typename T> void transform_batch_t(int nb, const double *c, int64_t ld,
                                                bool has_c2, double *sigma, double w_eff);
+  template <typename T> void cnto_t(int ns, const double *R, const double *w, int o_act, int v_act,
+                                    double *m_eig, double *n_eig, double *C, double *eps_out,
+                                    double *fock_out, double *L_out, bool L_out_dev);
   template <typename T> void ccsd_integrals_t();
   template <typename T> void ccsd_omega2_t();
   template <typename T> void ccsd_prepare_t();

@@ -30,7 +30,7 @@ namespace {
 struct Request {
   uint64_t ticket = 0;
   mlcc_problem_desc desc{};
-  std::vector<double> L, eps;  // owned copies (L empty for synthetic inputs)
+  std::vector<double> L, eps, fock;  // owned copies (L empty for synthetic inputs)
   int32_t n_roots = 0;
   mlcc_solver_opts gs{}, es{};
   uint64_t footprint = 0;
@@ -134,6 +134,7 @@ void mlcc_server::work(Lane *lane) {
       mlcc_problem_desc d = r->desc;
       if (!(d.flags & MLCC_SYNTH_L)) d.L = r->L.data();
       d.eps = r->eps.data();
+      d.fock = r->fock.empty() ? nullptr : r->fock.data();
       std::unique_ptr<mlcc_problem> P(problem_new(ctx, &lane->ex, &d));
       mlcc_info gi{};
       mlcc_status gs = ground_state(*P, r->gs, gi);
@@ -263,6 +264,7 @@ mlcc_status mlcc_submit(mlcc_server *s, const mlcc_problem_desc *desc, int32_t n
   };
   try {
     if (!copy_in(r->eps, desc->eps, n)) return MLCC_E_DEVICE;
+    if (desc->fock && !copy_in(r->fock, desc->fock, n * n)) return MLCC_E_DEVICE;
     if (!(desc->flags & MLCC_SYNTH_L) && !copy_in(r->L, desc->L, (int64_t)desc->n_chol * n * n))
       return MLCC_E_DEVICE;
   } catch (const std::bad_alloc &) {

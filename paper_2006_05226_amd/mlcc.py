@@ -32,7 +32,7 @@ class ProblemDesc(C.Structure):
     _fields_ = [("n_occ", C.c_int32), ("n_vir", C.c_int32), ("n_chol", C.c_int32),
                 ("n_occ_act", C.c_int32), ("n_vir_act", C.c_int32), ("model", C.c_int32),
                 ("precision", C.c_int32), ("L", C.c_void_p), ("eps", C.c_void_p),
-                ("flags", C.c_uint32), ("seed", C.c_uint64)]
+                ("flags", C.c_uint32), ("seed", C.c_uint64), ("fock", C.c_void_p)]
 
 
 SYNTH_L = 1
@@ -70,7 +70,7 @@ EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "ml
            "mlcc_jacobian_transform", "mlcc_jacobian_transform_eff", "mlcc_davidson_solve",
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
            "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_debug_get", "mlcc_profile_enable",
-           "mlcc_profile_get", "mlcc_gemm_tile"]
+           "mlcc_profile_get", "mlcc_gemm_tile", "mlcc_cnto"]
 
 _lib = None
 
@@ -112,6 +112,7 @@ def load(path: str = LIB_PATH):
         "mlcc_profile_enable": (i32, [vp, i32]),
         "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
         "mlcc_gemm_tile": (i32, [i32, i32, P(i32)]),
+        "mlcc_cnto": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -219,20 +220,22 @@ class Problem:
     """One MLCC problem on a context (see mlcc_problem_create)."""
 
     def __init__(self, ctx: Context, L, eps, n_occ, n_vir, n_occ_act=None, n_vir_act=None,
-                 model="mlcc2", precision="fp64", n_chol=None, seed=None):
+                 model="mlcc2", precision="fp64", n_chol=None, seed=None, fock=None):
         """L=None with n_chol and seed: Cholesky vectors drawn on the device
-        (MLCC_SYNTH_L)."""
+        (MLCC_SYNTH_L).  fock: the full [n][n] Fock matrix of a semicanonical
+        basis (eps its diagonal), or None for diag(eps)."""
         self.ctx = ctx
         L = _f64(L)
         eps = _f64(eps)
+        fock = _f64(fock)
         synth = L is None
         n_chol = n_chol if synth else L.shape[0]
-        self._keep = (L, eps)
+        self._keep = (L, eps, fock)
         d = ProblemDesc(n_occ, n_vir, n_chol,
                         n_occ if n_occ_act is None else n_occ_act,
                         n_vir if n_vir_act is None else n_vir_act,
                         MODEL[model], PREC[precision], _ptr(L), _ptr(eps),
-                        SYNTH_L if synth else 0, int(seed or 0))
+                        SYNTH_L if synth else 0, int(seed or 0), _ptr(fock))
         h = C.c_void_p()
         ctx.check(ctx.lib.mlcc_problem_create(ctx.h, C.byref(d), C.byref(h)))
         self._keep = None  # the library copied the inputs
@@ -314,6 +317,27 @@ class Problem:
         return dict(omega=w, r1=r1, iterations=info.iterations, converged=bool(info.converged),
                     residual=info.residual, transforms=info.transforms,
                     complex_roots=info.complex_roots, status=st)
+
+    def cnto(self, R, omega, n_occ_act, n_vir_act, want_L=True, L_device=False):
+        """CNTOs (mlcc_cnto) from excitation vectors R [n_states][n_vir][n_occ]
+        and energies omega.  Returns dict(m_eig, n_eig, C, eps, fock, L); L is
+        a host array, or a torch tensor on the GPU with L_device=True."""
+        R = _f64(np.asarray(R).reshape(len(omega), self.n1))
+        w = _f64(np.asarray(omega, dtype=np.float64))
+        n = self.n_occ + self.n_vir
+        m_eig, n_eig = np.empty(self.n_occ), np.empty(self.n_vir)
+        Cm, eps, fock = np.empty((n, n)), np.empty(n), np.empty((n, n))
+        L = None
+        if want_L:
+            if L_device:
+                import torch
+                L = torch.empty((self.n_chol, n, n), dtype=torch.float64, device="cuda")
+            else:
+                L = np.empty((self.n_chol, n, n))
+        self.ctx.check(self.ctx.lib.mlcc_cnto(self.h, len(w), _ptr(R), _ptr(w), n_occ_act,
+                                              n_vir_act, _ptr(m_eig), _ptr(n_eig), _ptr(Cm),
+                                              _ptr(eps), _ptr(fock), _ptr(L)))
+        return dict(m_eig=m_eig, n_eig=n_eig, C=Cm, eps=eps, fock=fock, L=L)
 
     def debug_get(self, which):
         sizes = {0: (self.n_occ + self.n_vir,) * 2,
