@@ -165,6 +165,79 @@ def _mlccsd_leg(mlcc, steps, warmup, precisions, config="mlccsd_60_600_2000", nv
     return out
 
 
+def _cnto_leg(mlcc, precisions=("fp64", "bf16x3"), config="mlcc2_40_400_1200", n_states=4):
+    """Orbital selection (Sec. 2.3) at a full-size workload: CCS roots in the
+    canonical basis, CNTOs from them with n_vir_act = (n_vir / n_occ) n_occ_act
+    (eq. select_CNTOs), then MLCC2 on the new orbitals with their full Fock
+    matrix.  Cholesky vectors drawn on the device (seed 0), canonical orbital
+    energies.  The CNTO step runs twice: the first call includes the
+    eigensolver library's start-up."""
+    import numpy as np
+    import torch
+    from paper_2006_05226_amd.synth import CONFIGS, gen_eps
+
+    c = CONFIGS[config]
+    O, V, J, o = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"]
+    v = V * o // O
+    n1, n = V * O, O + V
+    eps = gen_eps(O, V, seed=0)
+    # per state: gbar 4 n1^2 K, M and N 2 n1 (O^2 V + V^2 O), Z 2 V O K (V + O); then L' = C^T L C
+    flops = n_states * (4.0 * n1 * n1 * J + 2.0 * n1 * (O * O * V + V * V * O)
+                        + 2.0 * V * O * J * (V + O)) + 4.0 * n ** 3 * J
+    out = {"workload": f"CCS roots -> CNTOs -> MLCC2, n_occ={O} n_vir={V} n_chol={J}, {n_states} "
+                       f"CCS states, active {o}/{v} (n_vir_act = n_vir/n_occ x n_occ_act), "
+                       f"device-drawn Cholesky vectors",
+           "cnto_flops": flops}
+    for prec in precisions:
+        print(f"cnto: {prec}", file=sys.stderr, flush=True)
+        ctx = mlcc.Context(0)
+        Pc = mlcc.Problem(ctx, None, eps, O, V, 0, 0, model="ccs", precision=prec, n_chol=J, seed=0)
+        t0 = time.perf_counter()
+        Pc.ground_state(tol=1e-10)
+        dav = Pc.davidson(n_states, tol=1e-6, want_vectors=True)
+        t_ccs = time.perf_counter() - t0
+        R = dav["r1"].reshape(n_states, V, O)
+        R = R / np.sqrt((R * R).sum(axis=(1, 2)))[:, None, None]
+        t0 = time.perf_counter()
+        res = Pc.cnto(R, dav["omega"], o, v, want_L=False)
+        t_cold = time.perf_counter() - t0
+        ctx.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = Pc.cnto(R, dav["omega"], o, v, L_device=True)
+        torch.cuda.synchronize()
+        t_cnto = time.perf_counter() - t0
+        stats = ctx.profile_stats()
+        ctx.profile(False)
+        Pc.close()
+        P = mlcc.Problem(ctx, res["L"], res["eps"], O, V, o, v, model="mlcc2", precision=prec,
+                         fock=res["fock"])
+        res["L"] = None
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        gs = P.ground_state(tol=1e-8 if prec == "fp64" else 1e-6)
+        t_gs = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        roots = P.davidson(n_states, tol=1e-6)
+        t_dav = time.perf_counter() - t0
+        P.close()
+        ctx.close()
+        top = sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:4]
+        out[prec] = dict(ccs_seconds=t_ccs, ccs_omega=list(dav["omega"]),
+                         cnto_seconds=t_cnto, cnto_seconds_first_call=t_cold,
+                         cnto_tflops=flops / t_cnto / 1e12,
+                         m_eig_top=list(res["m_eig"][:o + 2]), n_eig_sum_active=float(np.sum(res["n_eig"][:v])),
+                         n_eig_sum=float(np.sum(res["n_eig"])),
+                         contractions={k: dict(ms=st["ms"], tflops=st["flops"] / max(st["ms"], 1e-9) / 1e9)
+                                       for k, st in top},
+                         mlcc2_gs_seconds=t_gs, mlcc2_e_corr=gs["energy"],
+                         mlcc2_davidson_seconds=t_dav, mlcc2_omega=list(roots["omega"]),
+                         mlcc2_converged=bool(gs["converged"] and roots["converged"]))
+        del res
+        torch.cuda.empty_cache()
+    return out
+
+
 def _c4_leg(mlcc, steps=3, nvec=5, precisions=("fp32", "bf16x3")):
     """MLCC2 at 150/1200/3600 (active 50/500), FP32 or split-BF16 contractions,
     FP64 updates, effective-singles Davidson for 5 roots; device-drawn
@@ -311,6 +384,7 @@ def main():
     ap.add_argument("--no-solves", action="store_true", help="skip the Davidson solve timing")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-mlccsd", action="store_true", help="skip the MLCCSD leg")
+    ap.add_argument("--no-cnto", action="store_true", help="skip the orbital-selection leg")
     ap.add_argument("--c4", action="store_true",
                     help="also run MLCC2 at 150/1200/3600 (active 50/500), ~1 minute")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -421,6 +495,8 @@ def main():
         extra["c4"] = _c4_leg(mlcc)
     if not args.no_mlccsd:
         extra["mlccsd"] = _mlccsd_leg(mlcc, max(3, args.steps // 4), 1, precs)
+    if not args.no_cnto:
+        extra["cnto"] = _cnto_leg(mlcc, [p for p in ("fp64", "bf16x3") if p in precs])
     if args.serve > 0:
         print(f"serving: {args.serve} requests", file=sys.stderr, flush=True)
         extra["serving"] = _serving(mlcc, args.serve, args.slots)

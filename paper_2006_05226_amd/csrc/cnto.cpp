@@ -120,20 +120,25 @@ void semicanonical(Exec &ex, Alloc *al, SymEig &se, int64_t m, const std::vector
                    const std::vector<double> &F, int64_t c0, int64_t k, std::vector<double> &C,
                    double *e) {
   if (k == 0) return;
-  // B = U_blk^T F U_blk (k x k)
+  // B = U_blk^T F U_blk (k x k), with every inner loop over contiguous memory
   std::vector<double> FU(m * k, 0.0), B(k * k, 0.0);
   for (int64_t r = 0; r < m; ++r)
     for (int64_t s = 0; s < m; ++s) {
       const double f = F[r * m + s];
       if (f == 0.0) continue;
-      for (int64_t c = 0; c < k; ++c) FU[r * k + c] += f * U[s * m + c0 + c];
+      const double *us = &U[s * m + c0];
+      double *fu = &FU[r * k];
+      for (int64_t c = 0; c < k; ++c) fu[c] += f * us[c];
     }
-  for (int64_t c = 0; c < k; ++c)
-    for (int64_t d = 0; d < k; ++d) {
-      double s = 0.0;
-      for (int64_t r = 0; r < m; ++r) s += U[r * m + c0 + c] * FU[r * k + d];
-      B[c * k + d] = s;
+  for (int64_t r = 0; r < m; ++r) {
+    const double *ur = &U[r * m + c0];
+    const double *fu = &FU[r * k];
+    for (int64_t c = 0; c < k; ++c) {
+      const double uc = ur[c];
+      double *b = &B[c * k];
+      for (int64_t d = 0; d < k; ++d) b[d] += uc * fu[d];
     }
+  }
   for (int64_t c = 0; c < k; ++c)  // exact symmetry for the solver
     for (int64_t d = 0; d < c; ++d) B[c * k + d] = B[d * k + c] = 0.5 * (B[c * k + d] + B[d * k + c]);
   std::vector<double> w;
@@ -288,11 +293,14 @@ void mlcc_problem::cnto_t(int ns, const double *R, const double *w, int o_act, i
         if (f == 0.0) continue;
         for (int64_t c = 0; c < n; ++c) FC[r * n + c] += f * C[s * n + c];
       }
-    for (int64_t q = 0; q < n; ++q)
-      for (int64_t c = 0; c < n; ++c) {
-        double s = 0.0;
-        for (int64_t r = 0; r < n; ++r) s += C[r * n + q] * FC[r * n + c];
-        fock_out[q * n + c] = s;
+    std::fill(fock_out, fock_out + n2, 0.0);
+    for (int64_t r = 0; r < n; ++r)
+      for (int64_t q = 0; q < n; ++q) {
+        const double cr = C[r * n + q];
+        if (cr == 0.0) continue;
+        const double *x = &FC[r * n];
+        double *y = &fock_out[q * n];
+        for (int64_t c = 0; c < n; ++c) y[c] += cr * x[c];
       }
   }
   if (L_out) {

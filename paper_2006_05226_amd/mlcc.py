@@ -361,17 +361,19 @@ class Server:
 
     @staticmethod
     def desc(L, eps, n_occ, n_vir, n_occ_act, n_vir_act, model="mlcc2", precision="fp64",
-             n_chol=None, seed=None):
-        """Problem descriptor; L=None with seed set draws L on the device."""
+             n_chol=None, seed=None, fock=None):
+        """Problem descriptor; L=None with seed set draws L on the device;
+        fock: a full Fock matrix (semicanonical basis) or None."""
         eps = _f64(eps)
+        fock = _f64(fock)
         if L is None:
             d = ProblemDesc(n_occ, n_vir, n_chol, n_occ_act, n_vir_act, MODEL[model],
-                            PREC[precision], None, _ptr(eps), SYNTH_L, seed)
-            return d, (eps,)
+                            PREC[precision], None, _ptr(eps), SYNTH_L, seed, _ptr(fock))
+            return d, (eps, fock)
         L = _f64(L)
         d = ProblemDesc(n_occ, n_vir, L.shape[0], n_occ_act, n_vir_act, MODEL[model],
-                        PREC[precision], _ptr(L), _ptr(eps), 0, 0)
-        return d, (L, eps)
+                        PREC[precision], _ptr(L), _ptr(eps), 0, 0, _ptr(fock))
+        return d, (L, eps, fock)
 
     def submit(self, desc, n_roots, gs_tol=1e-8, es_tol=1e-6, effective=True, max_iter=100):
         gs = opts(tol=gs_tol, max_iter=max_iter)

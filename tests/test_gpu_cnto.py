@@ -127,6 +127,27 @@ def test_full_fock_input(ctx, model, precision, tol):
     assert abs(gs1["energy"] - gs0["energy"]) < (1e-11 if precision == "fp64" else 1e-7)
 
 
+def test_served_request_with_fock(ctx):
+    """A request with a full Fock matrix through the server gives the result
+    of the same problem solved alone."""
+    O, V, J, o, v = 5, 14, 33, 2, 5
+    inp = gen_inputs(O, V, J, seed=27)
+    L1, F1 = rotate_inactive(inp.L, np.diag(inp.eps), O, V, o, v, seed=28)
+    e1 = np.diag(F1).copy()
+    P = mlcc.Problem(ctx, L1, e1, O, V, o, v, fock=F1)
+    gs = P.ground_state(tol=1e-8)
+    dav = P.davidson(2, tol=1e-6, effective=True)
+    P.close()
+    S = mlcc.Server(ctx, max_slots=2)
+    d, keep = mlcc.Server.desc(L1, e1, O, V, o, v, fock=F1)
+    t = S.submit(d, 2, gs_tol=1e-8, es_tol=1e-6, effective=True)
+    r = S.wait(t)
+    S.close()
+    assert r["status"] == 0
+    assert abs(r["e_corr"] - gs["energy"]) < 1e-12
+    assert np.abs(np.array(r["omega"][:2]) - np.array(dav["omega"])).max() < 1e-10
+
+
 def test_cnto_rejects_bad_sizes(ctx):
     inp = gen_inputs(3, 6, 10, seed=26)
     P = mlcc.Problem(ctx, inp.L, inp.eps, 3, 6, 0, 0, model="ccs")
