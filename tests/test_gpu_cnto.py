@@ -55,6 +55,30 @@ def test_cnto_matches_oracle(ctx, precision, O, V, J, o, v):
     assert rel(got["L"], ref["L"]) < (1e-10 if precision == "fp64" else 50 * tol)
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_cnto_medium_size(ctx, precision):
+    """20/200/600 (V*O = 4000 pairs, 2 states): every GEMM of the path spans
+    many tiles with ragged edges; spectra and Fock matrix against the oracle.
+    The active sizes sit at wide gaps of the M and N spectra (0.033 | 0.0041 and
+    0.0020 | 0.0003), so that both precisions select the same spaces."""
+    O, V, J, o, v = 20, 200, 600, 3, 8
+    inp = gen_inputs(O, V, J, seed=29)
+    d = om.Dims(O, V, O, V)
+    rng = np.random.default_rng(30)
+    Rs = rng.standard_normal((2, V, O)) * np.exp(-np.arange(O))[None, None, :]
+    Rs /= np.sqrt((Rs * Rs).sum(axis=(1, 2)))[:, None, None]
+    w = np.array([0.45, 0.5])
+    ref = oc.cnto_basis(inp.L, inp.eps, d, list(Rs), w, o, v)
+    P = mlcc.Problem(ctx, inp.L, inp.eps, O, V, 0, 0, model="ccs", precision=precision)
+    got = P.cnto(Rs, w, o, v, want_L=False)
+    P.close()
+    tol = TOL[precision]
+    assert rel(got["m_eig"], ref["m_eig"]) < tol
+    assert rel(got["n_eig"], ref["n_eig"]) < tol
+    assert np.abs(got["fock"] - ref["fock"]).max() < tol * np.abs(ref["fock"]).max()
+
+
 def test_pipeline_ccs_cnto_mlcc2(ctx):
     """CCS roots on the GPU, CNTOs on the GPU, MLCC2 in the new basis on the
     GPU with its full Fock matrix; the oracle repeats the last two steps from
