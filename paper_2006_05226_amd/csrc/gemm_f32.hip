@@ -15,7 +15,8 @@ const gk::Tile kSplitTiles[] = {MLCC_GEMM_TILES_SPLIT(MLCC_TILE_ENTRY)};
 
 void gemm_f32(Exec &ex, const GemmArgs &a) {
   if (a.K > 0 && a.R > 0 && gk::gemm_split_ok(a))
-    gk::dispatch<float, float>(ex, a, kSplitTiles, (int)(sizeof(kSplitTiles) / sizeof(kSplitTiles[0])));
+    gk::dispatch<float, float>(ex, a, kSplitTiles, (int)(sizeof(kSplitTiles) / sizeof(kSplitTiles[0])),
+                                 48.0);
   else if (a.K > 0 && a.R > 0 && gk::gemm_vonly(a, gk::Tr<float>::VEC))
     gk::dispatch<float, float>(ex, a, kTiles, (int)(sizeof(kTiles) / sizeof(kTiles[0])));
   else

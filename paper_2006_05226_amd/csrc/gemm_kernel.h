@@ -770,10 +770,15 @@ struct Tile {
 };
 
 // Pick the tile with the lowest modelled time: padded MACs, an operand-load
-// overhead that grows as the tile shrinks, the number of rounds of ~2048
-// resident waves, and the split reduction's traffic.
+// overhead that grows as the tile shrinks (coefficient load_coef), the number
+// of rounds of ~2048 resident waves, and the split reduction's traffic.  The
+// split BF16 kernel takes a larger coefficient: its per-k-step work (the
+// hi/lo split, two LDS rows per element) grows with the tile's perimeter, and
+// with 48 the model picks the measured best tile on each of the shapes swept
+// (a 4096^3 product, the batch-reduced 400 x 160 x 480000, 2250 x 9000 x
+// 1200, 14400 x 144 x 14400).
 template <typename T, typename TC>
-void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles) {
+void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles, double load_coef = 16.0) {
   constexpr int BK = Tr<T>::BK;
   const int64_t steps = a.R * cdiv(a.K, BK);
   auto waves_of = [](int bm, int bn) { return (bm % 32 == 0 ? 2 : 1) * (bn % 32 == 0 ? 2 : 1); };
@@ -799,7 +804,7 @@ void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles) {
     const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
     const int s = splits_for(blocks, nw);
     const double rounds = std::ceil((double)(blocks * s * nw) / 2048.0);
-    const double f = 1.0 + 16.0 * (1.0 / bm + 1.0 / bn);
+    const double f = 1.0 + load_coef * (1.0 / bm + 1.0 / bn);
     const double per_block = (double)bm * bn * ((double)cdiv(steps, s) * BK * f + 16.0);
     double cost = rounds * per_block * 4.0 / nw;
     if (s > 1) cost += 2.0 * (double)s * a.Z * a.M * a.N;
