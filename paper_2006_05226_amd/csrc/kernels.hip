@@ -7,6 +7,8 @@
 //
 // These are HBM-bound: grid-stride loops with consecutive lanes on consecutive
 // addresses; reductions are two-pass with a fixed order (deterministic).
+#include <algorithm>
+
 #include "mlcc_internal.h"
 
 namespace mlcc {
@@ -135,6 +137,34 @@ __global__ void k_u_of(int o, int v, const double *x, TU *u, int nz, int64_t ldx
     const double *xz = x + z * ldx;
     const int64_t row = occ_rows ? i * v + a : ai;
     u[z * ldu + row * M + bj] = (TU)(2.0 * xz[t] - xz[(a * o + j) * M + (b * o + i)]);
+  }
+}
+
+// The same through LDS: a workgroup takes the o x (nb*o) slab of rows (a, i)
+// and columns (b, j) for nb consecutive b, where both x_aibj and x_ajbi live,
+// so the loads and the stores run along contiguous (b, j).
+template <typename TU>
+__global__ void k_u_of_tiled(int o, int v, const double *x, TU *u, int64_t ldx, int64_t ldu,
+                             bool occ_rows, int bchunk) {
+  extern __shared__ double slab[];  // [o][bchunk*o + 1]
+  const int64_t M = (int64_t)o * v;
+  const int S = bchunk * o + 1;
+  const int z = blockIdx.z, a = blockIdx.y, b0 = blockIdx.x * bchunk;
+  const int nb = min(bchunk, v - b0);
+  const int W = nb * o;
+  const double *xz = x + z * ldx;
+  TU *uz = u + z * ldu;
+  for (int t = threadIdx.x; t < o * W; t += blockDim.x) {
+    const int i = t / W, c = t - i * W;
+    slab[i * S + c] = xz[((int64_t)a * o + i) * M + (int64_t)b0 * o + c];
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < o * W; t += blockDim.x) {
+    const int i = t / W, c = t - i * W;
+    const int bl = c / o, j = c - bl * o;
+    const double val = 2.0 * slab[i * S + c] - slab[j * S + bl * o + i];
+    const int64_t row = occ_rows ? (int64_t)i * v + a : (int64_t)a * o + i;
+    uz[row * M + (int64_t)b0 * o + c] = (TU)val;
   }
 }
 
@@ -412,8 +442,17 @@ void u_of(Exec &ex, int o, int v, const double *x, TU *u, int nz, int64_t ldx, i
           bool occ_rows) {
   const int64_t M = (int64_t)o * v;
   if (M == 0 || nz <= 0) return;
-  hipLaunchKernelGGL((k_u_of<TU>), dim3(blocks_for(M * M * nz)), dim3(TPB), 0, ex.stream, o, v, x,
-                     u, nz, ldx, ldu, occ_rows);
+  if (o <= 64 && v <= 65535 && nz <= 65535) {
+    // slabs of at most 4096 doubles (+ padding) of LDS
+    const int bchunk = std::max(1, std::min(v, 4096 / (o * o)));
+    const size_t lds = (size_t)o * (bchunk * o + 1) * sizeof(double);
+    const dim3 grid((unsigned)((v + bchunk - 1) / bchunk), (unsigned)v, (unsigned)nz);
+    hipLaunchKernelGGL((k_u_of_tiled<TU>), grid, dim3(TPB), lds, ex.stream, o, v, x, u,
+                       nz > 1 ? ldx : 0, nz > 1 ? ldu : 0, occ_rows, bchunk);
+  } else {
+    hipLaunchKernelGGL((k_u_of<TU>), dim3(blocks_for(M * M * nz)), dim3(TPB), 0, ex.stream, o, v,
+                       x, u, nz, ldx, ldu, occ_rows);
+  }
   MLCC_HIP(hipGetLastError());
 }
 
