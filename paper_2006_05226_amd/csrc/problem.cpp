@@ -447,10 +447,11 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   G(O, b, J, 1, V).A(lt + O * n, 1, n2, 0, n).B(Xk.p, b, 1).C(sigma, 1, ld, O, 2.0, 1.0)
       .tag("ccs_coul").run(x, p, true);
   // W^K[vec][i][B] = sum_J c_BJ L~^K_Ji, stored with B innermost so that the
-  // reduction index of ccs_vv is contiguous
+  // reduction index of ccs_vv is contiguous; computed as rows i x columns
+  // (vec, B) so that the output rows are contiguous too
   W.ensure(al, (size_t)J * b * V * O * sizeof(T));
-  G(b * V, O, O, 1, J).A(ct, O, 1, 0, 0).Mhi(V, V * O, V * O).B(loot, 1, O, 0, O * O)
-      .C(W.p, 1, V, b * V * O).tag("ccs_W").run(x, p, o64);
+  G(O, b * V, O, 1, J).A(loot, O, 1, 0, O * O).B(ct, 1, O, 0, 0).Nhi(V, n1, V * O)
+      .C(W.p, V, 1, b * V * O).tag("ccs_W").run(x, p, o64);
   G(V, b * O, V, J).A(lt + O * n + O, n, 1, n2).B(W.p, 1, V, b * V * O).Nhi(O, V * O, ld)
       .C(sigma, O, 1, 0, -1.0, 1.0).tag("ccs_vv").run(x, p, true);
   if (!has_doubles()) return;
