@@ -466,8 +466,10 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   rv.ensure(al, M * b * sizeof(T));
   P.ensure(al, (size_t)J * o * b * O * sizeof(T));
   G(M, b, J).A(off<T>(Lvo0), 1, M).B(Xk.p, b, 1).C(qv.p, b, 1).tag("jac_q").run(x, p, o64);
-  G(o, b * O, V, 1, J).A(lt + O, n, 1, 0, n2).B(ct, O, 1, 0, 0).Nhi(O, n1, O)
-      .C(P.p, b * O, 1, o * b * O).tag("jac_P").run(x, p, o64);
+  // P^K[i][vec, J] = sum_B L~^K_iB c_BJ as one launch over rows (K, i), reading
+  // the transposed singles so that the reduction index is contiguous in both
+  G(J * o, b * O, V).A(lt + O, n, 1).Mhi(o, n2, o * b * O).B(ctt, 1, V).Nhi(O, n1, O)
+      .C(P.p, b * O, 1).tag("jac_P").run(x, p, o64);
   G(v, o * b, O, J).A(lt + O, 1, n, n2).B(P.p, 1, O, o * b * O).C(rv.p, o * b, 1)
       .tag("jac_r").run(x, p, o64);
   k::lincomb<T>(x, M * b, 2.0, off<T>(qv), -1.0, off<T>(rv), off<T>(qv));
