@@ -38,3 +38,22 @@ def test_create_error_without_gpu_is_reported():
     st = lib.mlcc_context_create(0, None, 0, ctypes.byref(h))
     assert st < 0
     assert len(lib.mlcc_last_error(None)) > 0
+
+
+def test_tile_override_arguments():
+    """mlcc_gemm_tile needs no device: negative sizes are refused, 0 x 0
+    restores the cost model and the previous call's tile is reported."""
+    lib = mlcc.load()
+    assert lib.mlcc_gemm_tile(-1, 32, None) == mlcc.E_ARG
+    last = (ctypes.c_int32 * 2)()
+    assert lib.mlcc_gemm_tile(128, 96, last) == 0
+    assert lib.mlcc_gemm_tile(0, 0, last) == 0
+
+
+def test_cnto_and_fock_argument_checks():
+    """Entry points added with the orbital selection refuse NULL handles
+    without touching a device; the descriptor carries the Fock pointer last."""
+    lib = mlcc.load()
+    assert lib.mlcc_cnto(None, 1, None, None, 0, 0, None, None, None, None, None, None) == mlcc.E_ARG
+    names = [f[0] for f in mlcc.ProblemDesc._fields_]
+    assert names[-1] == "fock"
