@@ -782,11 +782,14 @@ void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles, double
   constexpr int BK = Tr<T>::BK;
   const int64_t steps = a.R * cdiv(a.K, BK);
   auto waves_of = [](int bm, int bn) { return (bm % 32 == 0 ? 2 : 1) * (bn % 32 == 0 ? 2 : 1); };
+  // splits: as many as fit one round of ~2048 resident waves.  Rounding up
+  // instead would leave a few blocks to run alone in a second round (7 tiles
+  // x 74 splits = 518 blocks of 4 waves).
   auto splits_for = [&](int64_t blocks, int nw) {
     const int64_t target = 2048 / nw;
     int s = 1;
     if (blocks < target && steps >= 8) {
-      s = (int)std::min<int64_t>(cdiv(target, blocks), steps / 4);
+      s = (int)std::min<int64_t>(target / blocks, steps / 4);
       s = std::max(1, std::min(s, 128));
     }
     return s;

@@ -306,8 +306,10 @@ template <typename T> void mlcc_problem::doubles_mlcc2_t() {
     k::pack2d<T, T>(x, off<T>(Lai), off<T>(Lt, O * n), J, n2, d.v, d.o, n);
     k::u_of<T>(x, d.o, d.v, x2(), off<T>(u));
   }
+  // Z^K_ai = sum_bj L^K_bj u_bj,ai, with u read through its pair symmetry
+  // (u_bj,ai = u_ai,bj) so that both operands run along the reduction index
   Z.ensure(al, (size_t)J * M * sizeof(T));
-  G(J, M, M).A(off<T>(Lvo0), M, 1).B(off<T>(u), M, 1).C(Z.p, M, 1).tag("Z_uL").run(x, p, sizeof(T) == 8);
+  G(J, M, M).A(off<T>(Lvo0), M, 1).B(off<T>(u), 1, M).C(Z.p, M, 1).tag("Z_uL").run(x, p, sizeof(T) == 8);
 }
 
 // Omega_AI += [I act] sum_Kb L~^K_Ab Z^K_bi - [A act] sum_Kk Z^K_ak L~^K_kI
