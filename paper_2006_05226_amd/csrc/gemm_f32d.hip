@@ -5,20 +5,20 @@
 
 namespace mlcc {
 namespace {
-#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<float, double, BMv, BNv, true>},
+#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<float, double, BMv, BNv, true>, &gk::tile_occupancy<float, double, BMv, BNv, true>},
 const gk::Tile kTiles[] = {MLCC_GEMM_TILES(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
-#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<float, double, BMv, BNv, true, true>},
+#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<float, double, BMv, BNv, true, true>, &gk::tile_occupancy<float, double, BMv, BNv, true, true>},
 const gk::Tile kSplitTiles[] = {MLCC_GEMM_TILES_SPLIT(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
 }  // namespace
 
 void gemm_f32_out64(Exec &ex, const GemmArgs &a) {
   if (a.K > 0 && a.R > 0 && gk::gemm_split_ok(a))
-    gk::dispatch<float, double>(ex, a, kSplitTiles, (int)(sizeof(kSplitTiles) / sizeof(kSplitTiles[0])),
+    gk::dispatch_load<float, double>(ex, a, kSplitTiles, (int)(sizeof(kSplitTiles) / sizeof(kSplitTiles[0])),
                                  48.0);
   else if (a.K > 0 && a.R > 0 && gk::gemm_vonly(a, gk::Tr<float>::VEC))
-    gk::dispatch<float, double>(ex, a, kTiles, (int)(sizeof(kTiles) / sizeof(kTiles[0])));
+    gk::dispatch_load<float, double>(ex, a, kTiles, (int)(sizeof(kTiles) / sizeof(kTiles[0])), 16.0);
   else
     gemm_f32_out64_general(ex, a);
 }

@@ -4,7 +4,7 @@
 
 namespace mlcc {
 namespace {
-#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<float, float, BMv, BNv, false>},
+#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<float, float, BMv, BNv, false>, &gk::tile_occupancy<float, float, BMv, BNv, false>},
 const gk::Tile kTiles[] = {MLCC_GEMM_TILES_GENERAL(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
 }  // namespace
@@ -19,7 +19,7 @@ void gemm_f32_general(Exec &ex, const GemmArgs &a) {
     gk::launch_tile<float, float, 32, 32, false>(ex, b, 1);
     return;
   }
-  gk::dispatch<float, float>(ex, a, kTiles, (int)(sizeof(kTiles) / sizeof(kTiles[0])));
+  gk::dispatch_load<float, float>(ex, a, kTiles, (int)(sizeof(kTiles) / sizeof(kTiles[0])), 16.0);
 }
 
 }  // namespace mlcc

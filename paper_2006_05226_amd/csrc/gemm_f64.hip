@@ -4,7 +4,7 @@
 
 namespace mlcc {
 namespace {
-#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<double, double, BMv, BNv, true>},
+#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<double, double, BMv, BNv, true>, &gk::tile_occupancy<double, double, BMv, BNv, true>},
 const gk::Tile kTiles[] = {MLCC_GEMM_TILES(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
 }  // namespace

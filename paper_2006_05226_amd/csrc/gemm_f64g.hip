@@ -4,7 +4,7 @@
 
 namespace mlcc {
 namespace {
-#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<double, double, BMv, BNv, false>},
+#define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<double, double, BMv, BNv, false>, &gk::tile_occupancy<double, double, BMv, BNv, false>},
 const gk::Tile kTiles[] = {MLCC_GEMM_TILES_GENERAL(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
 }  // namespace

@@ -39,6 +39,7 @@
 //   tiles, which share operand rows in that XCD's L2.
 #pragma once
 
+#include <algorithm>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -747,6 +748,28 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   }
 }
 
+// Resident blocks per CU of the kernel launch_tile runs for this layout (the
+// compiled register and LDS use decide it), queried once per variant.
+template <typename T, typename TC, int BM, int BN, bool VONLY, bool SPLIT = false>
+int tile_occupancy(const GemmArgs &a) {
+  static std::atomic<int> cache[4];
+  const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
+  const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
+  const int v = SPLIT ? 0 : (akm ? 2 : 0) + (bkn ? 1 : 0);
+  int nb = cache[v].load(std::memory_order_relaxed);
+  if (nb > 0) return nb;
+  const void *f;
+  if constexpr (SPLIT) f = reinterpret_cast<const void *>(&k_gemm_split<TC, BM, BN>);
+  else if (akm && bkn) f = reinterpret_cast<const void *>(&k_gemm<T, TC, BM, BN, true, true, VONLY>);
+  else if (akm) f = reinterpret_cast<const void *>(&k_gemm<T, TC, BM, BN, true, false, VONLY>);
+  else if (bkn) f = reinterpret_cast<const void *>(&k_gemm<T, TC, BM, BN, false, true, VONLY>);
+  else f = reinterpret_cast<const void *>(&k_gemm<T, TC, BM, BN, false, false, VONLY>);
+  MLCC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, WaveGrid<BM, BN>::NT, 0));
+  nb = std::max(nb, 1);
+  cache[v].store(nb, std::memory_order_relaxed);
+  return nb;
+}
+
 // The tile menus: (BM, BN) multiples of 32 (two waves along each
 // dimension); the general (element-wise fallback) kernel is built for fewer
 // shapes.  Tiles of 80 (one wave along that dimension, FM or FN = 5) were
@@ -764,21 +787,95 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   X(96, 160) X(160, 96) X(64, 160) X(160, 64) X(32, 160) X(160, 32)
 
 typedef void (*LaunchFn)(Exec &, const GemmArgs &, int);
+typedef int (*OccFn)(const GemmArgs &);
 struct Tile {
   int bm, bn;
   LaunchFn fn;
+  OccFn occ;
 };
 
-// Pick the tile with the lowest modelled time: padded MACs, an operand-load
-// overhead that grows as the tile shrinks (coefficient load_coef), the number
-// of rounds of ~2048 resident waves, and the split reduction's traffic.  The
+// Compute units of the device (queried once; the library runs on one GPU model).
+inline int cu_count() {
+  static std::atomic<int> n{0};
+  int c = n.load(std::memory_order_relaxed);
+  if (c > 0) return c;
+  int dev = 0;
+  MLCC_HIP(hipGetDevice(&dev));
+  MLCC_HIP(hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev));
+  c = std::max(c, 1);
+  n.store(c, std::memory_order_relaxed);
+  return c;
+}
+
+// Forced tile (mlcc_gemm_tile): index of bm x bn in the menu, or -1.
+inline int forced_tile(const Tile *tiles, int ntiles) {
+  const int fm = g_force_bm.load(std::memory_order_relaxed);
+  const int fn = g_force_bn.load(std::memory_order_relaxed);
+  for (int t = 0; t < ntiles; ++t)
+    if (tiles[t].bm == fm && tiles[t].bn == fn) return t;
+  return -1;  // none, or one this menu lacks: the cost model decides
+}
+
+inline void launch_chosen(Exec &ex, const GemmArgs &a, const Tile &t, int splits) {
+  g_last_bm.store(t.bm, std::memory_order_relaxed);
+  g_last_bn.store(t.bn, std::memory_order_relaxed);
+  t.fn(ex, a, splits);
+}
+
+// FP64 MFMA kernels: pick the tile (and split count) with the lowest modelled
+// time.  Per k-step a wave issues (bm/32)(bn/32) groups of sixteen 4x4x4
+// products of 16 cycles, W cycles in all, and waits about kStepLatency cycles
+// (global load, LDS store, barrier, LDS read) that only the other resident
+// blocks of its CU can hide: r resident blocks take max(r W, W + kStepLatency)
+// cycles per k-step.  r is at most the kernel's occupancy; the split count is
+// the largest that keeps every block resident at once; a split reduction adds
+// its partial sums' traffic (16 bytes each at ~5 TB/s) and a launch.  The
+// constants were fitted to tile sweeps of the MLCC2 Jacobian's contractions
+// (10 to 2800 us) and checked on a 4096^3 product.  The FP32 kernels keep the
+// load-coefficient model below: on them this one picked slower large tiles.
+template <typename T, typename TC>
+void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles) {
+  constexpr int BK = Tr<T>::BK;
+  constexpr double kStepLatency = 3000.0, kClockMHz = 2400.0, kUsPerPartialByte = 0.2e-6;
+  const int64_t steps = a.R * cdiv(a.K, BK);
+  const int64_t ncu = cu_count();
+  const int forced = forced_tile(tiles, ntiles);
+  int best = -1, best_s = 1;
+  double best_us = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    if (forced >= 0 && t != forced) continue;
+    const int bm = tiles[t].bm, bn = tiles[t].bn;
+    const int64_t occ = tiles[t].occ(a);
+    const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
+    int64_t s = 1;
+    if (blocks < occ * ncu && steps >= 8)
+      s = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(occ * ncu / blocks, steps / 4), 128));
+    const int64_t nb = blocks * s;
+    const int64_t r = std::min<int64_t>(occ, cdiv(nb, ncu));
+    const int64_t rounds = cdiv(nb, ncu * r);
+    const double W = 256.0 * (bm / 32) * (bn / 32);
+    double us = (double)rounds * (double)cdiv(steps, s) * std::max((double)r * W, W + kStepLatency) / kClockMHz;
+    if (s > 1) us += kUsPerPartialByte * 16.0 * (double)s * a.Z * a.M * a.N + 3.0;
+    if (best < 0 || us < best_us) {
+      best = t;
+      best_s = (int)s;
+      best_us = us;
+    }
+  }
+  launch_chosen(ex, a, tiles[best], best_s);
+}
+
+// FP32 MFMA and split BF16 kernels: pick the tile with the lowest modelled
+// time: padded MACs, an operand-load overhead that grows as the tile shrinks
+// (coefficient load_coef, 16 for FP32 MFMA), the number of rounds of ~2048
+// resident waves, and the split reduction's traffic.  The
 // split BF16 kernel takes a larger coefficient: its per-k-step work (the
 // hi/lo split, two LDS rows per element) grows with the tile's perimeter, and
 // with 48 the model picks the measured best tile on each of the shapes swept
 // (a 4096^3 product, the batch-reduced 400 x 160 x 480000, 2250 x 9000 x
 // 1200, 14400 x 144 x 14400).
 template <typename T, typename TC>
-void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles, double load_coef = 16.0) {
+void dispatch_load(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles, double load_coef) {
   constexpr int BK = Tr<T>::BK;
   const int64_t steps = a.R * cdiv(a.K, BK);
   auto waves_of = [](int bm, int bn) { return (bm % 32 == 0 ? 2 : 1) * (bn % 32 == 0 ? 2 : 1); };
@@ -794,16 +891,12 @@ void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles, double
     }
     return s;
   };
-  int fm = g_force_bm.load(std::memory_order_relaxed);
-  int fn = g_force_bn.load(std::memory_order_relaxed);
-  bool listed = false;
-  for (int t = 0; t < ntiles; ++t) listed = listed || (tiles[t].bm == fm && tiles[t].bn == fn);
-  if (!listed) fm = fn = 0;  // a forced tile this menu lacks: the cost model decides
+  const int forced = forced_tile(tiles, ntiles);
   int best = -1;
   double best_cost = 0.0;
   for (int t = 0; t < ntiles; ++t) {
     const int bm = tiles[t].bm, bn = tiles[t].bn, nw = waves_of(bm, bn);
-    if (fm > 0 && (bm != fm || bn != fn)) continue;
+    if (forced >= 0 && t != forced) continue;
     const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
     const int s = splits_for(blocks, nw);
     const double rounds = std::ceil((double)(blocks * s * nw) / 2048.0);
@@ -817,10 +910,7 @@ void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles, double
     }
   }
   const int bm = tiles[best].bm, bn = tiles[best].bn;
-  g_last_bm.store(bm, std::memory_order_relaxed);
-  g_last_bn.store(bn, std::memory_order_relaxed);
-  const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
-  tiles[best].fn(ex, a, splits_for(blocks, waves_of(bm, bn)));
+  launch_chosen(ex, a, tiles[best], splits_for(cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z, waves_of(bm, bn)));
 }
 
 }  // namespace gk
