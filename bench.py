@@ -168,7 +168,7 @@ def _mlccsd_leg(mlcc, steps, warmup, precisions, config="mlccsd_60_600_2000", nv
 
 
 def _cnto_leg(mlcc, precisions=("fp64", "bf16x3"), config="mlcc2_40_400_1200", n_states=4):
-    """Orbital selection (Sec. 2.3) at a full-size workload: CCS roots in the
+    """Orbital selection (Sec. 2.2) at a full-size workload: CCS roots in the
     canonical basis, CNTOs from them with n_vir_act = (n_vir / n_occ) n_occ_act
     (eq. select_CNTOs), then MLCC2 on the new orbitals with their full Fock
     matrix.  Cholesky vectors drawn on the device (seed 0), canonical orbital

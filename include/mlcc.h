@@ -98,7 +98,7 @@ typedef struct {
   uint64_t seed;                  /* seed of MLCC_SYNTH_L */
   const double *fock;             /* [n][n] symmetric Fock matrix (host or device), or
                                      NULL for diag(eps).  For a semicanonical basis
-                                     (Sec. 2.3: the Fock matrix diagonal within the
+                                     (Sec. 2.2: the Fock matrix diagonal within the
                                      active and within the inactive orbitals, as
                                      mlcc_cnto returns it); eps must be its diagonal,
                                      which the denominators use.  The occupied-virtual
@@ -262,7 +262,7 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
                        const int64_t sC[3], const int64_t lvl[6]);
 
 /* ---- orbital selection ------------------------------------------------------
- * Correlated natural transition orbitals from CCS excitation vectors (Sec. 2.3:
+ * Correlated natural transition orbitals from CCS excitation vectors (Sec. 2.2:
  * eqs. M, N, approx_double_1, approx_double_2, select_CNTOs).  prob: a problem
  * in the canonical (or semicanonical) basis of the full space; its L, Fock
  * matrix and precision are used, whatever its model.  R [n_states][n_vir][n_occ]

@@ -3,9 +3,12 @@
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
 execute anything in this package: only the test-suite, the smoke check and the
 CPU-baseline leg of the benchmark use it.  It shares no code with the HIP
-library and is deliberately plain and slow: NumPy in float64 (complex128 where
+library and is deliberately plain and slow: float64 arrays (complex128 where
 a derivative is taken by complex step), every step written as the equation it
-follows, with the contraction order left to ``numpy.einsum``.
+follows.  Multi-index contractions are written as einsum expressions; the
+helper ``mlcc._einsum`` evaluates each along numpy's optimal pairwise path,
+one pairwise product at a time through torch.einsum on the CPU (host BLAS),
+which changes only the rounding order.
 
 Modules
   mlcc        residual, energy, ground state, Jacobian transform (complex step),

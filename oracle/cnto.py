@@ -1,13 +1,15 @@
 """Correlated natural transition orbitals (CNTOs) from CCS excitation vectors,
-and the semicanonical basis the multilevel models run in (Sec. 2.3: eqs. M,
+and the semicanonical basis the multilevel models run in (Sec. 2.2: eqs. M,
 N, approx_double_1, approx_double_2 and select_CNTOs) -- plain FP64 oracle.
 
 TEST INFRASTRUCTURE ONLY -- never called by the product path.
 
-Pinned by tests/test_oracle_cnto.py.  One factor is parity unpinned: the
-1/(1 + delta_{ai,bj}) of eq. approx_double_1 on the diagonal pairs, taken as
-printed (the derivative form of gbar, the delta terms of eqs. M and N and the
-semicanonical basis are pinned).
+Pinned by tests/test_oracle_cnto.py: gbar as the derivative of the X1
+transformed g_aibj, the approximate doubles (with their 1/(1 + delta_{ai,bj})
+on the diagonal pairs) as the first-order CIS(D)-type doubles of the CCS
+state on explicit determinants, read as packed amplitudes of
+sum_{ai >= bj} r_aibj E_ai E_bj, the delta terms of eqs. M and N and the
+semicanonical basis.
 
 Everything here is in the canonical basis of the full problem: L [K, n, n],
 eps [n] (occupied first), a CCS excitation vector R [V, O] with its excitation
@@ -75,7 +77,7 @@ def _semicanonical(U, F, n_act):
 
 
 def cnto_basis(L, eps, d: Dims, Rs, ws, n_occ_act, n_vir_act, fock=None):
-    """Sec. 2.3: sum M and N over the excitations, diagonalise them, take the
+    """Sec. 2.2: sum M and N over the excitations, diagonalise them, take the
     eigenvectors of the largest eigenvalues as the active orbitals (occupied
     and virtual separately), then make the active and inactive blocks
     semicanonical.  Returns a dict with

@@ -118,7 +118,7 @@ def two_electron_fock(L, d: Dims):
 def core_hamiltonian(L, eps, d: Dims, fock=None):
     """One-electron integrals h implied by the reference: F = h + G(D_HF), so
     h = F - G with F = diag(eps) (canonical) or a given Fock matrix (e.g. the
-    semicanonical basis of Sec. 2.3, whose active-inactive blocks couple)."""
+    semicanonical basis of Sec. 2.2, whose active-inactive blocks couple)."""
     F = np.diag(eps).astype(L.dtype) if fock is None else np.asarray(fock, dtype=L.dtype)
     return F - two_electron_fock(L, d)
 

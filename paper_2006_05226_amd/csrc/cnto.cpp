@@ -1,5 +1,5 @@
 // Correlated natural transition orbitals (CNTOs) from CCS excitation vectors
-// and the semicanonical basis the multilevel models run in (Sec. 2.3: eqs. M,
+// and the semicanonical basis the multilevel models run in (Sec. 2.2: eqs. M,
 // N, approx_double_1, approx_double_2 and select_CNTOs).
 //
 // For each excitation (R, w), over the full orbital space (pair p = a*O + i):

@@ -1,4 +1,4 @@
-"""CNTO orbital selection (Sec. 2.3) and the full-Fock model input on the GPU
+"""CNTO orbital selection (Sec. 2.2) and the full-Fock model input on the GPU
 against the FP64 oracle: the M / N spectra, the semicanonical Fock matrix, the
 rotation and the rotated Cholesky vectors from the same excitation vectors;
 the whole pipeline CCS -> CNTOs -> MLCC2; and MLCC2 / MLCCSD with a

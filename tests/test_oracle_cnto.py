@@ -1,4 +1,4 @@
-"""Pins of the CNTO oracle (Sec. 2.3: eqs. M, N, approx_double_1,
+"""Pins of the CNTO oracle (Sec. 2.2: eqs. M, N, approx_double_1,
 approx_double_2, select_CNTOs) and of the full-Fock (semicanonical) model
 input, against facts the definitions fix (CPU only).
 
@@ -11,17 +11,19 @@ input, against facts the definitions fix (CPU only).
 * a full active space gives back the canonical orbitals: MLCC2 there is CC2
 * MLCC2 with the full Fock matrix is unchanged by rotations among the inactive
   occupied or among the inactive virtual orbitals
+* the approximate doubles of eq. approx_double_1 are the first-order
+  (CIS(D)-type) doubles of the CCS state, -(F - <F>_HF - w)^-1 P_2 H R_1|HF>,
+  built on explicit determinants and read as the amplitudes r of the operator
+  sum_{ai >= bj} r_aibj E_ai E_bj: this fixes the 1/(1 + delta_{ai,bj}) factor
+  on the diagonal pairs
 * planted mistakes fail these pins
-
-The factor 1/(1 + delta_{ai,bj}) of eq. approx_double_1 on the diagonal pairs
-is taken as printed; no pin fixes it independently (parity unpinned for that
-factor; every other part of the approximate doubles is pinned above).
 """
 import numpy as np
 import pytest
 
 from oracle import cnto as oc
 from oracle import mlcc as om
+from oracle.bruteforce import DetSpace
 from paper_2006_05226_amd.synth import gen_inputs
 
 pytestmark = pytest.mark.filterwarnings("ignore::numpy.exceptions.ComplexWarning")
@@ -60,6 +62,52 @@ def packed_doubles_norm2(R2):
         for q in range(p + 1):
             s += X[p, q] ** 2
     return s
+
+
+def first_order_doubles_packed(inp, d, R, w):
+    """-(F - <F>_HF - w)^-1 P_2 H R_1 |HF> on explicit determinants (R_1 =
+    sum_ai R_ai E_ai, F = sum_p eps_p E_pp), as the coefficients r_aibj of
+    sum_{ai >= bj} r_aibj E_ai E_bj |HF> (returned as a symmetric (V,O,V,O)
+    array)."""
+    S = DetSpace(d.n, d.O)
+    H = S.hamiltonian(om.core_hamiltonian(inp.L, inp.eps, d), om.eri(inp.L))
+    f = np.diag(S.fock_op(np.diag(inp.eps)))     # F is diagonal on determinants
+    hf = S.hf_vector()
+    vec = H @ (S.t1_op(R) @ hf)
+    two = S.level == 2
+    D = np.zeros_like(vec)
+    D[two] = -vec[two] / (f[two] - f[S.hf] - w)
+    # project() returns the biorthonormal coordinates: the ket coefficient on
+    # ai != bj, twice it on ai = bj
+    _, bio = S.project(D)
+    n1 = d.V * d.O
+    packed = bio.reshape(n1, n1).copy()
+    packed[np.arange(n1), np.arange(n1)] *= 0.5
+    return packed.reshape(d.V, d.O, d.V, d.O)
+
+
+def test_approx_doubles_are_packed_first_order_doubles():
+    """eq. approx_double_1 (with eq. approx_double_2) against the CIS(D)-type
+    first-order doubles built from their definition on determinants; the
+    diagonal pairs carry the 1/(1 + delta_{ai,bj}) of the packed amplitudes."""
+    inp, d = setup(O=2, V=3, J=12, seed=5)
+    w, Rs = cis_vectors(inp, d, 3)
+    n1 = d.V * d.O
+    for R, wk in zip(Rs, w):
+        ref = first_order_doubles_packed(inp, d, R, wk)
+        got = oc.approx_doubles(inp.L, inp.eps, d, R, wk)
+        scale = np.abs(ref).max()
+        assert scale > 1e-4
+        assert np.abs(got - ref).max() < 1e-12 * scale
+        diag = np.einsum("aiai->ai", ref)
+        assert np.abs(diag).max() > 1e-3 * scale   # the diagonal pairs are exercised
+        # planted mistake: the delta factor dropped (full-array doubles)
+        full = -oc.gbar(inp.L, d, R) / (
+            (inp.eps[d.vir][:, None] - inp.eps[d.occ][None, :])[:, :, None, None]
+            + (inp.eps[d.vir][:, None] - inp.eps[d.occ][None, :])[None, None] - wk)
+        assert np.abs(full - ref).max() > 1e-3 * scale
+        assert np.abs(full.reshape(n1, n1) - ref.reshape(n1, n1))[~np.eye(n1, dtype=bool)].max() \
+            < 1e-12 * scale
 
 
 def test_traces_and_delta_factors():
