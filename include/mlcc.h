@@ -239,28 +239,6 @@ mlcc_status mlcc_poll(mlcc_server *srv, uint64_t ticket, mlcc_result *out);
 uint64_t mlcc_request_footprint(const mlcc_problem_desc *desc, int32_t n_roots,
                                 const mlcc_solver_opts *es_opts);
 
-/* ---- kernel-level entry points (used by the kernel unit tests) -------------
- * Batched, batch-reduced strided GEMM on the device, the engine every
- * Cholesky-index contraction runs on:
- *   C_z[m][n] = alpha * sum_{r<R} sum_{k<K} A_zr[m][k] B_zr[k][n] + beta * C_z[m][n]
- * with A_zr[m][k] at A + z*sA[3] + r*sA[2] + m*sA[0] + k*sA[1] and likewise
- * B (sB = {k, n, r, z}) and C (sC = {m, n, z}).  Device pointers only.
- * prec: MLCC_FP64 (FP64 MFMA), MLCC_FP32 (A, B, C float; FP32 MFMA) or
- * MLCC_BF16X3 (A, B, C float; split BF16 products when A and B are both
- * contiguous along k and laid out for 16-byte loads, FP32 MFMA otherwise). */
-mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int64_t K,
-                      int64_t R, int64_t Z, double alpha, const void *A, const int64_t sA[4],
-                      const void *B, const int64_t sB[4], double beta, void *C,
-                      const int64_t sC[3]);
-
-/* As mlcc_gemm with two-level row and column indices: lvl = {Mlo, sA_m_hi,
- * sC_m_hi, Nlo, sB_n_hi, sC_n_hi}; row m has offset (m/Mlo)*hi + (m%Mlo)*lo
- * (lo = the ordinary stride), columns likewise; Mlo or Nlo 0 = one level. */
-mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int64_t K,
-                       int64_t R, int64_t Z, double alpha, const void *A, const int64_t sA[4],
-                       const void *B, const int64_t sB[4], double beta, void *C,
-                       const int64_t sC[3], const int64_t lvl[6]);
-
 /* ---- orbital selection ------------------------------------------------------
  * Correlated natural transition orbitals from CCS excitation vectors (Sec. 2.2:
  * eqs. M, N, approx_double_1, approx_double_2, select_CNTOs).  prob: a problem
@@ -294,33 +272,6 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
 mlcc_status mlcc_cnto(mlcc_problem *prob, int32_t n_states, const double *R, const double *omega,
                       int32_t n_occ_act, int32_t n_vir_act, double *m_eig, double *n_eig,
                       double *C, double *eps_out, double *fock_out, double *L_out);
-
-/* Tile override of the contraction engine, process-wide, for parity tests
- * and tuning: later engine calls whose tile menu lists the bm x bn output tile
- * use it (with the split count the cost model gives it); bm = bn = 0 restores
- * the cost model.  last (may be NULL) receives the tile of the previous
- * engine call.  MLCC_E_ARG for negative sizes. */
-mlcc_status mlcc_gemm_tile(int32_t bm, int32_t bn, int32_t last[2]);
-
-/* Per-contraction timing: when enabled, every GEMM-engine launch is bracketed
- * by HIP events on the context stream and accumulated under the name of the
- * contraction it computes (e.g. "g_aibj", "ccs_vv").  flops counts the
- * algorithmic 2*M*N*K*R*Z of each launch.  Enabling clears the record. */
-typedef struct {
-  char name[40];
-  int64_t launches;
-  double ms;      /* summed kernel time of the GEMM launches */
-  double flops;   /* summed algorithmic flops */
-} mlcc_kernel_stat;
-mlcc_status mlcc_profile_enable(mlcc_context *ctx, int32_t on);
-/* Fills up to max entries, returns how many there are (synchronises). */
-int32_t mlcc_profile_get(mlcc_context *ctx, mlcc_kernel_stat *out, int32_t max);
-
-/* Internal intermediates for step-by-step parity tests.  which: 0 = F~ [n][n],
- * 1 = L~ [n_chol][n][n] (FP64 copy), 2 = g~_aibj [M][M], 3 = t1 [n_vir][n_occ],
- * 4 = doubles [M][M].  out is host memory of the stated size.  The values are
- * those of the last mlcc_residual / transform call. */
-mlcc_status mlcc_debug_get(mlcc_problem *prob, int32_t which, double *out);
 
 #ifdef __cplusplus
 }

@@ -5,51 +5,12 @@
 #include <cstring>
 #include <numeric>
 
+#include "api_util.h"
 #include "drivers.h"
 
 using namespace mlcc;
 
 namespace {
-
-thread_local std::string g_create_error;
-
-bool is_device_ptr(const void *p) {
-  if (!p) return false;
-  hipPointerAttribute_t at;
-  hipError_t e = hipPointerGetAttributes(&at, p);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return at.type == hipMemoryTypeDevice;
-}
-
-void set_error(mlcc_context *ctx, const std::string &m) {
-  if (!ctx) {
-    g_create_error = m;
-    return;
-  }
-  std::lock_guard<std::mutex> lk(ctx->err_mu);
-  ctx->last_error = m;
-}
-
-template <typename F> mlcc_status guarded(mlcc_context *ctx, F &&f) {
-  try {
-    return f();
-  } catch (const Error &e) {
-    set_error(ctx, e.msg);
-    return e.code;
-  } catch (const std::bad_alloc &) {
-    set_error(ctx, "host allocation failed");
-    return MLCC_E_OOM;
-  } catch (const std::exception &e) {
-    set_error(ctx, e.what());
-    return MLCC_E_DEVICE;
-  } catch (...) {
-    set_error(ctx, "unknown error");
-    return MLCC_E_DEVICE;
-  }
-}
 
 // Stage a caller array (host or device) as a device pointer.
 struct In {
@@ -144,6 +105,8 @@ mlcc_status mlcc_context_create(int device, void *hip_stream, uint64_t hbm_budge
       delete c;
       throw Error{MLCC_E_DEVICE, "pinned host allocation failed"};
     }
+    // the no-allocation engine's array on this device (its address, once)
+    noalloc_scratch_init(device);
     *out = c;
     return MLCC_OK;
   });
@@ -466,26 +429,7 @@ mlcc_status mlcc_davidson_solve(mlcc_problem *P, int32_t n_roots, const mlcc_sol
 mlcc_status mlcc_gemm(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int64_t K, int64_t R,
                       int64_t Z, double alpha, const void *A, const int64_t sA[4], const void *B,
                       const int64_t sB[4], double beta, void *C, const int64_t sC[3]) {
-  if (!ctx) return MLCC_E_ARG;
-  return guarded(ctx, [&]() -> mlcc_status {
-    MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32 || prec == MLCC_BF16X3, MLCC_E_ARG,
-                 "bad precision");
-    MLCC_REQUIRE(M >= 0 && N >= 0 && K >= 0 && R >= 1 && Z >= 1, MLCC_E_ARG, "bad sizes");
-    MLCC_REQUIRE(A && B && C && sA && sB && sC, MLCC_E_ARG, "NULL argument");
-    MLCC_REQUIRE(is_device_ptr(A) && is_device_ptr(B) && is_device_ptr(C), MLCC_E_ARG,
-                 "mlcc_gemm takes device pointers");
-    GemmArgs a;
-    a.M = M; a.N = N; a.K = K; a.R = R; a.Z = Z;
-    a.A = A; a.sAm = sA[0]; a.sAk = sA[1]; a.sAr = sA[2]; a.sAz = sA[3];
-    a.B = B; a.sBk = sB[0]; a.sBn = sB[1]; a.sBr = sB[2]; a.sBz = sB[3];
-    a.C = C; a.Cin = C; a.sCm = sC[0]; a.sCn = sC[1]; a.sCz = sC[2];
-    a.alpha = alpha; a.beta = beta;
-    MLCC_HIP(hipSetDevice(ctx->device));
-    gemm(ctx->ex, prec == MLCC_FP64 ? Prec::F64 : prec == MLCC_FP32 ? Prec::F32 : Prec::BF16X3, a,
-         prec == MLCC_FP64);
-    MLCC_HIP(hipStreamSynchronize(ctx->ex.stream));
-    return MLCC_OK;
-  });
+  return mlcc_gemm2(ctx, prec, M, N, K, R, Z, alpha, A, sA, B, sB, beta, C, sC, nullptr);
 }
 
 mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, int64_t K,
@@ -494,24 +438,10 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
                        const int64_t sC[3], const int64_t lvl[6]) {
   if (!ctx) return MLCC_E_ARG;
   return guarded(ctx, [&]() -> mlcc_status {
-    MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32 || prec == MLCC_BF16X3, MLCC_E_ARG,
-                 "bad precision");
-    MLCC_REQUIRE(M >= 0 && N >= 0 && K >= 0 && R >= 1 && Z >= 1, MLCC_E_ARG, "bad sizes");
-    MLCC_REQUIRE(A && B && C && sA && sB && sC && lvl, MLCC_E_ARG, "NULL argument");
-    MLCC_REQUIRE(lvl[0] >= 0 && lvl[3] >= 0, MLCC_E_ARG, "bad two-level sizes");
-    MLCC_REQUIRE(is_device_ptr(A) && is_device_ptr(B) && is_device_ptr(C), MLCC_E_ARG,
-                 "mlcc_gemm2 takes device pointers");
-    GemmArgs a;
-    a.M = M; a.N = N; a.K = K; a.R = R; a.Z = Z;
-    a.A = A; a.sAm = sA[0]; a.sAk = sA[1]; a.sAr = sA[2]; a.sAz = sA[3];
-    a.B = B; a.sBk = sB[0]; a.sBn = sB[1]; a.sBr = sB[2]; a.sBz = sB[3];
-    a.C = C; a.Cin = C; a.sCm = sC[0]; a.sCn = sC[1]; a.sCz = sC[2];
-    a.alpha = alpha; a.beta = beta;
-    a.Mlo = lvl[0]; a.sAm_hi = lvl[1]; a.sCm_hi = lvl[2];
-    a.Nlo = lvl[3]; a.sBn_hi = lvl[4]; a.sCn_hi = lvl[5];
+    check_engine_args(prec, M, N, K, R, Z, A, sA, B, sB, C, sC, lvl, "mlcc_gemm");
+    const GemmArgs a = engine_args(M, N, K, R, Z, alpha, A, sA, B, sB, beta, C, sC, lvl);
     MLCC_HIP(hipSetDevice(ctx->device));
-    gemm(ctx->ex, prec == MLCC_FP64 ? Prec::F64 : prec == MLCC_FP32 ? Prec::F32 : Prec::BF16X3, a,
-         prec == MLCC_FP64);
+    gemm(ctx->ex, engine_prec(prec), a, prec == MLCC_FP64);
     MLCC_HIP(hipStreamSynchronize(ctx->ex.stream));
     return MLCC_OK;
   });
@@ -542,14 +472,14 @@ mlcc_status mlcc_cnto(mlcc_problem *P, int32_t n_states, const double *R, const 
   });
 }
 
-mlcc_status mlcc_gemm_tile(int32_t bm, int32_t bn, int32_t last[2]) {
-  if (bm < 0 || bn < 0) return MLCC_E_ARG;
+mlcc_status mlcc_gemm_tile(mlcc_context *ctx, int32_t bm, int32_t bn, int32_t last[2]) {
+  if (!ctx || bm < 0 || bn < 0) return MLCC_E_ARG;
   if (last) {
-    last[0] = gk::g_last_bm.load();
-    last[1] = gk::g_last_bn.load();
+    last[0] = ctx->ex.last_bm;
+    last[1] = ctx->ex.last_bn;
   }
-  gk::g_force_bm.store(bm);
-  gk::g_force_bn.store(bn);
+  ctx->ex.force_bm = bm;
+  ctx->ex.force_bn = bn;
   return MLCC_OK;
 }
 

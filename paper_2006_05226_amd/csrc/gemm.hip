@@ -4,10 +4,6 @@
 
 namespace mlcc {
 
-namespace gk {
-std::atomic<int> g_force_bm{0}, g_force_bn{0}, g_last_bm{0}, g_last_bn{0};
-}
-
 std::pair<hipEvent_t, hipEvent_t> Profiler::next() {
   if (used == pool.size()) {
     hipEvent_t a, b;

@@ -710,7 +710,15 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   MLCC_REQUIRE(kp.per_xcd * kXcd < (int64_t)1 << 31, MLCC_E_ARG, "gemm: grid too large");
   typedef typename std::conditional<sizeof(T) == 8, double, float>::type acc_t;
   kp.work = nullptr;
-  if (splits > 1) kp.work = ex.scratch(sizeof(acc_t) * (size_t)splits * a.Z * a.M * a.N);
+  if (splits > 1) {
+    const size_t need = sizeof(acc_t) * (size_t)splits * a.Z * a.M * a.N;
+    if (a.work) {
+      MLCC_REQUIRE(need <= a.work_cap, MLCC_E_ARG, "gemm: split partials exceed the workspace");
+      kp.work = a.work;
+    } else {
+      kp.work = ex.scratch(need);
+    }
+  }
   // layouts: an operand is staged [k][m] when m has the smaller stride
   const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
   const bool bkn = std::llabs(a.sBn) < std::llabs(a.sBk);
@@ -807,19 +815,26 @@ inline int cu_count() {
   return c;
 }
 
-// Forced tile (mlcc_gemm_tile): index of bm x bn in the menu, or -1.
-inline int forced_tile(const Tile *tiles, int ntiles) {
-  const int fm = g_force_bm.load(std::memory_order_relaxed);
-  const int fn = g_force_bn.load(std::memory_order_relaxed);
+// Forced tile of the lane (mlcc_gemm_tile): index of bm x bn in the menu, or -1.
+inline int forced_tile(const Exec &ex, const Tile *tiles, int ntiles) {
   for (int t = 0; t < ntiles; ++t)
-    if (tiles[t].bm == fm && tiles[t].bn == fn) return t;
+    if (tiles[t].bm == ex.force_bm && tiles[t].bn == ex.force_bn) return t;
   return -1;  // none, or one this menu lacks: the cost model decides
 }
 
 inline void launch_chosen(Exec &ex, const GemmArgs &a, const Tile &t, int splits) {
-  g_last_bm.store(t.bm, std::memory_order_relaxed);
-  g_last_bn.store(t.bn, std::memory_order_relaxed);
+  ex.last_bm = t.bm;
+  ex.last_bn = t.bn;
   t.fn(ex, a, splits);
+}
+
+// With a caller workspace the split count is bounded by what fits in it.
+template <typename T> inline int64_t cap_splits(const GemmArgs &a, int64_t s) {
+  if (!a.work || s <= 1) return s;
+  typedef typename std::conditional<sizeof(T) == 8, double, float>::type acc_t;
+  const double per = (double)sizeof(acc_t) * (double)a.Z * (double)a.M * (double)a.N;
+  const int64_t fit = (int64_t)std::floor((double)a.work_cap / per);
+  return std::max<int64_t>(1, std::min<int64_t>(s, fit));
 }
 
 // FP64 MFMA kernels: pick the tile (and split count) with the lowest modelled
@@ -839,7 +854,7 @@ void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles) {
   constexpr double kStepLatency = 3000.0, kClockMHz = 2400.0, kUsPerPartialByte = 0.2e-6;
   const int64_t steps = a.R * cdiv(a.K, BK);
   const int64_t ncu = cu_count();
-  const int forced = forced_tile(tiles, ntiles);
+  const int forced = forced_tile(ex, tiles, ntiles);
   int best = -1, best_s = 1;
   double best_us = 0.0;
   for (int t = 0; t < ntiles; ++t) {
@@ -850,6 +865,7 @@ void dispatch(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles) {
     int64_t s = 1;
     if (blocks < occ * ncu && steps >= 8)
       s = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(occ * ncu / blocks, steps / 4), 128));
+    s = cap_splits<T>(a, s);
     const int64_t nb = blocks * s;
     const int64_t r = std::min<int64_t>(occ, cdiv(nb, ncu));
     const int64_t rounds = cdiv(nb, ncu * r);
@@ -889,9 +905,9 @@ void dispatch_load(Exec &ex, const GemmArgs &a, const Tile *tiles, int ntiles, d
       s = (int)std::min<int64_t>(target / blocks, steps / 4);
       s = std::max(1, std::min(s, 128));
     }
-    return s;
+    return (int)cap_splits<T>(a, s);
   };
-  const int forced = forced_tile(tiles, ntiles);
+  const int forced = forced_tile(ex, tiles, ntiles);
   int best = -1;
   double best_cost = 0.0;
   for (int t = 0; t < ntiles; ++t) {

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/mlcc.h"
+#include "../../include/mlcc_engine.h"
 
 namespace mlcc {
 
@@ -113,6 +114,10 @@ struct Exec {
   DBuf work;      // split-K partials
   DBuf red;       // reduction partials (dot products)
   double *pinned = nullptr;    // pinned host scalars (512 doubles) for results
+  // Tile override of the contraction engine on this lane (parity tests,
+  // tuning): a forced bm x bn is used by every call whose menu has it; the
+  // tile of the lane's last dispatched call is kept.
+  int force_bm = 0, force_bn = 0, last_bm = 0, last_bn = 0;
   void *scratch(size_t bytes) {
     work.ensure(al, bytes);
     return work.p;
@@ -149,6 +154,11 @@ struct GemmArgs {
   bool slack = false;
   // set by gemm(): FP32 operands may run on the BF16 matrix cores (split products)
   bool bf16x3 = false;
+  // Caller-provided workspace for split partial sums (work_cap bytes): when
+  // set, the engine allocates nothing and uses only as many reduction splits
+  // as fit in it.
+  void *work = nullptr;
+  size_t work_cap = 0;
 };
 
 // prec selects the operand type (double or float) and the MFMA; out_f64
@@ -156,11 +166,6 @@ struct GemmArgs {
 // accumulator written out as double).
 void gemm(Exec &ex, Prec prec, const GemmArgs &a, bool out_f64);
 
-namespace gk {
-// Tile override (parity tests, tuning): a forced bm x bn is used by every
-// call whose menu has it; the tile of the last dispatched call is kept.
-extern std::atomic<int> g_force_bm, g_force_bn, g_last_bm, g_last_bn;
-}
 
 // ---------------------------------------------------------------------------
 // element-wise and reduction kernels (kernels.hip)

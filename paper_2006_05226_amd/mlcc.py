@@ -69,8 +69,10 @@ EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "ml
            "mlcc_set_amplitudes", "mlcc_residual", "mlcc_ground_state",
            "mlcc_jacobian_transform", "mlcc_jacobian_transform_eff", "mlcc_davidson_solve",
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
-           "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_debug_get", "mlcc_profile_enable",
-           "mlcc_profile_get", "mlcc_gemm_tile", "mlcc_cnto"]
+           "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_gemm_noalloc",
+           "mlcc_debug_get", "mlcc_profile_enable", "mlcc_profile_get", "mlcc_gemm_tile", "mlcc_cnto"]
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 _lib = None
 
@@ -108,10 +110,12 @@ def load(path: str = LIB_PATH):
                             vp, P(i64)]),
         "mlcc_gemm2": (i32, [vp, i32, i64, i64, i64, i64, i64, dbl, vp, P(i64), vp, P(i64), dbl,
                              vp, P(i64), P(i64)]),
+        "mlcc_gemm_noalloc": (i32, [vp, i32, i64, i64, i64, i64, i64, dbl, vp, P(i64), vp, P(i64),
+                                    dbl, vp, P(i64), P(i64)]),
         "mlcc_debug_get": (i32, [vp, i32, vp]),
         "mlcc_profile_enable": (i32, [vp, i32]),
         "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
-        "mlcc_gemm_tile": (i32, [i32, i32, P(i32)]),
+        "mlcc_gemm_tile": (i32, [vp, i32, i32, P(i32)]),
         "mlcc_cnto": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -185,12 +189,23 @@ class Context:
         return self.check(self.lib.mlcc_gemm(self.h, prec, M, N, K, R, Z, alpha, _ptr(A), a4,
                                              _ptr(B), b4, beta, _ptr(Cm), c3))
 
+    def gemm_noalloc(self, prec, M, N, K, R, Z, alpha, A, sA, B, sB, beta, Cm, sC, lvl=None):
+        """mlcc_gemm_noalloc: the engine with its split partial sums in the
+        library's fixed device array; enqueued on the context stream, not
+        waited for."""
+        a4 = (C.c_int64 * 4)(*sA)
+        b4 = (C.c_int64 * 4)(*sB)
+        c3 = (C.c_int64 * 3)(*sC)
+        l6 = None if lvl is None else (C.c_int64 * 6)(*lvl)
+        return self.check(self.lib.mlcc_gemm_noalloc(self.h, prec, M, N, K, R, Z, alpha, _ptr(A),
+                                                     a4, _ptr(B), b4, beta, _ptr(Cm), c3, l6))
+
     def gemm_tile(self, bm=0, bn=0):
-        """Force the bm x bn output tile on later engine calls whose tile menu
-        has it (0, 0: the cost model picks); returns the tile of the previous
-        engine call."""
+        """Force the bm x bn output tile on later engine calls of this context
+        whose tile menu has it (0, 0: the cost model picks); returns the tile of
+        the context's previous engine call."""
         last = (C.c_int32 * 2)()
-        self.check(self.lib.mlcc_gemm_tile(bm, bn, last))
+        self.check(self.lib.mlcc_gemm_tile(self.h, bm, bn, last))
         return (last[0], last[1])
 
     def profile(self, on=True):

@@ -1,6 +1,7 @@
-"""The C-ABI library loads and exports every function include/mlcc.h declares
+"""The C-ABI library loads and exports every function include/*.h declares
 (CPU only: no device call is made)."""
 import ctypes
+import glob
 import os
 import re
 
@@ -8,9 +9,11 @@ from paper_2006_05226_amd import mlcc
 
 
 def header_functions(root):
-    text = open(os.path.join(root, "include", "mlcc.h")).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(mlcc_[a-z0-9_]+)\s*\(", text)))
+    names = set()
+    for h in sorted(glob.glob(os.path.join(root, "include", "*.h"))):
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names.update(re.findall(r"\b(mlcc_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol(root):
@@ -41,13 +44,25 @@ def test_create_error_without_gpu_is_reported():
 
 
 def test_tile_override_arguments():
-    """mlcc_gemm_tile needs no device: negative sizes are refused, 0 x 0
-    restores the cost model and the previous call's tile is reported."""
+    """mlcc_gemm_tile is per context: without one it is refused, never a crash."""
     lib = mlcc.load()
-    assert lib.mlcc_gemm_tile(-1, 32, None) == mlcc.E_ARG
     last = (ctypes.c_int32 * 2)()
-    assert lib.mlcc_gemm_tile(128, 96, last) == 0
-    assert lib.mlcc_gemm_tile(0, 0, last) == 0
+    assert lib.mlcc_gemm_tile(None, 128, 96, last) == mlcc.E_ARG
+    assert lib.mlcc_gemm_tile(None, -1, 32, None) == mlcc.E_ARG
+
+
+def test_noalloc_engine_arguments():
+    """mlcc_gemm_noalloc refuses a NULL context without touching a device, and
+    its scratch size is the one the header states."""
+    lib = mlcc.load()
+    s4 = (ctypes.c_int64 * 4)(1, 1, 0, 0)
+    s3 = (ctypes.c_int64 * 3)(1, 1, 0)
+    assert lib.mlcc_gemm_noalloc(None, mlcc.FP64, 1, 1, 1, 1, 1, 1.0, None, s4, None, s4, 0.0,
+                                 None, s3, None) == mlcc.E_ARG
+    text = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                             "include", "mlcc_engine.h")).read()
+    m = re.search(r"#define MLCC_NOALLOC_SCRATCH_BYTES \(\(uint64_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == mlcc.NOALLOC_SCRATCH_BYTES
 
 
 def test_cnto_and_fock_argument_checks():
