@@ -87,6 +87,15 @@ mlcc_status mlcc_gemm_noalloc(mlcc_context *ctx, int32_t prec, int64_t M, int64_
  * context or negative sizes. */
 mlcc_status mlcc_gemm_tile(mlcc_context *ctx, int32_t bm, int32_t bn, int32_t last[2]);
 
+/* Occupied indices per pair block of the MLCC2 doubles (the ground state
+ * with the analytic s2 and the effective transformation build g~ and c2 per
+ * occupied-pair block (I, J), I <= J) on problems of this context: occ > 0
+ * forces blocks of occ occupied indices (the last one ragged), 0 restores the
+ * memory rule (the largest blocks whose buffers fit in 4 GB).  For tests that
+ * cover diagonal, off-diagonal and ragged blocks, and for tuning.  MLCC_E_ARG
+ * for a NULL context or a negative occ. */
+mlcc_status mlcc_pair_block_occ(mlcc_context *ctx, int32_t occ);
+
 /* Per-contraction timing: when enabled, every GEMM-engine launch on the
  * context's stream is bracketed by HIP events and accumulated under the name
  * of the contraction it computes (e.g. "g_aibj", "ccs_vv").  flops counts

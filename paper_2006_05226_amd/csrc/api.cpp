@@ -193,6 +193,7 @@ mlcc_status mlcc_set_amplitudes(mlcc_problem *P, const double *t1, const double 
     const int64_t MM = P->d.M * P->d.M;
     if (P->has_doubles()) {
       if (x2) {
+        P->ensure_doubles();
         In b(*P, x2, MM);
         MLCC_HIP(hipMemcpyAsync(P->x2(), b.p, MM * sizeof(double), hipMemcpyDeviceToDevice,
                                 ex.stream));
@@ -216,7 +217,17 @@ mlcc_status mlcc_residual(mlcc_problem *P, double *omega1, double *omega2, doubl
   return guarded(P->ctx, [&]() -> mlcc_status {
     MLCC_REQUIRE(P->have_amp, MLCC_E_STATE, "no amplitudes set");
     MLCC_REQUIRE(omega1 != nullptr, MLCC_E_ARG, "NULL omega1");
-    P->compute_state(false);
+    // MLCC2 keeps its doubles arrays only on request
+    P->want_s = x2_out != nullptr && P->has_doubles();
+    P->want_om2 = omega2 != nullptr && P->has_doubles();
+    if (P->want_s || P->want_om2) P->ensure_doubles();
+    try {
+      P->compute_state(false);
+    } catch (...) {
+      P->want_s = P->want_om2 = false;
+      throw;
+    }
+    P->want_s = P->want_om2 = false;
     Exec &ex = *P->ex;
     const int64_t MM = P->d.M * P->d.M;
     Out o1(*P, omega1, P->d.n1);
@@ -225,7 +236,7 @@ mlcc_status mlcc_residual(mlcc_problem *P, double *omega1, double *omega2, doubl
     o1.commit();
     if (omega2 && P->has_doubles()) {
       Out o2(*P, omega2, MM);
-      MLCC_HIP(hipMemcpyAsync(o2.p, P->om.as<double>() + P->d.n1, MM * sizeof(double),
+      MLCC_HIP(hipMemcpyAsync(o2.p, P->om2(), MM * sizeof(double),
                               hipMemcpyDeviceToDevice, ex.stream));
       o2.commit();
       MLCC_HIP(hipStreamSynchronize(ex.stream));
@@ -483,6 +494,12 @@ mlcc_status mlcc_gemm_tile(mlcc_context *ctx, int32_t bm, int32_t bn, int32_t la
   return MLCC_OK;
 }
 
+mlcc_status mlcc_pair_block_occ(mlcc_context *ctx, int32_t occ) {
+  if (!ctx || occ < 0) return MLCC_E_ARG;
+  ctx->pair_occ = occ;
+  return MLCC_OK;
+}
+
 mlcc_status mlcc_profile_enable(mlcc_context *ctx, int32_t on) {
   if (!ctx) return MLCC_E_ARG;
   return guarded(ctx, [&]() -> mlcc_status {
@@ -536,9 +553,9 @@ mlcc_status mlcc_debug_get(mlcc_problem *P, int32_t which, double *out) {
     switch (which) {
       case 0: MLCC_REQUIRE(P->Ft.p, MLCC_E_STATE, "no state"); get(P->Ft.p, n2, false); break;
       case 1: MLCC_REQUIRE(P->Lt.p, MLCC_E_STATE, "no state"); get(P->Lt.p, J * n2, f32); break;
-      case 2: MLCC_REQUIRE(P->g.p, MLCC_E_STATE, "no g"); get(P->g.p, MM, false); break;
+      case 2: MLCC_REQUIRE(P->g.p, MLCC_E_STATE, "g~ is not stored"); get(P->g.p, MM, false); break;
       case 3: get(P->t1(), P->d.n1, false); break;
-      case 4: get(P->x2(), MM, false); break;
+      case 4: MLCC_REQUIRE(P->x2(), MLCC_E_STATE, "no doubles stored"); get(P->x2(), MM, false); break;
       default: throw Error{MLCC_E_ARG, "unknown debug quantity"};
     }
     return MLCC_OK;

@@ -335,12 +335,14 @@ __device__ __forceinline__ void epilogue(const KParams &kp, const Acc4 (&acc)[FM
         const int64_t row = m0 + wm * WTM + i * 16 + OutMap<T, ROTA>::row(lane, e);
         if (row >= p.M) continue;
         const int64_t roff = two_level(row, p.Mlo, p.sCm, p.sCm_hi);
+        const double dr = p.den_row ? p.den_row[row] + p.den_shift : 0.0;
 #pragma unroll
         for (int j = 0; j < FN; ++j) {
           if (!cok[j][e]) continue;
           const int64_t o = roff + coff[j][e];
           double out = p.alpha * (double)acc[i][j][e];
           if (p.beta != 0.0) out += p.beta * (double)Cin[o];
+          if (p.den_row) out /= dr + p.den_col[n0 + wn * WTN + j * 16 + OutMap<T, ROTA>::col(lane, e)];
           C[o] = (TC)out;
         }
       }
@@ -657,6 +659,7 @@ __global__ void k_split_reduce(KParams kp) {
                         two_level(col, p.Nlo, p.sCn, p.sCn_hi);
     double out = p.alpha * s;
     if (p.beta != 0.0) out += p.beta * (double)static_cast<const TC *>(p.Cin)[off];
+    if (p.den_row) out /= p.den_row[row] + p.den_col[col] + p.den_shift;
     static_cast<TC *>(p.C)[off] = (TC)out;
   }
 }

@@ -110,22 +110,6 @@ __global__ void k_nonfinite_partial(int64_t n, const double *x, double *part) {
   if (threadIdx.x == 0) part[blockIdx.x] = b;
 }
 
-// s = -g/eps_aibj, u = 2 s - s(i<->j).  ai = a*o + i; s(i<->j)[ai][bj] = s[aj][bi]
-// and eps_ajbi = eps_aibj.
-template <typename TG, typename TU>
-__global__ void k_mlcc2_s_u(int o, int v, const TG *g, const double *eps_ai, double *s, TU *u) {
-  const int64_t M = (int64_t)o * v;
-  GRID_STRIDE(t, M * M) {
-    const int64_t ai = t / M, bj = t - ai * M;
-    const int64_t a = ai / o, i = ai - a * o, b = bj / o, j = bj - b * o;
-    const double den = eps_ai[ai] + eps_ai[bj];
-    const double sv = -(double)g[t] / den;
-    const double sx = -(double)g[(a * o + j) * M + (b * o + i)] / den;
-    if (s) s[t] = sv;
-    u[t] = (TU)(2.0 * sv - sx);
-  }
-}
-
 template <typename TU>
 __global__ void k_u_of(int o, int v, const double *x, TU *u, int nz, int64_t ldx, int64_t ldu,
                        bool occ_rows) {
@@ -165,6 +149,60 @@ __global__ void k_u_of_tiled(int o, int v, const double *x, TU *u, int64_t ldx, 
     const double val = 2.0 * slab[i * S + c] - slab[j * S + bl * o + i];
     const int64_t row = occ_rows ? (int64_t)i * v + a : (int64_t)a * o + i;
     uz[row * M + (int64_t)b0 * o + c] = (TU)val;
+  }
+}
+
+// u = 2x - x(i<->j) on one occupied-pair block of a doubles array.  The block
+// holds rows (i, a) for i in an occupied range I (row (i - i0) v + a) and
+// columns (j, b) for j in a range J (column (j - j0) v + b).  x_ajbi = x_biaj
+// lies in the same block, at row (i, b) and column (j, a), so each v x v
+// sub-block (i, j) is combined with its own transpose: u_ij = 2 x_ij - x_ij^T.
+// A workgroup takes a 32 x 32 tile of a sub-block and the mirrored tile into
+// LDS, so that loads and stores run along contiguous addresses.  u1 receives
+// the block (rows (i, a), leading dimension ldu1); u2, unless NULL, the
+// mirrored block (J, I) of the symmetric u, u2 = u1^T (rows (j, b), ldu2).
+// xs, unless NULL, receives x itself at its a-major place in a full [ai][bj]
+// array (ai = a o + i) and the mirrored place.
+template <typename TU>
+__global__ void k_u_pairblock(int o, int v, int nj, const double *x, int64_t ldx, int64_t sxz,
+                              TU *u1, int64_t ldu1, TU *u2, int64_t ldu2, int64_t suz,
+                              double *xs, int i0, int j0) {
+  __shared__ double t1[32][33], t2[32][33];
+  const int nt = (v + 31) / 32;
+  const int ta = blockIdx.x / nt, tb = blockIdx.x - ta * nt;
+  const int il = blockIdx.y / nj, jl = blockIdx.y - il * nj;
+  const int64_t z = blockIdx.z;
+  x += z * sxz;
+  u1 += z * suz;
+  if (u2) u2 += z * suz;
+  const int a0 = ta * 32, b0 = tb * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t rI = (int64_t)il * v, cJ = (int64_t)jl * v;
+  // t1[a][b] = x[(i, a)][(j, b)],  t2[b][a] = x[(i, b)][(j, a)]
+  for (int y = ty; y < 32; y += 8) {
+    const int a = a0 + y, b = b0 + tx;
+    t1[y][tx] = (a < v && b < v) ? x[(rI + a) * ldx + cJ + b] : 0.0;
+    const int bb = b0 + y, aa = a0 + tx;
+    t2[y][tx] = (bb < v && aa < v) ? x[(rI + bb) * ldx + cJ + aa] : 0.0;
+  }
+  __syncthreads();
+  const int64_t M = (int64_t)o * v;
+  const int i = i0 + il, j = j0 + jl;
+  for (int y = ty; y < 32; y += 8) {
+    const int a = a0 + y, b = b0 + tx;
+    if (a < v && b < v) {
+      u1[(rI + a) * ldu1 + cJ + b] = (TU)(2.0 * t1[y][tx] - t2[tx][y]);
+      if (xs) {
+        xs[((int64_t)a * o + i) * M + (int64_t)b * o + j] = t1[y][tx];
+        xs[((int64_t)b * o + j) * M + (int64_t)a * o + i] = t1[y][tx];
+      }
+    }
+  }
+  if (u2) {
+    for (int y = ty; y < 32; y += 8) {
+      const int b = b0 + y, a = a0 + tx;
+      if (a < v && b < v) u2[(cJ + b) * ldu2 + rI + a] = (TU)(2.0 * t1[tx][y] - t2[y][tx]);
+    }
   }
 }
 
@@ -428,15 +466,6 @@ void nonfinite(Exec &ex, int64_t n, const double *x, double *res) {
   MLCC_HIP(hipGetLastError());
 }
 
-template <typename TG, typename TU>
-void mlcc2_s_u(Exec &ex, int o, int v, const TG *g, const double *eps_ai, double *s, TU *u) {
-  const int64_t M = (int64_t)o * v;
-  if (M == 0) return;
-  hipLaunchKernelGGL((k_mlcc2_s_u<TG, TU>), dim3(blocks_for(M * M)), dim3(TPB), 0, ex.stream, o,
-                     v, g, eps_ai, s, u);
-  MLCC_HIP(hipGetLastError());
-}
-
 template <typename TU>
 void u_of(Exec &ex, int o, int v, const double *x, TU *u, int nz, int64_t ldx, int64_t ldu,
           bool occ_rows) {
@@ -453,6 +482,20 @@ void u_of(Exec &ex, int o, int v, const double *x, TU *u, int nz, int64_t ldx, i
     hipLaunchKernelGGL((k_u_of<TU>), dim3(blocks_for(M * M * nz)), dim3(TPB), 0, ex.stream, o, v,
                        x, u, nz, ldx, ldu, occ_rows);
   }
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TU>
+void u_pairblock(Exec &ex, int o, int v, int ni, int nj, const double *x, int64_t ldx,
+                 int64_t sxz, TU *u1, int64_t ldu1, TU *u2, int64_t ldu2, int64_t suz, int nz,
+                 double *xs, int i0, int j0) {
+  if (v <= 0 || ni <= 0 || nj <= 0 || nz <= 0) return;
+  const int64_t nt = (v + 31) / 32;
+  MLCC_REQUIRE(nt * nt <= 2147483647 && (int64_t)ni * nj <= 65535 && nz <= 65535, MLCC_E_ARG,
+               "u_pairblock: block too large");
+  const dim3 grid((unsigned)(nt * nt), (unsigned)(ni * nj), (unsigned)nz);
+  hipLaunchKernelGGL((k_u_pairblock<TU>), grid, dim3(256), 0, ex.stream, o, v, nj, x, ldx, sxz,
+                     u1, ldu1, u2, ldu2, suz, xs, i0, j0);
   MLCC_HIP(hipGetLastError());
 }
 
@@ -578,13 +621,15 @@ INST_PACK(double, float)
 template void dot_mixed<double, double>(Exec &, int64_t, const double *, const double *, double *);
 template void dot_mixed<float, float>(Exec &, int64_t, const float *, const float *, double *);
 template void dot_mixed<double, float>(Exec &, int64_t, const double *, const float *, double *);
-template void mlcc2_s_u<double, double>(Exec &, int, int, const double *, const double *, double *,
-                                        double *);
-template void mlcc2_s_u<double, float>(Exec &, int, int, const double *, const double *, double *,
-                                       float *);
 template void u_of<double>(Exec &, int, int, const double *, double *, int, int64_t, int64_t,
                            bool);
 template void u_of<float>(Exec &, int, int, const double *, float *, int, int64_t, int64_t, bool);
+template void u_pairblock<double>(Exec &, int, int, int, int, const double *, int64_t, int64_t,
+                                  double *, int64_t, double *, int64_t, int64_t, int, double *,
+                                  int, int);
+template void u_pairblock<float>(Exec &, int, int, int, int, const double *, int64_t, int64_t,
+                                 float *, int64_t, float *, int64_t, int64_t, int, double *, int,
+                                 int);
 template void acc3d<double>(Exec &, int64_t, int64_t, int64_t, double, const double *, int64_t,
                             int64_t, int64_t, double *, int64_t, int64_t);
 template void acc3d<float>(Exec &, int64_t, int64_t, int64_t, double, const float *, int64_t,

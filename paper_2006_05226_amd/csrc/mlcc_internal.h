@@ -154,6 +154,11 @@ struct GemmArgs {
   bool slack = false;
   // set by gemm(): FP32 operands may run on the BF16 matrix cores (split products)
   bool bf16x3 = false;
+  // Optional orbital-energy denominator applied in FP64 by the epilogue:
+  //   C[m][n] = (alpha * acc + beta * Cin[m][n]) / (den_row[m] + den_col[n] + den_shift)
+  // (m, n: output row and column indices, before any two-level mapping).
+  const double *den_row = nullptr, *den_col = nullptr;
+  double den_shift = 0.0;
   // Caller-provided workspace for split partial sums (work_cap bytes): when
   // set, the engine allocates nothing and uses only as many reduction splits
   // as fit in it.
@@ -191,9 +196,6 @@ void fill(Exec &ex, double *x, int64_t n, double v);
 void dot(Exec &ex, int64_t n, const double *x, const double *y, double *res);
 template <typename TA, typename TB>
 void dot_mixed(Exec &ex, int64_t n, const TA *x, const TB *y, double *res);
-// MLCC2 doubles from g~: s = -g/eps_aibj (f64), u = 2s - s(i<->j) (TU)
-template <typename TG, typename TU>
-void mlcc2_s_u(Exec &ex, int o, int v, const TG *g, const double *eps_ai, double *s, TU *u);
 // u = 2x - x(i<->j) of full doubles arrays (TU output); nz arrays, x[z] at
 // x + z*ldx and u[z] at u + z*ldu.  occ_rows: row (a,i) of u is stored at
 // row index i*v + a (columns keep the pair order b*o + j).
@@ -210,6 +212,14 @@ void sym_plus_diag(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *
 template <typename TG, typename TO>
 void sym_div(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
              TO *out, int nz = 1, int64_t sGz = 0, int64_t ldo = 0);
+// u = 2x - x(i<->j) of an occupied-pair block (rows (i, a), i in [i0, i0+ni);
+// columns (j, b), j in [j0, j0+nj); see kernels.hip): u1 the block, u2 (or
+// NULL) its transpose, xs (or NULL) x scattered to a full a-major [ai][bj];
+// nz blocks at strides sxz (x) and suz (u1, u2)
+template <typename TU>
+void u_pairblock(Exec &ex, int o, int v, int ni, int nj, const double *x, int64_t ldx,
+                 int64_t sxz, TU *u1, int64_t ldu1, TU *u2, int64_t ldu2, int64_t suz, int nz,
+                 double *xs, int i0, int j0);
 // dst[z*d_z + r*d_r + c] += alpha * src[z*s_z + r*s_r + c*s_c]
 template <typename TS>
 void acc3d(Exec &ex, int64_t nz, int64_t rows, int64_t cols, double alpha, const TS *src,

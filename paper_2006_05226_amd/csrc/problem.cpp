@@ -10,16 +10,38 @@
 //   L, Lt      [J][n][n]   Cholesky vectors and their X1 transform
 //   Lvo0, Lai  [J][M]      packed active L_ai (untransformed) and L~_ai (MLCCSD)
 //   LaiT       [M][J]      L~_ai pair-major (MLCC2)
-//   Z          [J][M]      Z^K_ai = sum_bj u_ai,bj L^K_bj  (shared by Omega_1
-//                          and the energy)
-//   g, u       [M][M]      g~_aibj and u = 2x - x(i<->j)
-//   amp, om    [n1 + M*M]  (t1 | doubles) and (Omega_1 | Omega_2)
+//   LvoJ       [J+1][o][v] L^K_bj occupied-major (row J: F~_jb), the reduction
+//                          operand of the pair-blocked Z contractions
+//   Z          [J(+1)][M]  Z^K_ai = sum_bj u_ai,bj L^K_bj  (shared by Omega_1
+//                          and the energy; row J: sum_bj u_ai,bj F~_jb)
+//   g, u       [M][M]      g~_aibj and u = 2x - x(i<->j), where stored (below)
+//   amp, om    [n1 (+M*M)] (t1 | MLCCSD t2) and (Omega_1 | Omega_2)
+//   s2, o2     [M][M]      MLCC2 s2 and Omega_2, only when given or asked for
+//
+// MLCC2 with the analytic s2 (the ground state, the Jacobian at its solution)
+// never stores g~ nor any other M x M array of the ground state: the doubles
+// are built per occupied-pair block (I, J), I <= J, of o_b occupied indices
+// each (rows (i in I, a), columns (j in J, b)):
+//   s_IJ = -L~_I^T L~_J / eps   (one GEMM; FP64 denominator in its epilogue)
+//   u_IJ = 2 s_IJ - s_IJ(i<->j) and u_JI = u_IJ^T (one LDS-tiled kernel: the
+//          exchange partner of every element lies in the same block)
+//   Z_I += L_J u_IJ^T, Z_J += L_I u_JI^T   (two GEMMs)
+// which builds the upper pair-triangle of g~ only.  The effective Jacobian
+// transformation treats c2 = P[L~ dL~] / (w - eps) the same way.
 #include "problem.h"
 
 #include <cmath>
 #include <cstring>
 
 namespace mlcc {
+
+// Occupied indices per pair block: nz blocks of (o_b v)^2 values in FP64 (two
+// buffers) and of u in the operand type (two buffers) within kPairBlockBytes.
+int pair_block_occ(int o, int v, int nz, int tsize) {
+  const double per = (double)nz * (16.0 + 2.0 * (double)tsize);
+  const double rows = std::floor(std::sqrt(kPairBlockBytes / per));
+  return (int)std::max(1.0, std::min((double)o, std::floor(rows / std::max(v, 1))));
+}
 
 void *Alloc::get(size_t bytes) {
   const size_t total = bytes + kSlack;
@@ -125,6 +147,11 @@ void mlcc_problem::setup_t(const double *Lsrc, bool dev, const uint64_t *synth_s
     // the u(c2) contraction with L_bj also yields sum_bj u_aibj F~_jb
     Lvo0.alloc(al, (size_t)(J + 1) * d.M * sizeof(T));
     k::pack2d<T, T>(x, off<T>(Lvo0), off<T>(L, (int64_t)O * n), J, n2, d.v, d.o, n);
+    if (model == MLCC_MLCC2) {
+      // the same occupied-major, LvoJ[K][j*v+b] = L^K[O+b][j] (spare row J likewise)
+      LvoJ.alloc(al, (size_t)(J + 1) * d.M * sizeof(T));
+      k::pack2d_t<T, T>(x, off<T>(LvoJ), off<T>(L, (int64_t)O * n), J, n2, d.v, d.o, n);
+    }
   }
   MLCC_HIP(hipStreamSynchronize(x.stream));
 }
@@ -175,6 +202,9 @@ void mlcc_problem::setup(const mlcc_problem_desc &desc) {
   eps_ai.alloc(al, std::max<int64_t>(d.M, 1) * sizeof(double));
   k::denominators(x, d.O, d.V, d.o, d.v, eps.as<double>(), eps_ai.as<double>(),
                   eps_vo.as<double>());
+  eps_aiT.alloc(al, std::max<int64_t>(d.M, 1) * sizeof(double));
+  if (d.M > 0)
+    k::pack2d_t<double, double>(x, eps_aiT.as<double>(), eps_ai.as<double>(), 1, 0, d.v, d.o, d.o);
   res.alloc(al, 64 * sizeof(double));
   // NaN/Inf in eps
   k::nonfinite(x, d.n, eps.as<double>(), res.as<double>());
@@ -204,7 +234,8 @@ void mlcc_problem::setup(const mlcc_problem_desc &desc) {
   k::nonfinite(x, d.n2, h.as<double>(), res.as<double>());
   MLCC_REQUIRE(fetch(res.as<double>()) == 0.0, MLCC_E_NUMERIC, "non-finite Cholesky vectors");
 
-  amp.alloc(al, (size_t)(d.n1 + d.M * d.M) * sizeof(double));
+  const int64_t nd = model == MLCC_MLCCSD ? d.M * d.M : 0;
+  amp.alloc(al, (size_t)(d.n1 + nd) * sizeof(double));
   MLCC_HIP(hipMemsetAsync(amp.p, 0, amp.bytes, x.stream));
   om.alloc(al, amp.bytes);
   MLCC_HIP(hipStreamSynchronize(x.stream));
@@ -277,15 +308,16 @@ template <typename T> void mlcc_problem::dress_t(bool full_fock) {
   fock_full = full_fock;
 }
 
-// MLCC2 / MLCCSD doubles-dependent quantities at the current amplitudes:
-// L~_ai packed, g~_aibj (MLCC2), s = -g~/eps (unless given), u, and
-// Z^K_ai = sum_bj u_ai,bj L^K_bj.
+// Doubles-dependent quantities at given doubles (MLCC2 with an independent s2,
+// MLCCSD t2): L~_ai packed, g~_aibj (MLCC2, stored for Omega_2 = g~ + eps s),
+// u = 2x - x(i<->j) and Z^K_ai = sum_bj u_ai,bj L^K_bj.
 template <typename T> void mlcc_problem::doubles_mlcc2_t() {
   Exec &x = *ex;
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, M = d.M;
   const Prec p = gemm_prec<T>();
   u.ensure(al, (size_t)M * M * sizeof(T));
+  u_occ = false;
   if (model == MLCC_MLCC2) {
     // L~_ai pair-major, LaiT[ai][K]: the reduction index of g~ and of the
     // Jacobian's doubles block is contiguous (split BF16 products need it)
@@ -296,10 +328,7 @@ template <typename T> void mlcc_problem::doubles_mlcc2_t() {
     // g~_ai,bj = sum_K L~^K_ai L~^K_bj
     G(M, M, J).A(off<T>(LaiT), J, 1).B(off<T>(LaiT), 1, J).C(g.p, M, 1).tag("g_aibj")
         .run(x, p, true);
-    if (!x2_set)
-      k::mlcc2_s_u<double, T>(x, d.o, d.v, g.as<double>(), eps_ai.as<double>(), x2(), off<T>(u));
-    else
-      k::u_of<T>(x, d.o, d.v, x2(), off<T>(u));
+    k::u_of<T>(x, d.o, d.v, x2(), off<T>(u));
   } else {
     // MLCCSD: L~_ai K-major, Lai[K][ai] (its integral blocks read it so)
     Lai.ensure(al, (size_t)J * M * sizeof(T));
@@ -310,6 +339,70 @@ template <typename T> void mlcc_problem::doubles_mlcc2_t() {
   // (u_bj,ai = u_ai,bj) so that both operands run along the reduction index
   Z.ensure(al, (size_t)J * M * sizeof(T));
   G(J, M, M).A(off<T>(Lvo0), M, 1).B(off<T>(u), 1, M).C(Z.p, M, 1).tag("Z_uL").run(x, p, sizeof(T) == 8);
+}
+
+int mlcc_problem::occ_batch(int nz) const {
+  if (ctx->pair_occ > 0) return std::min(ctx->pair_occ, d.o);
+  return pair_block_occ(d.o, d.v, nz, (int)tsize);
+}
+
+// MLCC2 doubles with the analytic s2 (App. A, MLCC2 Omega vector: the
+// doubles equation is solved by s_aibj = -g~_aibj / eps_aibj in the
+// semicanonical basis), built per occupied-pair block and contracted at once
+// into Z^K_ai = sum_bj u_ai,bj L^K_bj (row J: sum_bj u_ai,bj F~_jb).  keep_u
+// also stores u (occupied-major rows and columns) for the Jacobian; want_s
+// writes s to the full a-major s2 array.
+template <typename T> void mlcc_problem::doubles_pairblocks_t(bool keep_u) {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, M = d.M, o = d.o, v = d.v;
+  const Prec p = gemm_prec<T>();
+  // L~_ai pair-major, LaiT[ai][K] (reduction index contiguous)
+  LaiT.ensure(al, (size_t)J * M * sizeof(T));
+  const int64_t nn[4] = {1, v, o, J}, ss[4] = {0, n, 1, n2};
+  k::permute4<T, T>(x, off<T>(LaiT), off<T>(Lt, O * n), nn, ss, 1.0, 0.0);
+  // F~_jb (occupied-major) in the spare row of LvoJ
+  k::pack2d<T, double>(x, off<T>(LvoJ, J * M), Ft.as<double>() + O, 1, 0, o, v, n);
+  Z.ensure(al, (size_t)(J + 1) * M * sizeof(T));
+  MLCC_HIP(hipMemsetAsync(Z.p, 0, (size_t)(J + 1) * M * sizeof(T), x.stream));
+  g.release();  // no g~ is kept
+  const int ob = occ_batch(1);
+  const int64_t Rm = (int64_t)std::min<int64_t>(ob, o) * v;
+  pbX.ensure(al, (size_t)Rm * Rm * sizeof(double));
+  if (keep_u) {
+    u.ensure(al, (size_t)M * M * sizeof(T));
+    u_occ = true;
+  } else {
+    pbU1.ensure(al, (size_t)Rm * Rm * sizeof(T));
+    pbU2.ensure(al, (size_t)Rm * Rm * sizeof(T));
+  }
+  if (want_s) ensure_doubles();
+  const T *lai = off<T>(LaiT);
+  const double *eT = eps_aiT.as<double>();
+  for (int i0 = 0; i0 < o; i0 += ob) {
+    const int ni = (int)std::min<int64_t>(ob, o - i0);
+    const int64_t RI = (int64_t)ni * v;
+    for (int j0 = i0; j0 < o; j0 += ob) {
+      const int nj = (int)std::min<int64_t>(ob, o - j0);
+      const int64_t RJ = (int64_t)nj * v;
+      const bool diag = j0 == i0;
+      // s[(i,a)][(j,b)] = -sum_K L~^K_ai L~^K_bj / (e_a - e_i + e_b - e_j)
+      G(RI, RJ, J).A(lai + i0 * J, o * J, 1).Mhi(v, J, v * RJ).B(lai + j0 * J, 1, o * J)
+          .Nhi(v, J, v).C(pbX.p, RJ, 1, 0, -1.0, 0.0).den(eT + i0 * v, eT + j0 * v)
+          .tag("g_aibj").run(x, p, true);
+      T *u1 = keep_u ? off<T>(u, i0 * v * M + j0 * v) : off<T>(pbU1);
+      T *u2 = diag ? nullptr : (keep_u ? off<T>(u, j0 * v * M + i0 * v) : off<T>(pbU2));
+      const int64_t l1 = keep_u ? M : RJ, l2 = keep_u ? M : RI;
+      k::u_pairblock<T>(x, (int)o, (int)v, ni, nj, pbX.as<double>(), RJ, 0, u1, l1, u2, l2, 0, 1,
+                        want_s ? x2() : nullptr, i0, j0);
+      // Z^K_ai (i in I) += sum_(j,b) L^K_bj u_IJ; rows K and the F~ row J
+      G(J + 1, RI, RJ).A(off<T>(LvoJ, j0 * v), M, 1).B(u1, 1, l1).Nhi(v, v * l1, 1)
+          .C(off<T>(Z, i0), M, o, 0, 1.0, 1.0).tag("Z_uL").run(x, p, sizeof(T) == 8);
+      if (!diag)
+        G(J + 1, RJ, RI).A(off<T>(LvoJ, i0 * v), M, 1).B(u2, 1, l2).Nhi(v, v * l2, 1)
+            .C(off<T>(Z, j0), M, o, 0, 1.0, 1.0).tag("Z_uL").run(x, p, sizeof(T) == 8);
+    }
+  }
 }
 
 // Omega_AI += [I act] sum_Kb L~^K_Ab Z^K_bi - [A act] sum_Kk Z^K_ak L~^K_kI
@@ -329,22 +422,35 @@ void mlcc_problem::omega_singles_t(const void *Zb, const void *ub, double *om1, 
   G(V, o, v, J).A(lt + O * n + O, n, 1, n2).B(zb, o, 1, M).C(om1, O, 1, 0, 1.0, 1.0)
       .run(x, p, true);
   G(v, O, o, J).A(zb, o, 1, M).B(lt, n, 1, n2).C(om1, O, 1, 0, -1.0, 1.0).run(x, p, true);
+  if (!ub) {
+    // the pair-blocked doubles carry sum_bj u_aibj F~_jb in row J of Z
+    k::acc3d<T>(x, 1, v, o, 1.0, zb + J * M, 0, o, 1, om1, 0, O);
+    return;
+  }
   fvec.ensure(al, M * sizeof(T));
   k::pack2d_t<T, double>(x, off<T>(fvec), Ft.as<double>() + O, 1, 0, o, v, n);
   G(o, 1, M, 1, v).A(ub, M, 1, 0, o * M).B(fvec.p, 1, 0).C(om1, 1, 0, O, 1.0, 1.0)
       .run(x, p, true);
 }
 
-template <typename T> void mlcc_problem::compute_state_t(bool full_fock) {
+template <typename T> void mlcc_problem::compute_state_t(bool full_fock, bool keep_u) {
   Exec &x = *ex;
   const int64_t J = d.J, n = d.n, M = d.M, n1 = d.n1;
   dress_t<T>(full_fock);
   double *om1 = om.as<double>();
-  if (has_doubles()) {
+  if (has_doubles() && model == MLCC_MLCC2 && !x2_set) {
+    doubles_pairblocks_t<T>(keep_u);
+    omega_singles_t<T>(Z.p, nullptr, om1, true);
+    if (want_om2) {
+      // the analytic s2 solves the doubles equation: Omega_2 = 0
+      ensure_doubles();
+      MLCC_HIP(hipMemsetAsync(om2(), 0, (size_t)M * M * sizeof(double), x.stream));
+    }
+  } else if (has_doubles()) {
     doubles_mlcc2_t<T>();
     omega_singles_t<T>(Z.p, u.p, om1, true);
     if (model == MLCC_MLCC2)
-      k::mlcc2_omega2<double>(x, M, g.as<double>(), eps_ai.as<double>(), x2(), om1 + n1);
+      k::mlcc2_omega2<double>(x, M, g.as<double>(), eps_ai.as<double>(), x2(), om2());
     else
       ccsd_omega2_t<T>();
   } else {
@@ -359,7 +465,7 @@ template <typename T> void mlcc_problem::compute_state_t(bool full_fock) {
   // residual norms
   k::dot(x, n1, om1, om1, r + 2);
   if (has_doubles() && (model == MLCC_MLCCSD || x2_set))
-    k::dot(x, M * M, om1 + n1, om1 + n1, r + 3);
+    k::dot(x, M * M, om2(), om2(), r + 3);
   else
     k::fill(x, r + 3, 1, 0.0);
   double hr[4];
@@ -371,9 +477,9 @@ template <typename T> void mlcc_problem::compute_state_t(bool full_fock) {
 
 #include "ccsd.inl"
 
-void mlcc_problem::compute_state(bool full_fock) {
-  if (prec == MLCC_FP64) compute_state_t<double>(full_fock);
-  else compute_state_t<float>(full_fock);
+void mlcc_problem::compute_state(bool full_fock, bool keep_u) {
+  if (prec == MLCC_FP64) compute_state_t<double>(full_fock, keep_u);
+  else compute_state_t<float>(full_fock, keep_u);
 }
 
 // ---------------------------------------------------------------------------
@@ -391,7 +497,7 @@ template <typename T> void mlcc_problem::prepare_jacobian_t() {
   Alloc *al = &ctx->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
   const Prec p = gemm_prec<T>();
-  compute_state_t<T>(true);
+  compute_state_t<T>(true, true);
   {
     // LooT[K][i][J] = L~^K_Ji: the occupied reduction index J contiguous for
     // the c L~_oo products of the transformation
@@ -475,13 +581,21 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   G(v, o * b, O, J).A(lt + O, 1, n, n2).B(P.p, 1, O, o * b * O).C(rv.p, o * b, 1)
       .tag("jac_r").run(x, p, o64);
   k::lincomb<T>(x, M * b, 2.0, off<T>(qv), -1.0, off<T>(rv), off<T>(qv));
-  G(o, b, M, 1, v).A(u.p, M, 1, 0, o * M).B(qv.p, b, 1).C(sigma, 1, ld, O, 1.0, 1.0)
-      .tag("jac_uw").run(x, p, true);
+  if (u_occ) {
+    // u[(i,a)][(k,c)] occupied-major: rows (i, a), reduction c in slices k
+    G(M, b, v, o).A(u.p, M, 1, v).Mhi(v, v * M, 1).B(qv.p, o * b, 1, b)
+        .C(sigma, O, ld, 0, 1.0, 1.0).tag("jac_uw").run(x, p, true);
+  } else {
+    G(o, b, M, 1, v).A(u.p, M, 1, 0, o * M).B(qv.p, b, 1).C(sigma, 1, ld, O, 1.0, 1.0)
+        .tag("jac_uw").run(x, p, true);
+  }
 
   // singles -> doubles: dL~_ai = sum_B L~_aB c_Bi - sum_J c_aJ L~_Ji  ([K][vec][ai]),
   // G[ai][vec, bj] = sum_K L~^K_ai dL~^K_bj
+  // (the effective MLCC2 transformation works per occupied-pair block instead)
+  const bool eff_blocks = model == MLCC_MLCC2 && !has_c2 && std::isfinite(w_eff);
   dLai.ensure(al, (size_t)J * b * M * sizeof(T));
-  Gm.ensure(al, (size_t)M * b * M * sizeof(double));
+  if (!eff_blocks) Gm.ensure(al, (size_t)M * b * M * sizeof(double));
   // one launch per term: rows (K, a) x columns (vec, i), then rows (vec, a) x
   // columns (K, i) (MLCC2: K the low part of the two-level index)
   if (model == MLCC_MLCC2) {
@@ -491,8 +605,9 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
         .C(dLai.p, 1, J).tag("dLai").run(x, p, o64);
     G(b * v, J * o, O).A(ct, O, 1).Mhi(v, n1, M * J).B(loot, 1, O * O).Nhi(J, O, J)
         .C(dLai.p, o * J, 1, 0, -1.0, 1.0).tag("dLai").run(x, p, o64);
-    G(M, b * M, J).A(off<T>(LaiT), J, 1).B(dLai.p, 1, J).C(Gm.p, b * M, 1)
-        .tag("sigma2_LdL").run(x, p, true);
+    if (!eff_blocks)
+      G(M, b * M, J).A(off<T>(LaiT), J, 1).B(dLai.p, 1, J).C(Gm.p, b * M, 1)
+          .tag("sigma2_LdL").run(x, p, true);
   } else {
     // K-major dL~: dLai[K][vec][ai] (read so by the MLCCSD doubles terms)
     G(J * v, b * o, V).A(lt + O * n + O, n, 1).Mhi(v, n2, b * M).B(ct, O, 1).Nhi(o, n1, M)
@@ -503,6 +618,90 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
         .tag("sigma2_LdL").run(x, p, true);
   }
 
+  Zc.ensure(al, (size_t)(J + 1) * b * M * sizeof(T));
+  if (eff_blocks) {
+    eff_doubles_pairblocks_t<T>(nb, w_eff);
+  } else {
+    full_doubles_to_singles_t<T>(nb, c, ld, has_c2, sigma, w_eff);
+    if (!has_c2 && !std::isfinite(w_eff)) return;
+  }
+  // sigma_AI += sum_Kb L~^K_Ab Zc^K_bi  (A1-type)  - sum_Kk L~^K_kI Zc^K_ak  (B1-type)
+  G(V, b * o, v, J).A(lt + O * n + O, n, 1, n2).B(Zc.p, 1, v, b * M).Nhi(o, M, ld)
+      .C(sigma, O, 1, 0, 1.0, 1.0).tag("d2s_A1").run(x, p, true);
+  G(O, v, o, J, b).A(lt, 1, n, n2, 0).B(Zc.p, v, 1, b * M, M).C(sigma, 1, O, ld, -1.0, 1.0)
+      .tag("d2s_B1").run(x, p, true);
+  // sigma_ai += sum_bj u_aibj F~_jb  (row J of Zc)
+  k::acc3d<T>(x, b, v, o, 1.0, off<T>(Zc, J * b * M), M, 1, v, sigma, ld, O);
+}
+
+// Effective transformation (MLCC2): c2 = P[L~ dL~] / (w - eps) per
+// occupied-pair block (I, J), I <= J, for the nb vectors at once (dL~ is
+// pair-major, dLai[vec][ai][K]):
+//   off-diagonal  X = L~_I^T dL~_J, then X = (dL~_I^T L~_J + X) / (w - eps)
+//                 (FP64 denominator in the GEMM epilogue)
+//   diagonal      X = L~_I^T dL~_I, Y = (X + X^T) / (w - eps)
+// then u(c2) of the block and its mirror, Zc_I += L_J u_IJ^T and
+// Zc_J += L_I u_JI^T.  Zc[K][vec][i][a] (K = J: the F~_jb row).
+template <typename T> void mlcc_problem::eff_doubles_pairblocks_t(int nb, double w) {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, M = d.M, o = d.o, v = d.v, b = nb;
+  const Prec p = gemm_prec<T>();
+  const int ob = occ_batch(nb);
+  const int64_t Rm = (int64_t)std::min<int64_t>(ob, o) * v;
+  pbX.ensure(al, (size_t)b * Rm * Rm * sizeof(double));
+  pbY.ensure(al, (size_t)b * Rm * Rm * sizeof(double));
+  pbU1.ensure(al, (size_t)b * Rm * Rm * sizeof(T));
+  pbU2.ensure(al, (size_t)b * Rm * Rm * sizeof(T));
+  MLCC_HIP(hipMemsetAsync(Zc.p, 0, (size_t)(J + 1) * b * M * sizeof(T), x.stream));
+  // F~_jb (occupied-major) in the spare row of LvoJ: row J of Zc is sum_bj u_aibj F~_jb
+  k::pack2d<T, double>(x, off<T>(LvoJ, J * M), Ft.as<double>() + d.O, 1, 0, o, v, d.n);
+  const T *lai = off<T>(LaiT), *dl = off<T>(dLai);
+  const double *eT = eps_aiT.as<double>();
+  for (int i0 = 0; i0 < o; i0 += ob) {
+    const int ni = (int)std::min<int64_t>(ob, o - i0);
+    const int64_t RI = (int64_t)ni * v;
+    for (int j0 = i0; j0 < o; j0 += ob) {
+      const int nj = (int)std::min<int64_t>(ob, o - j0);
+      const int64_t RJ = (int64_t)nj * v, blk = RI * RJ;
+      const bool diag = j0 == i0;
+      const double *xv;
+      G(RI, RJ, J, 1, b).A(lai + i0 * J, o * J, 1, 0, 0).Mhi(v, J, v * RJ)
+          .B(dl + j0 * J, 1, o * J, 0, M * J).Nhi(v, J, v).C(pbX.p, RJ, 1, blk)
+          .tag("sigma2_LdL").run(x, p, true);
+      if (diag) {
+        k::sym_div<double, double>(x, RI, pbX.as<double>(), RI, eT + i0 * v, w,
+                                   pbY.as<double>(), (int)b, blk, blk);
+        xv = pbY.as<double>();
+      } else {
+        G(RI, RJ, J, 1, b).A(dl + i0 * J, o * J, 1, 0, M * J).Mhi(v, J, v * RJ)
+            .B(lai + j0 * J, 1, o * J, 0, 0).Nhi(v, J, v).C(pbX.p, RJ, 1, blk, -1.0, -1.0)
+            .den(eT + i0 * v, eT + j0 * v, -w).tag("sigma2_LdL").run(x, p, true);
+        xv = pbX.as<double>();
+      }
+      k::u_pairblock<T>(x, (int)o, (int)v, ni, nj, xv, RJ, blk, off<T>(pbU1), RJ,
+                        diag ? nullptr : off<T>(pbU2), RI, blk, (int)b, nullptr, i0, j0);
+      G(J + 1, RI, RJ, 1, b).A(off<T>(LvoJ, j0 * v), M, 1, 0, 0).B(pbU1.p, 1, RJ, 0, blk)
+          .C(off<T>(Zc, i0 * v), b * M, 1, M, 1.0, 1.0).tag("Zc_uL").run(x, p, sizeof(T) == 8);
+      if (!diag)
+        G(J + 1, RJ, RI, 1, b).A(off<T>(LvoJ, i0 * v), M, 1, 0, 0).B(pbU2.p, 1, RI, 0, blk)
+            .C(off<T>(Zc, j0 * v), b * M, 1, M, 1.0, 1.0).tag("Zc_uL")
+            .run(x, p, sizeof(T) == 8);
+    }
+  }
+}
+
+// Doubles -> singles of the full-space transformation (trial doubles) and of
+// the effective one on the stored-doubles path: c2 into u(c2) and Zc.
+template <typename T>
+void mlcc_problem::full_doubles_to_singles_t(int nb, const double *c, int64_t ld, bool has_c2,
+                                            double *sigma, double w_eff) {
+  Exec &x = *ex;
+  Alloc *al = &ctx->al;
+  const int64_t J = d.J, n = d.n, O = d.O, M = d.M, n1 = d.n1, b = nb;
+  const Prec p = gemm_prec<T>();
+  const bool o64 = sizeof(T) == 8;
+  const double *F = Ft.as<double>();
   // the doubles used by doubles -> singles: the trial doubles, or the
   // eliminated ones of the effective transformation
   const double *c2base = nullptr;
@@ -531,34 +730,32 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
   // Zc^K[vec][j][c] = sum_bk L_bk^K u_cj,bk has c contiguous, the reduction
   // index of the A1 term.
   ut.ensure(al, (size_t)b * M * M * sizeof(T));
-  Zc.ensure(al, (size_t)(J + 1) * b * M * sizeof(T));
   k::u_of<T>(x, d.o, d.v, c2base, off<T>(ut), (int)b, c2ld, M * M, true);
   // F~_jb in the spare row J of L_vo: row J of Zc is sum_bj u_aibj F~_jb
-  k::pack2d_t<T, double>(x, off<T>(Lvo0, J * M), F + O, 1, 0, o, v, n);
+  k::pack2d_t<T, double>(x, off<T>(Lvo0, J * M), F + O, 1, 0, d.o, d.v, n);
   G(J + 1, b * M, M).A(off<T>(Lvo0), M, 1).B(ut.p, 1, M).Nhi(M, M * M, M).C(Zc.p, b * M, 1)
       .tag("Zc_uL").run(x, p, o64);
-  G(V, b * o, v, J).A(lt + O * n + O, n, 1, n2).B(Zc.p, 1, v, b * M).Nhi(o, M, ld)
-      .C(sigma, O, 1, 0, 1.0, 1.0).tag("d2s_A1").run(x, p, true);
-  G(O, v, o, J, b).A(lt, 1, n, n2, 0).B(Zc.p, v, 1, b * M, M).C(sigma, 1, O, ld, -1.0, 1.0)
-      .tag("d2s_B1").run(x, p, true);
-  // sigma_ai += sum_bj u_aibj F~_jb  (row J of Zc)
-  k::acc3d<T>(x, b, v, o, 1.0, off<T>(Zc, J * b * M), M, 1, v, sigma, ld, O);
 }
 
 static constexpr int kMaxBatch = 8;
 
-// Trial vectors per batch: up to 8, fewer when the doubles scratch of a batch
-// (G in FP64, eliminated doubles in FP64, u(c2) in the operand type; M*M
-// each per vector) would pass 48 GB.
-int mlcc_problem::max_batch() const {
-  if (!has_doubles()) return kMaxBatch;
-  const double per = (double)d.M * (double)d.M * (16.0 + (double)tsize);
-  return (int)std::max(1.0, std::min((double)kMaxBatch, std::floor(48e9 / per)));
+// Trial vectors per batch: up to 8, fewer when the per-vector scratch of a
+// batch would pass 48 GB: W (J V O), dL~ and Zc (about 2 J M) and P (J o O)
+// in the operand type, and on the stored-doubles path G in FP64, the
+// eliminated doubles in FP64 and u(c2) in the operand type (M*M each).
+int mlcc_problem::max_batch(bool eff) const {
+  const double ts = (double)tsize;
+  const double per = ts * ((double)d.J * d.V * d.O + 2.0 * (double)d.J * d.M +
+                           (double)d.J * d.o * d.O);
+  double cap = std::floor(48e9 / per);
+  if (has_doubles() && !(eff && model == MLCC_MLCC2))
+    cap = std::min(cap, std::floor(48e9 / ((double)d.M * (double)d.M * (16.0 + ts))));
+  return (int)std::max(1.0, std::min((double)kMaxBatch, cap));
 }
 
 void mlcc_problem::transform(int nvec, const double *c, double *sigma) {
   const int64_t dm = dim();
-  const int mb = max_batch();
+  const int mb = max_batch(false);
   for (int i0 = 0; i0 < nvec; i0 += mb) {
     const int nb = std::min(mb, nvec - i0);
     if (prec == MLCC_FP64)
@@ -569,7 +766,7 @@ void mlcc_problem::transform(int nvec, const double *c, double *sigma) {
 }
 
 void mlcc_problem::transform_eff(double w, int nvec, const double *c1, double *s1) {
-  const int mb = max_batch();
+  const int mb = max_batch(true);
   for (int i0 = 0; i0 < nvec; i0 += mb) {
     const int nb = std::min(mb, nvec - i0);
     if (prec == MLCC_FP64)

@@ -12,6 +12,7 @@ struct mlcc_context {
   bool own_stream = false;
   mlcc::Alloc al;
   mlcc::Exec ex;
+  int pair_occ = 0;  // forced occupied indices per pair block (0: memory rule)
   std::string last_error;
   std::mutex err_mu;
 };
@@ -58,10 +59,20 @@ struct G {
     a.tag = t;
     return *this;
   }
+  // epilogue denominator: C = (alpha acc + beta Cin) / (row[m] + col[n] + shift)
+  G &den(const double *row, const double *col, double shift = 0.0) {
+    a.den_row = row; a.den_col = col; a.den_shift = shift;
+    return *this;
+  }
   void run(Exec &ex, Prec p, bool out64) const { gemm(ex, p, a, out64); }
 };
 
 template <typename T> inline Prec prec_of() { return sizeof(T) == 8 ? Prec::F64 : Prec::F32; }
+
+// Bytes of the pair-block buffers of the MLCC2 doubles, and the occupied
+// indices per block that keep nz blocks within them (operand size tsize).
+constexpr double kPairBlockBytes = 4e9;
+int pair_block_occ(int o, int v, int nz, int tsize);
 template <typename T> inline T *off(const DBuf &b, int64_t elems = 0) {
   return static_cast<T *>(b.p) + elems;
 }
@@ -88,9 +99,12 @@ struct mlcc_problem {
 
   // inputs and derived constants
   mlcc::DBuf L, eps, h, eps_ai, eps_vo, Lvo0;
+  mlcc::DBuf eps_aiT;  // f64 [o][v]: e_a - e_i in occupied-major pair order (i v + a)
+  mlcc::DBuf LvoJ;     // op [J+1][o][v]: L^K_bj occupied-major (row J: F~_jb)
   mlcc::DBuf fock;     // f64 [n][n] when the desc gave a Fock matrix (else diag(eps))
   // state at the current amplitudes
-  mlcc::DBuf amp;      // f64 [n1 + M*M]: t1 then doubles
+  mlcc::DBuf amp;      // f64 [n1 (+ M*M for MLCCSD)]: t1 then the MLCCSD doubles
+  mlcc::DBuf s2, o2;   // MLCC2, on demand: f64 [M][M] doubles and doubles residual
   mlcc::DBuf t1T;      // op [n1]
   mlcc::DBuf Lt, ht, Ft, dK, dKT;
   mlcc::DBuf Lai, LaiT, g, u, Z;
@@ -102,18 +116,24 @@ struct mlcc_problem {
   mlcc::DBuf cc_work;
   // transform scratch
   mlcc::DBuf cT, cTt, Xk, W, P, qv, rv, wv, ut, Zc, dLai, Gm, c2e;
+  // occupied-pair blocks of the MLCC2 doubles (ground state with analytic s2,
+  // effective transformation): f64 values and u in the operand type
+  mlcc::DBuf pbX, pbY, pbU1, pbU2;
 
   bool have_amp = false;
   bool x2_set = false;     // MLCC2: an independent s2 was given
   bool state_valid = false;  // dressed quantities match amp
   bool jac_ready = false;
   bool fock_full = false;
+  bool u_occ = false;      // u is stored in occupied-major pair order, rows and columns
+  bool want_s = false;     // the next state evaluation also writes the analytic s2
+  bool want_om2 = false;   // ... and the MLCC2 doubles residual
   double e_corr = 0.0;
   double omega_norm = 0.0;
 
   bool has_doubles() const { return model != MLCC_CCS && d.M > 0; }
   int64_t dim() const { return d.n1 + (has_doubles() ? d.M * d.M : 0); }
-  int max_batch() const;  // trial vectors per Jacobian batch
+  int max_batch(bool eff) const;  // trial vectors per Jacobian batch
   // contraction precision for operand type T (FP32 storage may run split
   // BF16 products)
   template <typename T> mlcc::Prec gemm_prec() const {
@@ -121,11 +141,28 @@ struct mlcc_problem {
                           : (prec == MLCC_BF16X3 ? mlcc::Prec::BF16X3 : mlcc::Prec::F32);
   }
   double *t1() const { return amp.as<double>(); }
-  double *x2() const { return amp.as<double>() + d.n1; }
+  // doubles amplitudes and residual: MLCCSD t2 after t1; MLCC2 s2 in its own
+  // array, allocated on demand (ensure_doubles)
+  double *x2() const {
+    return model == MLCC_MLCCSD ? amp.as<double>() + d.n1 : s2.as<double>();
+  }
+  double *om2() const {
+    return model == MLCC_MLCCSD ? om.as<double>() + d.n1 : o2.as<double>();
+  }
+  void ensure_doubles() {
+    if (model == MLCC_MLCC2 && d.M > 0) {
+      s2.ensure(&ctx->al, (size_t)d.M * d.M * sizeof(double));
+      o2.ensure(&ctx->al, (size_t)d.M * d.M * sizeof(double));
+    }
+  }
+  // occupied indices per block of the pair-blocked doubles, for nz vectors
+  int occ_batch(int nz) const;
 
   // model steps (problem.cpp)
   void setup(const mlcc_problem_desc &desc);
-  void compute_state(bool full_fock);  // dress + doubles + Z + Omega + energy
+  // dress + doubles + Z + Omega + energy; keep_u: store the ground-state u
+  // (the Jacobian's singles terms read it)
+  void compute_state(bool full_fock, bool keep_u = false);
   void prepare_jacobian();
   void transform(int nvec, const double *c, double *sigma);       // device pointers
   void transform_eff(double w, int nvec, const double *c1, double *s1);
@@ -141,12 +178,17 @@ struct mlcc_problem {
                                      const uint64_t *synth_seed);
   template <typename T> void dress_t(bool full_fock);
   template <typename T> void doubles_mlcc2_t();
+  template <typename T> void doubles_pairblocks_t(bool keep_u);
+  template <typename T> void eff_doubles_pairblocks_t(int nb, double w);
   template <typename T> void omega_singles_t(const void *Zb, const void *ub, double *om1,
                                              bool add_fock);
-  template <typename T> void compute_state_t(bool full_fock);
+  template <typename T> void compute_state_t(bool full_fock, bool keep_u);
   template <typename T> void prepare_jacobian_t();
   template <typename T> void transform_batch_t(int nb, const double *c, int64_t ld,
                                                bool has_c2, double *sigma, double w_eff);
+  template <typename T> void full_doubles_to_singles_t(int nb, const double *c, int64_t ld,
+                                                       bool has_c2, double *sigma,
+                                                       double w_eff);
   template <typename T> void cnto_t(int ns, const double *R, const double *w, int o_act, int v_act,
                                     double *m_eig, double *n_eig, double *C, double *eps_out,
                                     double *fock_out, double *L_out, bool L_out_dev);

@@ -72,38 +72,50 @@ struct mlcc_server {
 
 // Device bytes one request needs at its peak, with a 15% margin: the larger
 // of the set-up peak (L, plus its FP64 staging copy in FP32 mode) and the
-// solve peak (L, L~, doubles arrays, batch scratch, Davidson subspace).
+// solve peak (L, L~, packed blocks, the ground-state u that the Jacobian
+// reads, the pair blocks of the MLCC2 doubles, the per-vector scratch of a
+// Jacobian batch, the Davidson subspace and the DIIS history), plus the
+// lane's split-K partial sums (at most ~67 MB: resident blocks x compute
+// units x the largest FP64 tile) and reduction buffers.
 extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n_roots,
                                            const mlcc_solver_opts *es) {
   if (!d || n_roots < 1) return 0;
   const double O = d->n_occ, V = d->n_vir, J = d->n_chol, n = O + V;
-  const bool dbl = d->model != MLCC_CCS;
-  const double M = dbl ? (double)d->n_occ_act * d->n_vir_act : 0.0;
+  const bool dbl = d->model != MLCC_CCS && d->n_occ_act > 0 && d->n_vir_act > 0;
+  const double o = dbl ? d->n_occ_act : 0.0, v = dbl ? d->n_vir_act : 0.0;
+  const double M = o * v, MM = M * M;
   const double ts = d->precision == MLCC_FP64 ? 8.0 : 4.0;
-  const double nL = J * n * n, n1 = O * V, MM = M * M;
-  const bool eff = es && es->effective && d->model == MLCC_MLCC2;
+  const double nL = J * n * n, n1 = O * V;
+  const bool mlcc2 = d->model == MLCC_MLCC2, ccsd = d->model == MLCC_MLCCSD;
+  const bool eff = es && es->effective && mlcc2;
   const double dim = n1 + ((dbl && !eff) ? MM : 0.0);
-  // the batch rule of the Jacobian transformation (at most 8 vectors, at most
-  // 48 GB of doubles scratch)
-  double bmax = 8.0;
-  if (dbl && MM > 0) bmax = std::max(1.0, std::min(8.0, std::floor(48e9 / (MM * (16.0 + ts)))));
+  // trial vectors per Jacobian batch (the rule of the transformation)
+  const double per_v = ts * (J * V * O + 2.0 * J * M + J * o * O);
+  double bmax = std::floor(48e9 / per_v);
+  if (dbl && !eff) bmax = std::min(bmax, std::floor(48e9 / (MM * (16.0 + ts))));
+  bmax = std::max(1.0, std::min(8.0, bmax));
   const double b = std::min((double)n_roots + 2.0, bmax);
   const double setup = nL * ts + (ts == 4.0 ? nL * 8.0 : 0.0) + 6.0 * n * n * 8.0;
   double run = 2.0 * nL * ts;                 // L and L~
-  run += 6.0 * n * n * 8.0;                   // h, h~, F~ and scratch
-  run += MM * (8.0 * 4 + ts * 2);             // amplitudes, residual, g~, G, u
-  run += MM * b * (ts + 8.0);                 // batched u(c2), G
-  if (eff) run += MM * b * 8.0;               // eliminated doubles
-  run += J * M * ts * (3.0 + 2.0 * b);        // packed L_ai, Z, Zc, dL_ai
-  run += J * V * O * b * ts;                  // CCS intermediate
+  run += 8.0 * n * n * 8.0;                   // h, h~, F~, Fock and scratch
+  run += 5.0 * (J + 1.0) * M * ts;            // packed L_ai (two orders), L~_ai, Z, dot scratch
+  run += J * O * O * ts;                      // L~_oo transposed
+  run += b * (per_v + 3.0 * n1 * ts);         // transform batch: W, dL~, Zc, P, trial singles
+  if (mlcc2 && dbl) {
+    run += MM * ts;                           // ground-state u kept for the Jacobian
+    const int nz = eff ? (int)b : 1;
+    const double R = std::min((double)mlcc::pair_block_occ((int)o, (int)v, nz, (int)ts), o) * v;
+    run += nz * R * R * (16.0 + 2.0 * ts);    // pair blocks of the doubles
+    if (!eff) run += MM * b * (8.0 + ts);     // G and u(c2) of full-space batches
+  }
+  if (ccsd && dbl) {
+    run += MM * (8.0 * 2 + ts * 4) + MM * b * (ts + 8.0);  // t2, Omega_2, u, copies; G, u(c2)
+    run += (v * v * v * v + O * v * v * v + O * o * M) * ts + 16.0 * MM * ts;  // integral blocks
+  }
   const double space = es && es->max_subspace > 0 ? es->max_subspace : 20.0 * n_roots;
   run += dim * 8.0 * (2.0 * space + 3.0 * (n_roots + 2));  // Davidson
-  run += 2.0 * 8.0 * (n1 + (d->model == MLCC_MLCCSD ? MM : 0.0)) * 8;  // DIIS
-  if (d->model == MLCC_MLCCSD) {
-    const double v = d->n_vir_act, o = d->n_occ_act;
-    run += (v * v * v * v + O * v * v * v + O * o * M) * ts + 16.0 * MM * ts;
-  }
-  return (uint64_t)(std::max(setup, run) * 1.15) + (64ull << 20);
+  run += 2.0 * 8.0 * (n1 + (ccsd ? MM : 0.0)) * 8;         // DIIS
+  return (uint64_t)(std::max(setup, run) * 1.15) + (160ull << 20);
 }
 
 void mlcc_server::work(Lane *lane) {
@@ -153,6 +165,10 @@ void mlcc_server::work(Lane *lane) {
     } catch (...) {
       st = MLCC_E_DEVICE;
     }
+    // the lane's split and reduction scratch go back with the request's footprint
+    (void)hipStreamSynchronize(lane->ex.stream);
+    lane->ex.work.release();
+    lane->ex.red.release();
     {
       std::lock_guard<std::mutex> lk(mu);
       in_use -= r->footprint;

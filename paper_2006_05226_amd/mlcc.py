@@ -70,7 +70,8 @@ EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "ml
            "mlcc_jacobian_transform", "mlcc_jacobian_transform_eff", "mlcc_davidson_solve",
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
            "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_gemm_noalloc",
-           "mlcc_debug_get", "mlcc_profile_enable", "mlcc_profile_get", "mlcc_gemm_tile", "mlcc_cnto"]
+           "mlcc_debug_get", "mlcc_profile_enable", "mlcc_profile_get", "mlcc_gemm_tile", "mlcc_cnto",
+           "mlcc_pair_block_occ"]
 
 NOALLOC_SCRATCH_BYTES = 16 << 20
 
@@ -116,6 +117,7 @@ def load(path: str = LIB_PATH):
         "mlcc_profile_enable": (i32, [vp, i32]),
         "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
         "mlcc_gemm_tile": (i32, [vp, i32, i32, P(i32)]),
+        "mlcc_pair_block_occ": (i32, [vp, i32]),
         "mlcc_cnto": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -207,6 +209,11 @@ class Context:
         last = (C.c_int32 * 2)()
         self.check(self.lib.mlcc_gemm_tile(self.h, bm, bn, last))
         return (last[0], last[1])
+
+    def pair_block_occ(self, occ=0):
+        """Occupied indices per pair block of the MLCC2 doubles on this
+        context's problems (0: the memory rule)."""
+        self.check(self.lib.mlcc_pair_block_occ(self.h, occ))
 
     def profile(self, on=True):
         self.check(self.lib.mlcc_profile_enable(self.h, 1 if on else 0))
