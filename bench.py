@@ -1,21 +1,29 @@
 #!/usr/bin/env python3
 """MLCC2 Jacobian-transform throughput on one MI355X.
 
-Workload: MLCC2 excitation energies on synthetic Cholesky vectors, n_occ=40,
-n_vir=400, n_chol=1200, CC2 active 15 occ / 150 vir, CCS elsewhere (FP64 plain
-path; the FP32 mixed path is measured beside it).
+Workload (the headline): MLCC2 excitation energies on synthetic Cholesky
+vectors, n_occ=150, n_vir=1200, n_chol=3600, CC2 active 50 occ / 500 vir, CCS
+elsewhere, 5 roots by the effective-singles Davidson (the doubles-doubles
+block of MLCC2 is diagonal, so the doubles are eliminated at each frequency;
+g~ and the eliminated doubles are built per occupied-pair block and never
+stored).  Cholesky vectors drawn on the device (seed 0).
 
-One step = one batch of n_vec=4 trial vectors (one per requested root, as in a
-Davidson iteration) transformed by the full-space MLCC2 Jacobian at converged
-ground-state amplitudes: X1-basis CCS terms, MLCC2 singles terms,
-doubles->singles and singles->doubles (g~ derivative) contractions and the
-eps_aibj doubles diagonal.  Inputs and trial vectors are resident in HBM before
-the timed region.  value = transforms per second in FP64.
+One step = one batch of n_vec=5 trial vectors (one per root) transformed by
+the effective MLCC2 Jacobian A11 + A12 (w - eps)^-1 A21 at converged
+ground-state amplitudes: X1-basis CCS terms, MLCC2 singles terms, the
+singles -> doubles -> singles path with the FP64 denominator.  Inputs and
+trial vectors are resident in HBM before the timed region.  value =
+effective transforms per second with FP64 contractions; the FP32 and split-BF16
+(mixed) contractions are measured beside it (extra.fp32, extra.bf16x3), with
+their speedups and the energy / root differences from FP64.
 
-Also reported: FP32 transforms/s and its speedup, a full Davidson solve (4
-roots to 1e-6) and a ground-state solve, the dominant contraction's achieved
-TFLOP/s from HIP events on the library stream, and the FP64 oracle timed on the
-host cores for one transform at the same shape.
+Also reported: the ground state and the 5-root Davidson in each precision,
+per-contraction times and TFLOP/s, the roofline of the dominant contraction
+(HIP events on the library stream; HBM traffic from the committed rocprofv3
+summary), the full-space MLCC2 transform at 40/400/1200 (extra.c2), MLCCSD at
+60/600/2000 (extra.mlccsd), the CNTO orbital selection (extra.cnto), the
+256-request serving stream (extra.serving), and the FP64 oracle on the host
+cores (cpu_baseline).
 
 Serving (extra.serving): a stream of MLCC2 excitation requests of uneven size
 (n_occ uniform in [20, 80], n_vir = 10 n_occ, n_chol = 3 n_vir, active
@@ -39,49 +47,100 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 157.3}
-# split BF16 runs each FP32-accurate product as three dense BF16 MFMAs (2.5 PFLOP/s)
+# dense MFMA peaks of MI355X; a split-BF16 product is three dense BF16 MFMAs
+# (2.5 PFLOP/s), so its FP32-equivalent peak is 2500 / 3
 BF16_DENSE_TFLOPS = 2500.0
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": BF16_DENSE_TFLOPS / 3.0}
+PEAK_NOTE = {"fp64": "FP64 MFMA", "fp32": "FP32 MFMA",
+             "bf16x3": "BF16 MFMA / 3 (each FP32-accurate product is hi*hi + hi*lo + lo*hi)"}
+C4 = "mlcc2_150_1200_3600"
+# the CPU-baseline sample: the same model family at a size the oracle runs in seconds
+SAMPLE = dict(n_occ=30, n_vir=240, n_chol=720, n_occ_act=10, n_vir_act=100)
 HBM_PEAK_GBS = 8000.0
 
 
-def _cpu_baseline(timeout_s: float = 300.0):
-    """Time one oracle Jacobian transform at the workload's shape on the host
-    (a child process, so its BLAS threading is its own)."""
-    code = r"""
+def eff_transform_flops(n_occ, n_vir, n_chol, n_occ_act, n_vir_act):
+    """Algorithmic flops of one effective MLCC2 Jacobian transformation (one
+    vector): ccs_vv 2V^2OJ, ccs_W 2VO^2J, dL~ 2vo(V+O)J, the doubles block
+    2M^2J twice (c2 and its contraction with L), the doubles-to-singles
+    terms 2Vo vJ + 2vO oJ and jac_P 2oOVJ."""
+    O, V, J, o, v = n_occ, n_vir, n_chol, n_occ_act, n_vir_act
+    M = o * v
+    return 2.0 * J * (V * V * O + V * O * O + v * o * (V + O) + 2.0 * M * M + V * o * v
+                      + v * O * o + o * O * V)
+
+
+_ORACLE_SAMPLE = r"""
 import os, sys, time, json
 sys.path.insert(0, %r)
 import numpy as np
 from oracle import mlcc as om
-from paper_2006_05226_amd.synth import CONFIGS, gen_inputs, gen_amplitudes, gen_vectors
-c = CONFIGS['mlcc2_40_400_1200']
+from paper_2006_05226_amd.synth import gen_inputs, gen_amplitudes
+c = %r
 inp = gen_inputs(seed=0, **c)
 d = om.Dims(c['n_occ'], c['n_vir'], c['n_occ_act'], c['n_vir_act'])
 P = om.Problem(inp.L, inp.eps, d, 'mlcc2')
-t1, x2 = gen_amplitudes(d.O, d.V, d.o, d.v, seed=1, scale1=0.01, scale2=0.001)
-c1, c2 = gen_vectors(1, d.O, d.V, d.M, seed=2)
+t1, _ = gen_amplitudes(d.O, d.V, d.o, d.v, seed=1, scale1=0.01)
+s = P.s_analytic(t1)
+c1 = np.random.default_rng(2).standard_normal((d.V, d.O))
+w = 0.4
 t = time.perf_counter()
-om.jacobian_transform(P, t1, x2, c1[0], c2[0].reshape(d.v, d.o, d.v, d.o))
+_, a21 = om.jacobian_transform(P, t1, s, c1, np.zeros((d.v, d.o, d.v, d.o)))
+r1, _ = om.jacobian_transform(P, t1, s, c1, a21 / (w - om.orbital_denominators(inp.eps, d)))
 dt = time.perf_counter() - t
-try:
-    cores = len(os.sched_getaffinity(0))
-except Exception:
-    cores = os.cpu_count()
-threads = int(os.environ.get('OPENBLAS_NUM_THREADS') or os.environ.get('OMP_NUM_THREADS') or cores)
-print(json.dumps(dict(seconds=dt, cores=min(cores, threads))))
-""" % ROOT
+print(json.dumps(dict(seconds=dt)))
+"""
+
+
+def _cpu_model():
+    try:
+        for line in subprocess.run(["lscpu"], capture_output=True, text=True).stdout.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:  # noqa: BLE001
+        pass
+    return None
+
+
+def _cpu_baseline(timeout_s: float = 240.0):
+    """The FP64 oracle's effective transformation (complex-step Jacobian: A21
+    c1, the eliminated doubles, then A11 c1 + A12 c2) on one vector of a
+    bounded sample of the workload's model family, timed in child processes
+    on all host cores and pinned to one core with one BLAS thread, and scaled
+    to the headline workload by the algorithmic flop ratio."""
+    code = _ORACLE_SAMPLE % (ROOT, SAMPLE)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:  # noqa: BLE001
+        cores = os.cpu_count()
+    ratio = eff_transform_flops(**_c4_config()) / eff_transform_flops(**SAMPLE)
+    out = {"unit": "transforms/s", "kind": "oracle", "cpu_model": _cpu_model(),
+           "sample": (f"one effective MLCC2 transformation (complex-step FP64 oracle) at "
+                      f"n_occ={SAMPLE['n_occ']} n_vir={SAMPLE['n_vir']} n_chol={SAMPLE['n_chol']}, "
+                      f"active {SAMPLE['n_occ_act']}/{SAMPLE['n_vir_act']} (the workload's "
+                      f"ratios), scaled to 150/1200/3600 by the flop ratio {ratio:.0f}"),
+           "flop_ratio": ratio}
     try:
         r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                            timeout=timeout_s)
-        out = json.loads(r.stdout.strip().splitlines()[-1])
-        return {"value": 1.0 / out["seconds"], "unit": "transforms/s", "cores": out["cores"],
-                "kind": "oracle",
-                "sample": "one complex-step FP64 Jacobian transform (1 vector) at n_occ=40, "
-                          "n_vir=400, n_chol=1200, active 15/150, seeded synthetic amplitudes",
-                "seconds": out["seconds"]}
+        sec = json.loads(r.stdout.strip().splitlines()[-1])["seconds"]
+        out.update(value=1.0 / (sec * ratio), cores=cores, sample_seconds=sec)
     except Exception as e:  # noqa: BLE001
-        return {"value": None, "unit": "transforms/s", "cores": None, "kind": "oracle",
-                "sample": f"failed: {e}"}
+        out.update(value=None, cores=None, error=f"all-core run failed: {e}")
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    try:
+        r = subprocess.run(["taskset", "-c", "0", sys.executable, "-c", code], capture_output=True,
+                           text=True, timeout=timeout_s, env=env)
+        sec1 = json.loads(r.stdout.strip().splitlines()[-1])["seconds"]
+        out.update(single_core_value=1.0 / (sec1 * ratio), single_core_sample_seconds=sec1)
+    except Exception as e:  # noqa: BLE001
+        out.update(single_core_value=None, single_core_error=str(e))
+    return out
+
+
+def _c4_config():
+    from paper_2006_05226_amd.synth import CONFIGS
+    return CONFIGS[C4]
 
 
 def _profiled_traffic(tag: str, config: str, precision: str):
@@ -97,7 +156,9 @@ def _profiled_traffic(tag: str, config: str, precision: str):
             k, v = line.split(":", 1)
             fields[k] = v.strip()
     h = hashlib.sha256()
-    for f in ("gemm_kernel.h", "gemm_f64.hip", "gemm_f64g.hip"):
+    srcs = ("gemm_kernel.h", "gemm_f64.hip", "gemm_f64g.hip") if precision == "fp64" else \
+        ("gemm_kernel.h", "gemm_f32.hip", "gemm_f32d.hip", "gemm_f32g.hip", "gemm_f32dg.hip")
+    for f in srcs:
         with open(os.path.join(ROOT, "paper_2006_05226_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if fields.get("kernel_source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
@@ -240,63 +301,134 @@ def _cnto_leg(mlcc, precisions=("fp64", "bf16x3"), config="mlcc2_40_400_1200", n
     return out
 
 
-def _c4_leg(mlcc, steps=3, nvec=5, precisions=("fp32", "bf16x3")):
-    """MLCC2 at 150/1200/3600 (active 50/500), FP32 or split-BF16 contractions,
-    FP64 updates, effective-singles Davidson for 5 roots; device-drawn
-    Cholesky vectors.  g~ and the doubles live only in HBM (no host copies)."""
+def _c4_run(mlcc, prec, steps, warmup, nvec, solves, w=0.4, n_roots=5):
+    """The headline workload in one precision: set-up (L drawn on the device),
+    ground state, nvec effective transforms per step (the timed region), then
+    the n_roots Davidson solve."""
+    import numpy as np
     import torch
-    from paper_2006_05226_amd.synth import CONFIGS, gen_eps
+    from paper_2006_05226_amd.synth import gen_eps
 
-    c = CONFIGS["mlcc2_150_1200_3600"]
+    c = _c4_config()
     O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
     eps = gen_eps(O, V, o, seed=0)
-    out = {"workload": f"MLCC2 n_occ={O} n_vir={V} n_chol={J}, CC2 active {o}/{v}, effective-singles "
-                       "Davidson for 5 roots, device-drawn L, FP64 amplitudes/DIIS/Davidson"}
+    print(f"c4 {prec}: set-up", file=sys.stderr, flush=True)
+    ctx = mlcc.Context(0)
+    t0 = time.perf_counter()
+    P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlcc2", precision=prec, n_chol=J, seed=0)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    print(f"c4 {prec}: ground state", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    gs = P.ground_state(tol=1e-8 if prec == "fp64" else 1e-6)
+    t_gs = time.perf_counter() - t0
+    c1 = np.random.default_rng(1).standard_normal((nvec, O * V))
+    c1 /= np.linalg.norm(c1, axis=1)[:, None]
+    cd = torch.tensor(c1, device="cuda")
+    sd = torch.empty_like(cd)
+    print(f"c4 {prec}: transforms", file=sys.stderr, flush=True)
+    P.jacobian_transform_eff(w, cd, sd)  # builds the Jacobian intermediates
+    for _ in range(warmup):
+        P.jacobian_transform_eff(w, cd, sd)
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.jacobian_transform_eff(w, cd, sd)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = ctx.profile_stats()
+    ctx.profile(False)
+    entry = dict(transforms_per_s=steps * nvec / dt, ms_per_step=1e3 * dt / steps,
+                 setup_seconds=t_setup, gs_seconds=t_gs, gs_iterations=gs["iterations"],
+                 e_corr=gs["energy"], gs_converged=gs["converged"], stats=stats,
+                 hbm_bytes_after_transforms=ctx.bytes())
+    if solves:
+        print(f"c4 {prec}: davidson", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        dav = P.davidson(n_roots, tol=1e-6, effective=True)
+        entry.update(davidson_seconds=time.perf_counter() - t0, davidson_transforms=dav["transforms"],
+                     omega=list(dav["omega"]), davidson_converged=dav["converged"])
+    entry["hbm_bytes_allocated"] = ctx.bytes()
+    P.close()
+    ctx.close()
+    del cd, sd
+    torch.cuda.empty_cache()
+    return entry
+
+
+def _c2_leg(mlcc, steps, warmup, precisions, nvec=4, solves=True):
+    """Full-space MLCC2 Jacobian transforms/s at 40/400/1200 (active 15/150):
+    batches of nvec singles+doubles trial vectors at converged amplitudes,
+    host-drawn inputs (seed 0), and a 4-root full-space Davidson."""
+    import numpy as np
+    import torch
+    from paper_2006_05226_amd.synth import CONFIGS, gen_inputs, gen_vectors
+
+    c = CONFIGS["mlcc2_40_400_1200"]
+    O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
+    M = o * v
+    inp = gen_inputs(seed=0, **c)
+    c1, c2 = gen_vectors(nvec, O, V, M, seed=1)
+    cvec = np.concatenate([c1.reshape(nvec, -1), c2.reshape(nvec, -1)], axis=1)
+    out = {"workload": f"MLCC2 full-space Jacobian transform, n_occ={O} n_vir={V} n_chol={J}, "
+                       f"CC2 active {o}/{v}, batch of {nvec} trial vectors"}
     for prec in precisions:
-        print(f"c4: {prec}", file=sys.stderr, flush=True)
+        print(f"c2: {prec}", file=sys.stderr, flush=True)
         ctx = mlcc.Context(0)
+        P = mlcc.Problem(ctx, inp.L, inp.eps, O, V, o, v, model="mlcc2", precision=prec)
         t0 = time.perf_counter()
-        P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlcc2", precision=prec, n_chol=J,
-                         seed=0)
-        t_setup = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        gs = P.ground_state(tol=1e-6)
+        gs = P.ground_state(tol=1e-8 if prec == "fp64" else 1e-6)
         t_gs = time.perf_counter() - t0
-        c1 = torch.randn(nvec, O * V, dtype=torch.float64, device="cuda",
-                         generator=torch.Generator(device="cuda").manual_seed(0)) * 1e-2
-        s1 = torch.empty_like(c1)
-        P.jacobian_transform_eff(0.4, c1, s1)
+        cd = torch.tensor(cvec, device="cuda")
+        sd = torch.empty_like(cd)
+        P.jacobian_transform(cd, sd)
+        for _ in range(warmup):
+            P.jacobian_transform(cd, sd)
         torch.cuda.synchronize()
         ctx.profile(True)
         t0 = time.perf_counter()
         for _ in range(steps):
-            P.jacobian_transform_eff(0.4, c1, s1)
+            P.jacobian_transform(cd, sd)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         stats = ctx.profile_stats()
         ctx.profile(False)
-        t0 = time.perf_counter()
-        dav = P.davidson(5, tol=1e-5, effective=True)
-        t_dav = time.perf_counter() - t0
-        peak = ctx.bytes()
+        e = dict(transforms_per_s=steps * nvec / dt, ms_per_step=1e3 * dt / steps, gs_seconds=t_gs,
+                 gs_iterations=gs["iterations"], e_corr=gs["energy"],
+                 contractions=_contractions(stats, steps, 8))
+        if solves:
+            t0 = time.perf_counter()
+            dav = P.davidson(4, tol=1e-6)
+            e.update(davidson_seconds=time.perf_counter() - t0, davidson_transforms=dav["transforms"],
+                     omega=list(dav["omega"]), davidson_converged=dav["converged"])
+        out[prec] = e
         P.close()
         ctx.close()
-        del c1, s1
+        del cd, sd
         torch.cuda.empty_cache()
-        out[prec] = {
-            "setup_seconds": t_setup, "gs_seconds": t_gs, "gs_iterations": gs["iterations"],
-            "e_corr": gs["energy"], "eff_transforms_per_s": steps * nvec / dt,
-            "davidson_seconds": t_dav, "davidson_transforms": dav["transforms"],
-            "omega": list(dav["omega"]), "davidson_converged": dav["converged"],
-            "hbm_bytes_allocated": peak,
-            "contractions": {k: dict(ms_per_step=st["ms"] / steps,
-                                     tflops=st["flops"] / max(st["ms"], 1e-9) / 1e9)
-                             for k, st in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])[:8]}}
-    if len(precisions) == 2:
-        a, b = (out[p] for p in precisions)
-        out["difference"] = dict(e_corr=b["e_corr"] - a["e_corr"],
-                                 omega=[y - x for x, y in zip(a["omega"], b["omega"])])
+    for p in ("fp32", "bf16x3"):
+        if p in out and "fp64" in out:
+            out[f"speedup_{p}_vs_fp64"] = out[p]["transforms_per_s"] / out["fp64"]["transforms_per_s"]
     return out
+
+
+def _contractions(stats, steps, top=None):
+    items = sorted(stats.items(), key=lambda kv: -kv[1]["ms"])
+    if top:
+        items = items[:top]
+    return {k: dict(ms_per_step=st["ms"] / steps, launches_per_step=st["launches"] / steps,
+                    tflops=st["flops"] / max(st["ms"], 1e-9) / 1e9) for k, st in items}
+
+
+def _dominant_roofline(stats, prec):
+    dom = max(stats, key=lambda k: stats[k]["ms"])
+    d = stats[dom]
+    achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
+    return dom, {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                 "frac": achieved / PEAK_TFLOPS[prec], "peak_is": PEAK_NOTE[prec], "kernel": dom,
+                 "launches": d["launches"], "avg_launch_ms": d["ms"] / d["launches"],
+                 "flops_per_launch": d["flops"] / d["launches"]}
 
 
 def _serving(mlcc, n_req, slots, precision="bf16x3", rate_frac=0.7, gs_tol=1e-6, es_tol=1e-5):
@@ -378,22 +510,19 @@ def _serving(mlcc, n_req, slots, precision="bf16x3", rate_frac=0.7, gs_tol=1e-6,
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--nvec", type=int, default=4)
-    ap.add_argument("--config", default="mlcc2_40_400_1200")
+    ap.add_argument("--steps", type=int, default=4, help="timed steps (5 vectors each)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--nvec", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-solves", action="store_true", help="skip the Davidson solve timing")
+    ap.add_argument("--no-solves", action="store_true", help="skip the Davidson solves")
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 40/400/1200 full-space leg")
     ap.add_argument("--no-mlccsd", action="store_true", help="skip the MLCCSD leg")
     ap.add_argument("--no-cnto", action="store_true", help="skip the orbital-selection leg")
-    ap.add_argument("--c4", action="store_true",
-                    help="also run MLCC2 at 150/1200/3600 (active 50/500), ~1 minute")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy 3 times (reference for HBM counters)")
-    ap.add_argument("--serve", type=int, default=64,
-                    help="requests in the serving stream (0 = skip; 256 = the full stream, "
-                         "about 4 minutes)")
+    ap.add_argument("--serve", type=int, default=256,
+                    help="requests in the serving stream (0 = skip; 256 = the full stream)")
     ap.add_argument("--slots", type=int, default=8)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -403,11 +532,9 @@ def main():
               "transform) is designed but not built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2006_05226_amd import mlcc
-    from paper_2006_05226_amd.synth import CONFIGS, gen_inputs, gen_vectors
 
     if args.copy_calibration:
         src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")  # 512 MiB
@@ -417,98 +544,39 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    c = CONFIGS[args.config]
+    c = _c4_config()
     O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
-    M = o * v
-    inp = gen_inputs(seed=0, **c)
-    c1, c2 = gen_vectors(args.nvec, O, V, M, seed=1)
-    cvec = np.concatenate([c1.reshape(args.nvec, -1), c2.reshape(args.nvec, -1)], axis=1)
     precs = [p for p in args.precisions.split(",") if p]
-    res = {}
-    for prec in precs:
-        print(f"transforms: {prec}", file=sys.stderr, flush=True)
-        ctx = mlcc.Context(0)
-        P = mlcc.Problem(ctx, inp.L, inp.eps, O, V, o, v, model="mlcc2", precision=prec)
-        t0 = time.perf_counter()
-        gs = P.ground_state(tol=1e-8 if prec == "fp64" else 1e-6)
-        t_gs = time.perf_counter() - t0
-        cd = torch.tensor(cvec, device="cuda")
-        sd = torch.empty_like(cd)
-        P.jacobian_transform(cd, sd)  # builds the Jacobian intermediates
-        for _ in range(args.warmup):
-            P.jacobian_transform(cd, sd)
-        torch.cuda.synchronize()
-        ctx.profile(True)
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            P.jacobian_transform(cd, sd)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        stats = ctx.profile_stats()
-        ctx.profile(False)
-        entry = dict(transforms_per_s=args.steps * args.nvec / dt, ms_per_step=1e3 * dt / args.steps,
-                     gs_seconds=t_gs, gs_iterations=gs["iterations"], e_corr=gs["energy"],
-                     stats=stats)
-        if not args.no_solves:
-            t0 = time.perf_counter()
-            dav = P.davidson(4, tol=1e-6)
-            entry.update(davidson_seconds=time.perf_counter() - t0,
-                         davidson_transforms=dav["transforms"], omega=list(dav["omega"]),
-                         davidson_converged=dav["converged"])
-        res[prec] = entry
-        P.close()
-        ctx.close()
-        del cd, sd
-        torch.cuda.empty_cache()
-
+    res = {p: _c4_run(mlcc, p, args.steps, args.warmup, args.nvec, not args.no_solves)
+           for p in precs}
     main_p = precs[0]
     r0 = res[main_p]
-    # dominant contraction of the timed region
-    st = r0["stats"]
-    dom = max(st, key=lambda k: st[k]["ms"])
-    d = st[dom]
-    achieved = d["flops"] / (d["ms"] * 1e-3) / 1e12
-    total_gemm_ms = sum(s["ms"] for s in st.values())
-    traffic = _profiled_traffic(dom, args.config, main_p)
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[main_p],
-                "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[main_p], "traffic": traffic,
-                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, "
-                                "scaled by a 512 MiB copy)",
-                "kernel": dom, "launches": d["launches"],
-                "avg_launch_ms": d["ms"] / d["launches"],
-                "flops_per_launch": d["flops"] / d["launches"],
-                "gemm_share_of_step": total_gemm_ms / (r0["ms_per_step"] * args.steps)}
-    extra = {p: {k: v for k, v in e.items() if k != "stats"} for p, e in res.items()}
+    dom, roofline = _dominant_roofline(r0["stats"], main_p)
+    roofline["traffic"] = _profiled_traffic(dom, C4, main_p)
+    roofline["traffic_unit"] = ("HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a "
+                                "512 MiB copy)")
+    total_gemm_ms = sum(st["ms"] for st in r0["stats"].values())
+    roofline["gemm_share_of_step"] = total_gemm_ms / (r0["ms_per_step"] * args.steps)
+    flops_vec = eff_transform_flops(O, V, J, o, v)
+    extra = {"workload_flops_per_transform": flops_vec}
     for p, e in res.items():
-        extra[p]["contractions"] = {k: dict(ms_per_step=s["ms"] / args.steps,
-                                            tflops=s["flops"] / max(s["ms"], 1e-9) / 1e9)
-                                    for k, s in sorted(e["stats"].items(),
-                                                       key=lambda kv: -kv[1]["ms"])}
-        # the dominant contraction of this precision against its MFMA peak(s)
-        pst = e["stats"]
-        pdom = max(pst, key=lambda k: pst[k]["ms"])
-        pa = pst[pdom]["flops"] / (pst[pdom]["ms"] * 1e-3) / 1e12
-        pr = {"kernel": pdom, "achieved_tflops": pa, "peak_tflops": PEAK_TFLOPS[p],
-              "frac": pa / PEAK_TFLOPS[p]}
-        if p == "bf16x3":
-            pr.update(peak_note="FP32-equivalent flops; peak_tflops is the FP32 MFMA peak. "
-                                "Against the BF16 matrix cores (three dense BF16 MFMAs per product):",
-                      peak_bf16_three_products_tflops=BF16_DENSE_TFLOPS / 3.0,
-                      frac_bf16_three_products=pa / (BF16_DENSE_TFLOPS / 3.0))
-        extra[p]["roofline"] = pr
-    if "fp32" in res and "fp64" in res:
-        extra["speedup_fp32_vs_fp64"] = res["fp32"]["transforms_per_s"] / res["fp64"]["transforms_per_s"]
+        x = {k: val for k, val in e.items() if k != "stats"}
+        x["contractions"] = _contractions(e["stats"], args.steps)
+        x["sustained_tflops"] = flops_vec * e["transforms_per_s"] / 1e12
+        _, x["roofline"] = _dominant_roofline(e["stats"], p)
+        extra[p] = x
     for p in ("fp32", "bf16x3"):
         if p in res and "fp64" in res:
             extra[f"speedup_{p}_vs_fp64"] = res[p]["transforms_per_s"] / res["fp64"]["transforms_per_s"]
+            d = dict(e_corr_eh=res[p]["e_corr"] - res["fp64"]["e_corr"])
             if "omega" in res[p] and "omega" in res["fp64"]:
-                extra[f"{p}_minus_fp64"] = dict(
-                    e_corr=res[p]["e_corr"] - res["fp64"]["e_corr"],
-                    omega=[a - b for a, b in zip(res[p]["omega"], res["fp64"]["omega"])])
-    if args.c4:
-        extra["c4"] = _c4_leg(mlcc)
+                d["omega_eh"] = [a - b for a, b in zip(res[p]["omega"], res["fp64"]["omega"])]
+                d["omega_ev"] = [x * 27.211386245988 for x in d["omega_eh"]]
+            extra[f"{p}_minus_fp64"] = d
+    if not args.no_c2:
+        extra["c2"] = _c2_leg(mlcc, max(5, 5 * args.steps), 2, precs, solves=not args.no_solves)
     if not args.no_mlccsd:
-        extra["mlccsd"] = _mlccsd_leg(mlcc, max(3, args.steps // 4), 1, precs)
+        extra["mlccsd"] = _mlccsd_leg(mlcc, max(3, args.steps), 1, precs)
     if not args.no_cnto:
         extra["cnto"] = _cnto_leg(mlcc, [p for p in ("fp64", "bf16x3") if p in precs])
     if args.serve > 0:
@@ -516,7 +584,7 @@ def main():
         extra["serving"] = _serving(mlcc, args.serve, args.slots)
     cpu = None if args.no_cpu_baseline else _cpu_baseline()
     line = {
-        "metric": "Jacobian transforms/s (MLCC2, full space)",
+        "metric": "Jacobian transforms/s (MLCC2, effective singles)",
         "value": r0["transforms_per_s"],
         "unit": "transforms/s",
         "n_gpus": 1,
@@ -528,8 +596,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if main_p == "fp64" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"MLCC2 Jacobian transform, n_occ={O} n_vir={V} n_chol={J}, "
-                               f"CC2 active {o}/{v}, batch of {args.nvec} trial vectors",
+        "config": {"workload": f"MLCC2 effective-singles Jacobian transform, n_occ={O} n_vir={V} "
+                               f"n_chol={J}, CC2 active {o}/{v}, batch of {args.nvec} trial vectors, "
+                               "device-drawn Cholesky vectors",
                    "n_occ": O, "n_vir": V, "n_chol": J, "n_occ_act": o, "n_vir_act": v,
                    "n_vec": args.nvec, "precision": main_p},
         "roofline": roofline,
