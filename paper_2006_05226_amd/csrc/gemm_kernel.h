@@ -122,6 +122,8 @@ template <typename T, int BMN, bool KMAJ, bool VONLY, int NT> struct Stage {
   bool vec[U];      // the unit may use one 16-byte load
   bool contig[U];   // KMAJ: the unit's VEC output indices are consecutive in memory
   bool fast;        // every unit of every thread of the block may use 16-byte loads
+  int klim[U];      // load_v: leading elements of the unit inside the reduction range
+  bool kall;        // load_v: the whole k-step lies inside the reduction range
 
   // mn0: first output index of the tile; n_mn, lo, s_lo, s_hi: extent and
   // two-level strides of the output dimension.  Units wholly outside the
@@ -190,9 +192,15 @@ template <typename T, int BMN, bool KMAJ, bool VONLY, int NT> struct Stage {
       off[e] = i < n_mn ? two_level(i, lo, s_mn, s_hi) : off0;
     }
   }
+  // The loaded values are not masked here: a select on them would make the
+  // k-step wait for its loads at once, before the MFMAs of the current step
+  // that they are meant to overlap.  klim records how many leading elements
+  // of each unit lie inside the reduction range; mask() applies it when the
+  // registers go to LDS, after the MFMAs.
   __device__ __forceinline__ void load_v(T (&rg)[U][VEC], const T *X, int64_t k0, int64_t K,
-                                         int64_t s_k) const {
+                                         int64_t s_k) {
     typedef typename Tr<T>::g16 v16;
+    kall = k0 + BK <= K;
 #pragma unroll
     for (int e = 0; e < U; ++e) {
       const int64_t k = k0 + (KMAJ ? row[e] : col[e]);
@@ -201,8 +209,16 @@ template <typename T, int BMN, bool KMAJ, bool VONLY, int NT> struct Stage {
       const T *src = KMAJ ? X + off[e] + kc * s_k : X + off[e] + kc;
       const v16 v = *reinterpret_cast<const v16 *>(src);
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) rg[e][q] = (KMAJ ? in : k + q < K) ? v[q] : T(0);
+      for (int q = 0; q < VEC; ++q) rg[e][q] = v[q];
+      klim[e] = KMAJ ? (in ? VEC : 0) : (int)min<int64_t>(max<int64_t>(K - k, 0), VEC);
     }
+  }
+  __device__ __forceinline__ void mask(T (&rg)[U][VEC]) const {
+    if (kall) return;  // uniform: every step but a partial last one
+#pragma unroll
+    for (int e = 0; e < U; ++e)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) rg[e][q] = q < klim[e] ? rg[e][q] : T(0);
   }
 
   // a k-step of the block's interior: every unit in range and aligned, so
@@ -441,11 +457,19 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm(KParams kp) {
     }
   };
 
+  auto store_next = [&](int buf) {
+    if constexpr (VONLY) {
+      sa.mask(ra);
+      sb.mask(rb);
+    }
+    sa.store(As[buf], ra);
+    sb.store(Bs[buf], rb);
+  };
+
   int cur = 0;
   if (s_begin < s_end) {
     load_next();
-    sa.store(As[0], ra);
-    sb.store(Bs[0], rb);
+    store_next(0);
   }
   __syncthreads();
   for (int64_t step = s_begin; step < s_end; ++step) {
@@ -502,10 +526,7 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm(KParams kp) {
               acc[i][j][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i][s], bf[s], acc[i][j][r], 0, 0, 0);
         }
     }
-    if (more) {
-      sa.store(As[cur ^ 1], ra);
-      sb.store(Bs[cur ^ 1], rb);
-    }
+    if (more) store_next(cur ^ 1);
     __syncthreads();
     cur ^= 1;
   }
@@ -590,6 +611,8 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams k
     *reinterpret_cast<bf4v *>(lo) = l;
   };
   auto store = [&](int buf) {
+    sa.mask(ra);
+    sb.mask(rb);
 #pragma unroll
     for (int e = 0; e < SA::U; ++e)
       split_store(ra[e], &Ah[buf][sa.row[e]][sa.col[e]], &Al[buf][sa.row[e]][sa.col[e]]);
