@@ -413,6 +413,55 @@ def _c2_leg(mlcc, steps, warmup, precisions, nvec=4, solves=True):
     return out
 
 
+def _cholesky_leg(mlcc, precisions, n_ao=160, n_aux=480, n_mo=120, n_act=40, rel_tau=1e-8):
+    """Two-step Cholesky decomposition (Sec. 2.4) of synthetic AO integrals:
+    the basis by pivoted Cholesky without and with the MO-screened diagonal
+    (active = the first n_act MOs), then the MO Cholesky vectors by
+    Algorithm 1 in each precision, with the contraction rates."""
+    import numpy as np
+    import torch
+    from paper_2006_05226_amd.synth import gen_ao_eri, gen_mo_coefficients
+
+    G, _ = gen_ao_eri(n_ao, n_aux, 0)
+    Cmo = gen_mo_coefficients(n_ao, n_mo, 1)
+    tau = rel_tau * float(np.diag(G).max())
+    nu = (Cmo[:, :n_act] ** 2).max(axis=1)
+    npair = n_ao * (n_ao + 1) // 2
+    out = {"workload": f"AO integrals over {npair} pairs (n_ao={n_ao}, rank {n_aux}), n_mo={n_mo}, "
+                       f"MO screening on {n_act} active MOs, tau = {rel_tau:g} x max diagonal"}
+    ctx = mlcc.Context(0)
+    Gd = torch.tensor(G, device="cuda")
+    Cd = torch.tensor(Cmo, device="cuda")
+    for name, w in (("standard", None), ("mo_screened", nu)):
+        print(f"cholesky basis: {name}", file=sys.stderr, flush=True)
+        ctx.cholesky_basis(n_ao, Gd, tau, nu=w)   # warm-up (library start-up)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        piv, QiT = ctx.cholesky_basis(n_ao, Gd, tau, nu=w)
+        out[f"basis_{name}"] = dict(n_vectors=len(piv), seconds=time.perf_counter() - t0)
+    piv, QiT = ctx.cholesky_basis(n_ao, Gd, tau)
+    nJ = len(piv)
+    flops = nJ * (2.0 * n_mo * n_ao * n_ao + 2.0 * n_mo * n_mo * n_ao) + 2.0 * nJ * nJ * n_mo * n_mo
+    out["algorithm1_flops"] = flops
+    for prec in precisions:
+        print(f"algorithm 1: {prec}", file=sys.stderr, flush=True)
+        Ld = torch.empty((nJ, n_mo, n_mo), dtype=torch.float64, device="cuda")
+        ctx.mo_cholesky(n_ao, n_mo, Gd, piv, QiT, Cd, precision=prec, out=Ld)
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        ctx.mo_cholesky(n_ao, n_mo, Gd, piv, QiT, Cd, precision=prec, out=Ld)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.profile_stats()
+        ctx.profile(False)
+        out[prec] = dict(seconds=dt, tflops=flops / dt / 1e12, contractions=_contractions(st, 1))
+        del Ld
+    ctx.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def _contractions(stats, steps, top=None):
     items = sorted(stats.items(), key=lambda kv: -kv[1]["ms"])
     if top:
@@ -519,6 +568,8 @@ def main():
     ap.add_argument("--no-c2", action="store_true", help="skip the 40/400/1200 full-space leg")
     ap.add_argument("--no-mlccsd", action="store_true", help="skip the MLCCSD leg")
     ap.add_argument("--no-cnto", action="store_true", help="skip the orbital-selection leg")
+    ap.add_argument("--no-cholesky", action="store_true",
+                    help="skip the two-step Cholesky decomposition leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 512 MiB device copy 3 times (reference for HBM counters)")
     ap.add_argument("--serve", type=int, default=256,
@@ -579,6 +630,8 @@ def main():
         extra["mlccsd"] = _mlccsd_leg(mlcc, max(3, args.steps), 1, precs)
     if not args.no_cnto:
         extra["cnto"] = _cnto_leg(mlcc, [p for p in ("fp64", "bf16x3") if p in precs])
+    if not args.no_cholesky:
+        extra["cholesky"] = _cholesky_leg(mlcc, precs)
     if args.serve > 0:
         print(f"serving: {args.serve} requests", file=sys.stderr, flush=True)
         extra["serving"] = _serving(mlcc, args.serve, args.slots)

@@ -273,6 +273,47 @@ mlcc_status mlcc_cnto(mlcc_problem *prob, int32_t n_states, const double *R, con
                       int32_t n_occ_act, int32_t n_vir_act, double *m_eig, double *n_eig,
                       double *C, double *eps_out, double *fock_out, double *L_out);
 
+/* ---- Cholesky vectors in the MO basis (Sec. 2.4) -----------------------------
+ * The two-step Cholesky decomposition of AO electron-repulsion integrals,
+ * which builds the MO Cholesky vectors without storing AO ones.  The
+ * integrals are a matrix over packed AO pairs: G[ab][cd] = (ab|cd) for a >= b,
+ * c >= d, pair index a (a + 1) / 2 + b, npair = n_ao (n_ao + 1) / 2, row
+ * major, symmetric positive semidefinite (host or device memory; it stands in
+ * for an AO integral engine, which this library does not include).
+ *
+ * First step, the Cholesky basis: pivoted Cholesky decomposition of G.  The
+ * updated diagonal D_ab = (ab|ab) - sum_J (L^J_ab)^2 is screened as
+ * D~_ab = nu_a D_ab nu_b (eq. cd_screening) with nu [n_ao] (host or device;
+ * e.g. nu_a = max_p (C^a_ap)^2 over the active MOs, eq. mo_screening), or not
+ * screened when nu is NULL.  The pair with the largest D~ (the lowest pair
+ * index among equals) is the next pivot; the decomposition stops when
+ * max D~ < tau or after max_vectors pivots.
+ * Outputs: pivots [max_vectors] (host; pair indices in selection order),
+ * *n_vectors, and QinvT (host or device, NULL to skip): its first n_vectors^2
+ * entries, row stride n_vectors, hold Q^-T with S = Q Q^T the Cholesky
+ * factorization of S_KL = (K|L) over the pivots in selection order.
+ * MLCC_E_ARG for bad sizes or a non-positive tau; MLCC_E_NUMERIC for a
+ * non-finite diagonal, a matrix that is not positive semidefinite, or a
+ * singular S. */
+mlcc_status mlcc_cholesky_basis(mlcc_context *ctx, int32_t n_ao, const double *G, const double *nu,
+                                double tau, int32_t max_vectors, int32_t *pivots,
+                                int32_t *n_vectors, double *QinvT);
+
+/* Second step, Algorithm 1 (Sec. 2.4): the MO Cholesky vectors
+ *   L^J_pq = sum_K X_pqK [Q^-T]_KJ,  X_pqK = sum_ab C_ap C_bq (ab|K),
+ * built for batches of p_batch MO indices p at a time (0: as many as 2 GB of
+ * scratch allows), the integrals (ab|K) taken again from G at the pivots for
+ * each batch.  G as for mlcc_cholesky_basis; pivots [n_vec] (host) and QinvT
+ * [n_vec][n_vec] (host or device) as it returns them; C [n_ao][n_mo] MO
+ * coefficients (host or device).  L_out [n_vec][n_mo][n_mo] FP64 (host or
+ * device): the n_chol x n x n input of mlcc_problem_desc.  precision: the
+ * arithmetic of the three contractions (MLCC_FP64, MLCC_FP32, MLCC_BF16X3).
+ * MLCC_E_ARG for bad sizes, NULL pointers or pivots outside the pair range. */
+mlcc_status mlcc_mo_cholesky(mlcc_context *ctx, int32_t precision, int32_t n_ao, int32_t n_mo,
+                             const double *G, int32_t n_vec, const int32_t *pivots,
+                             const double *QinvT, const double *C, int32_t p_batch,
+                             double *L_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,279 @@
+"""MLCC2 quantities of the dense oracle (mlcc.py) at sampled elements, for
+workloads whose Cholesky vectors do not fit in host memory.
+
+TEST INFRASTRUCTURE ONLY -- never called by the product path.
+
+The Cholesky vectors come from a block source ``Lsrc(Ks, rows, cols)`` that
+returns L^K_pq for K in Ks, p in rows, q in cols (MO indices, occupied first;
+for a workload drawn on the device it regenerates the blocks from the
+generator's definition).  Singles amplitudes t1 and trial vectors are (V, O)
+arrays whose nonzero entries span small sets of virtual and occupied
+indices; every sum below runs over all indices where its summand can be
+nonzero, so the results are those of mlcc.py on the full arrays.
+
+* ``lt_block``      L~ = (1 - T) L (1 + T) on a block (App. A, X1 basis)
+* ``fock_block``    F~ = h~ + sum_I (2 g~_pqII - g~_pIIq), h = F - G(D_HF)
+* ``g_samples``     g~_aibj = sum_K L~^K_ai L~^K_bj at given quadruples
+* ``omega1_samples`` Omega_AI (App. A, MLCC2 Omega vector) at given (A, I),
+  with the doubles given by a rule on the g~ they are built from: the
+  analytic s = -g~/eps, or, for the effective Jacobian by complex step, the
+  eliminated doubles of the trial vector
+* ``eff_sigma_samples`` sigma = A11 c + A12 (w - eps)^-1 A21 c at given (A, I),
+  as Im Omega_AI(t1 + i h c, s + i h c2) / h (complex step, h = 1e-30)
+
+Pinned by tests/test_oracle_sampled.py against mlcc.py on small problems.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .mlcc import Dims, _einsum
+
+KCHUNK = 256  # Cholesky vectors per block request in the K-summed products
+
+
+def _support(t1):
+    """Virtual rows and occupied columns that hold nonzero amplitudes."""
+    nz = np.nonzero(t1)
+    return np.unique(nz[0]), np.unique(nz[1])
+
+
+def lt_block(Lsrc, t1, d: Dims, Ks, rows, cols):
+    """L~^K_pq = [(1 - T) L^K (1 + T)]_pq for K in Ks, p in rows, q in cols,
+    T[O+A][I] = t_AI:
+      L~_pq = L_pq + [q occ] sum_A L_pA t_Aq - [p vir] sum_I t_pI L_Iq
+              - [p vir, q occ] sum_IA t_pI L_IA t_Aq
+    with A and I over the support of t1."""
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    L = Lsrc(Ks, rows, cols)
+    SA, SI = _support(t1)
+    if len(SA) == 0:
+        return L.astype(np.result_type(L, t1))
+    mA = d.O + SA
+    # T[A][q] for q occupied (zero for virtual q); T[p][I] for p virtual
+    TAq = np.zeros((len(SA), len(cols)), dtype=t1.dtype)
+    qo = cols < d.O
+    TAq[:, qo] = t1[np.ix_(SA, cols[qo])]
+    TpI = np.zeros((len(rows), len(SI)), dtype=t1.dtype)
+    pv = rows >= d.O
+    TpI[pv, :] = t1[np.ix_(rows[pv] - d.O, SI)]
+    out = L + _einsum("Kpa,aq->Kpq", Lsrc(Ks, rows, mA), TAq)
+    out = out - _einsum("pi,Kiq->Kpq", TpI, Lsrc(Ks, SI, cols))
+    out = out - _einsum("pi,Kia,aq->Kpq", TpI, Lsrc(Ks, SI, mA), TAq)
+    return out
+
+
+def _ksum(fA, fB, spec, J):
+    """sum over the Cholesky index of products of two K-indexed blocks, taken
+    KCHUNK vectors at a time: fA(Ks), fB(Ks) -> arrays with K first."""
+    acc = None
+    for k0 in range(0, J, KCHUNK):
+        Ks = np.arange(k0, min(J, k0 + KCHUNK))
+        part = _einsum(spec, fA(Ks), fB(Ks))
+        acc = part if acc is None else acc + part
+    return acc
+
+
+def _occ_trace(Lsrc, t1, d: Dims, transformed: bool):
+    """d^K = sum_I L^K_II (or of L~) over all occupied I."""
+    occ = np.arange(d.O)
+    out = []
+    for k0 in range(0, Lsrc.n_chol, KCHUNK):
+        Ks = np.arange(k0, min(Lsrc.n_chol, k0 + KCHUNK))
+        blk = lt_block(Lsrc, t1, d, Ks, occ, occ) if transformed else Lsrc(Ks, occ, occ)
+        out.append(np.einsum("Kii->K", blk))
+    return np.concatenate(out)
+
+
+def h_block(Lsrc, eps, d: Dims, rows, cols, dK=None):
+    """h_pq = F_pq - sum_I (2 g_pqII - g_pIIq), F = diag(eps), untransformed."""
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    J = Lsrc.n_chol
+    occ = np.arange(d.O)
+    if dK is None:
+        dK = _occ_trace(Lsrc, np.zeros((d.V, d.O)), d, False)
+    coul = _ksum(lambda Ks: Lsrc(Ks, rows, cols), lambda Ks: dK[Ks], "Kpq,K->pq", J)
+    exch = _ksum(lambda Ks: Lsrc(Ks, rows, occ), lambda Ks: Lsrc(Ks, occ, cols), "Kpi,Kiq->pq", J)
+    F = (rows[:, None] == cols[None, :]) * eps[rows][:, None]
+    return F - (2.0 * coul - exch)
+
+
+def fock_block(Lsrc, eps, d: Dims, t1, rows, cols):
+    """F~_pq = h~_pq + sum_K (2 L~^K_pq d~^K - sum_I L~^K_pI L~^K_Iq) with
+    h~ = (1 - T) h (1 + T) (App. A, Fock matrix in the X1 basis with the
+    one-electron part h = F - G(D_HF))."""
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    J = Lsrc.n_chol
+    occ = np.arange(d.O)
+    dK = _occ_trace(Lsrc, np.zeros((d.V, d.O)), d, False)
+    dKt = _occ_trace(Lsrc, t1, d, True)
+    # h~ on the block, with A, I over the support of t1
+    SA, SI = _support(t1)
+    mA = d.O + SA
+    ht = h_block(Lsrc, eps, d, rows, cols, dK).astype(np.result_type(t1, float))
+    if len(SA):
+        TAq = np.zeros((len(SA), len(cols)), dtype=t1.dtype)
+        qo = cols < d.O
+        TAq[:, qo] = t1[np.ix_(SA, cols[qo])]
+        TpI = np.zeros((len(rows), len(SI)), dtype=t1.dtype)
+        pv = rows >= d.O
+        TpI[pv, :] = t1[np.ix_(rows[pv] - d.O, SI)]
+        ht = ht + h_block(Lsrc, eps, d, rows, mA, dK) @ TAq
+        ht = ht - TpI @ h_block(Lsrc, eps, d, SI, cols, dK)
+        ht = ht - TpI @ h_block(Lsrc, eps, d, SI, mA, dK) @ TAq
+    coul = _ksum(lambda Ks: lt_block(Lsrc, t1, d, Ks, rows, cols), lambda Ks: dKt[Ks],
+                 "Kpq,K->pq", J)
+    exch = _ksum(lambda Ks: lt_block(Lsrc, t1, d, Ks, rows, occ),
+                 lambda Ks: lt_block(Lsrc, t1, d, Ks, occ, cols), "Kpi,Kiq->pq", J)
+    return ht + 2.0 * coul - exch
+
+
+class Active:
+    """L~_ai and L~_jc over the whole active space (K, v, o) and (K, o, v)."""
+
+    def __init__(self, Lsrc, t1, d: Dims):
+        J = Lsrc.n_chol
+        av = d.O + np.arange(d.v)
+        ao = np.arange(d.o)
+        vo, ov = [], []
+        for k0 in range(0, J, KCHUNK):
+            Ks = np.arange(k0, min(J, k0 + KCHUNK))
+            vo.append(lt_block(Lsrc, t1, d, Ks, av, ao))
+            ov.append(lt_block(Lsrc, t1, d, Ks, ao, av))
+        self.vo = np.concatenate(vo)
+        self.ov = np.concatenate(ov)
+
+
+def g_samples(Lsrc, t1, d: Dims, quads, act=None):
+    """g~_aibj = sum_K L~^K_ai L~^K_bj at quadruples (a, i, b, j) of active
+    indices (a, b relative to the active virtual block)."""
+    act = act or Active(Lsrc, t1, d)
+    q = np.asarray(quads)
+    return np.einsum("Kn,Kn->n", act.vo[:, q[:, 0], q[:, 1]], act.vo[:, q[:, 2], q[:, 3]])
+
+
+def _den(eps, d: Dims):
+    """e_a - e_i over the active space, (v, o)."""
+    return eps[d.O:d.O + d.v][:, None] - eps[:d.o][None, :]
+
+
+def s_analytic_rule(g, den):
+    """MLCC2 doubles solved analytically: s = -g~ / eps."""
+    return -g / den
+
+
+def omega1_samples(Lsrc, eps, d: Dims, t1, pairs, s_rule=s_analytic_rule, act=None):
+    """Omega_AI (App. A, MLCC2 Omega vector) at the given (A, I):
+
+      Omega_AI = F~_AI + [I act] sum_bcj u_bicj g~_Abjc - [A act] sum_jkb u_ajbk g~_kbjI
+                 + [A, I act] sum_jb u_aibj F~_jb,   u = 2 s - s(i<->j)
+
+    with the doubles s given by s_rule(g~, eps) on the rows of g~ each term
+    needs (all active pairs against (b, I) for fixed I, or against (a, j) for
+    fixed a)."""
+    pairs = [(int(A), int(I)) for A, I in pairs]
+    act = act or Active(Lsrc, t1, d)
+    J = Lsrc.n_chol
+    D = _den(eps, d)
+    As = sorted({A for A, _ in pairs})
+    Is = sorted({I for _, I in pairs})
+    # F~_AI on the sampled rows and columns
+    F_AI = fock_block(Lsrc, eps, d, t1, d.O + np.asarray(As), np.asarray(Is))
+    out = {(A, I): F_AI[As.index(A), Is.index(I)] for A, I in pairs}
+    # F~_jb on the active block, for the u F~ term
+    Fjb = None
+    if any(A < d.v and I < d.o for A, I in pairs):
+        Fjb = fock_block(Lsrc, eps, d, t1, np.arange(d.o), d.O + np.arange(d.v))
+    # A1: [I act] sum_K sum_b L~^K_Ab Z^K_bI,  Z^K_bI = sum_cj u_bIcj L~^K_jc
+    av = d.O + np.arange(d.v)
+    for I in Is:
+        if I >= d.o:
+            continue
+        g = _einsum("Kb,Kcj->bcj", act.vo[:, :, I], act.vo)               # g~_bI,cj
+        s = s_rule(g, D[:, I][:, None, None] + D[None, :, :])
+        u = 2.0 * s - s.transpose(1, 0, 2)                                 # u_bIcj
+        Z = _einsum("bcj,Kjc->Kb", u, act.ov)                              # Z^K_bI
+        A1 = _ksum(lambda Ks: lt_block(Lsrc, t1, d, Ks, d.O + np.asarray(As), av),
+                   lambda Ks: Z[Ks], "KAb,Kb->A", J)
+        for A, I2 in pairs:
+            if I2 == I:
+                out[(A, I)] = out[(A, I)] + A1[As.index(A)]
+        # uF: [A, I act] sum_bj u_aIbj F~_jb
+        if any(A < d.v and I2 == I for A, I2 in pairs):
+            uF = np.einsum("acj,jc->a", u, Fjb)
+            for A, I2 in pairs:
+                if I2 == I and A < d.v:
+                    out[(A, I)] = out[(A, I)] + uF[A]
+    # B1: -[A act] sum_K sum_j Z^K_aj L~^K_jI,  Z^K_aj = sum_bk u_ajbk L~^K_kb
+    ao = np.arange(d.o)
+    for A in As:
+        if A >= d.v:
+            continue
+        g = _einsum("Kj,Kbk->jbk", act.vo[:, A, :], act.vo)                # g~_aj,bk
+        s = s_rule(g, D[A, :][:, None, None] + D[None, :, :])
+        u = 2.0 * s - s.transpose(2, 1, 0)                                 # u_ajbk
+        Z = _einsum("jbk,Kkb->Kj", u, act.ov)                              # Z^K_aj
+        B1 = _ksum(lambda Ks: Z[Ks], lambda Ks: lt_block(Lsrc, t1, d, Ks, ao, np.asarray(Is)),
+                   "Kj,KjI->I", J)
+        for A2, I in pairs:
+            if A2 == A:
+                out[(A, I)] = out[(A, I)] - B1[Is.index(I)]
+    return np.array([out[p] for p in pairs])
+
+
+def eff_sigma_samples(Lsrc, eps, d: Dims, t1, c1, w, pairs, h=1e-30):
+    """Effective MLCC2 transformation sigma = A11 c1 + A12 (w - eps)^-1 A21 c1
+    at the given (A, I), by complex step on the Omega vector with the doubles
+    as independent variables (the Jacobian is the derivative of Omega, and
+    the doubles-doubles block of MLCC2 is diagonal):
+      sigma_AI = Im Omega_AI(t1 + i h c1, s + i h c2) / h,
+      c2 = (A21 c1) / (w - eps) = (d g~ / d t1 . c1) / (w - eps),
+    where the real part of the doubles stays the analytic s of t1 and the
+    imaginary part of g~ at the complex amplitudes is h (d g~ . c1)."""
+    tc = t1.astype(complex) + 1j * h * c1
+
+    def rule(g, den):
+        return -g.real / den + 1j * (g.imag / (w - den))
+
+    om = omega1_samples(Lsrc, eps, d, tc, pairs, s_rule=rule)
+    return om.imag / h
+
+
+class DenseSource:
+    """A block source over a full (K, n, n) array (small problems, pins)."""
+
+    def __init__(self, L):
+        self.L = L
+        self.n_chol = L.shape[0]
+
+    def __call__(self, Ks, rows, cols):
+        return self.L[np.ix_(np.asarray(Ks), np.asarray(rows), np.asarray(cols))]
+
+
+class GeneratedSource:
+    """A block source that regenerates device-drawn Cholesky vectors (the
+    library's MLCC_SYNTH_L) from the generator's definition, keeping the
+    blocks it has drawn up to cache_bytes (the evaluations above request the
+    same blocks repeatedly)."""
+
+    def __init__(self, n_occ, n_vir, n_chol, seed, cache_bytes=16e9):
+        from paper_2006_05226_amd.synth import device_cholesky_block
+        self._gen = device_cholesky_block
+        self.n_occ, self.n_vir, self.n_chol, self.seed = n_occ, n_vir, n_chol, seed
+        self._cache = {}
+        self._bytes = 0
+        self._cap = cache_bytes
+
+    def __call__(self, Ks, rows, cols):
+        key = (tuple(np.asarray(Ks).tolist()), tuple(np.asarray(rows).tolist()),
+               tuple(np.asarray(cols).tolist()))
+        blk = self._cache.get(key)
+        if blk is None:
+            blk = self._gen(Ks, rows, cols, self.n_occ, self.n_vir, self.seed)
+            if self._bytes + blk.nbytes <= self._cap:
+                self._cache[key] = blk
+                self._bytes += blk.nbytes
+        return blk

@@ -71,7 +71,7 @@ EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "ml
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
            "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_gemm_noalloc",
            "mlcc_debug_get", "mlcc_profile_enable", "mlcc_profile_get", "mlcc_gemm_tile", "mlcc_cnto",
-           "mlcc_pair_block_occ"]
+           "mlcc_pair_block_occ", "mlcc_cholesky_basis", "mlcc_mo_cholesky"]
 
 NOALLOC_SCRATCH_BYTES = 16 << 20
 
@@ -118,6 +118,8 @@ def load(path: str = LIB_PATH):
         "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
         "mlcc_gemm_tile": (i32, [vp, i32, i32, P(i32)]),
         "mlcc_pair_block_occ": (i32, [vp, i32]),
+        "mlcc_cholesky_basis": (i32, [vp, i32, vp, vp, dbl, i32, vp, P(i32), vp]),
+        "mlcc_mo_cholesky": (i32, [vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]),
         "mlcc_cnto": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
@@ -215,6 +217,32 @@ class Context:
         context's problems (0: the memory rule)."""
         self.check(self.lib.mlcc_pair_block_occ(self.h, occ))
 
+    def cholesky_basis(self, n_ao, G, tau, nu=None, max_vectors=None):
+        """Pivots and Q^-T of the Cholesky basis of the AO pair matrix G
+        (mlcc_cholesky_basis); nu: MO screening weights or None."""
+        npair = n_ao * (n_ao + 1) // 2
+        cap = npair if max_vectors is None else max_vectors
+        piv = np.empty(cap, dtype=np.int32)
+        nv = C.c_int32()
+        QiT = np.empty(cap * cap) if cap * cap <= (1 << 27) else None
+        G = _f64(G)
+        nu = _f64(nu)
+        self.check(self.lib.mlcc_cholesky_basis(self.h, n_ao, _ptr(G), _ptr(nu), float(tau), cap,
+                                                _ptr(piv), C.byref(nv), _ptr(QiT)))
+        n = nv.value
+        return piv[:n].copy(), (QiT[: n * n].reshape(n, n).copy() if QiT is not None else None)
+
+    def mo_cholesky(self, n_ao, n_mo, G, piv, QinvT, Cmo, precision="fp64", p_batch=0, out=None):
+        """MO Cholesky vectors [n_vec][n_mo][n_mo] by Algorithm 1 (mlcc_mo_cholesky)."""
+        piv = np.ascontiguousarray(piv, dtype=np.int32)
+        nvec = len(piv)
+        if out is None:
+            out = np.empty((nvec, n_mo, n_mo))
+        G, QinvT, Cmo = _f64(G), _f64(QinvT), _f64(Cmo)
+        self.check(self.lib.mlcc_mo_cholesky(self.h, PREC[precision], n_ao, n_mo, _ptr(G), nvec,
+                                             _ptr(piv), _ptr(QinvT), _ptr(Cmo), p_batch, _ptr(out)))
+        return out
+
     def profile(self, on=True):
         self.check(self.lib.mlcc_profile_enable(self.h, 1 if on else 0))
 
@@ -284,10 +312,14 @@ class Problem:
         x2 = _f64(x2)
         self.ctx.check(self.ctx.lib.mlcc_set_amplitudes(self.h, _ptr(t1), _ptr(x2)))
 
-    def residual(self):
+    def residual(self, doubles=True, x2_out=None):
+        """Omega_1, Omega_2, the doubles used and the energy.  doubles=False
+        skips Omega_2 and the doubles (host M x M arrays); x2_out (a device
+        tensor or host array [M][M]) receives the doubles in place."""
         om1 = np.empty((self.n_vir, self.n_occ))
-        om2 = np.empty((self.M, self.M)) if self.M else None
-        x2 = np.empty((self.M, self.M)) if self.M else None
+        om2 = np.empty((self.M, self.M)) if (self.M and doubles) else None
+        x2 = x2_out if x2_out is not None else \
+            (np.empty((self.M, self.M)) if (self.M and doubles) else None)
         e = C.c_double()
         self.ctx.check(self.ctx.lib.mlcc_residual(self.h, _ptr(om1), _ptr(om2), _ptr(x2),
                                                   C.byref(e)))

@@ -145,3 +145,99 @@ CONFIGS = {
     # large MLCC2 reduced-space run, active 50/500
     "mlcc2_150_1200_3600": dict(n_occ=150, n_vir=1200, n_chol=3600, n_occ_act=50, n_vir_act=500),
 }
+
+
+# ---------------------------------------------------------------------------
+# Cholesky vectors drawn on the device (the library's MLCC_SYNTH_L), regenerated
+# block by block on the host, so that a workload too large for the host can
+# still be checked at sampled elements.  Philox4x32-10 (Salmon, Moraes, Dror,
+# Shaw, "Parallel random numbers: as easy as 1, 2, 3", SC'11) with counter
+# (min(p,q) n + max(p,q), K, 0, 0) and key (seed lo, seed hi); Box-Muller on
+# the first two output words: z = sqrt(-2 ln u1) cos(2 pi u2), u = (w + 1/2)
+# 2^-32; L[K][p][q] = (sigma exp(-K/10)) z with sigma = 0.5 / sqrt(n_occ n_vir).
+# ---------------------------------------------------------------------------
+_PHILOX_M = (0xD2511F53, 0xCD9E8D57)
+_PHILOX_W = (0x9E3779B9, 0xBB67AE85)
+_U32 = np.uint64(0xFFFFFFFF)
+
+
+def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
+    """Philox4x32-10 on arrays of 32-bit counter words (broadcast); returns
+    the four output words as uint64 arrays holding 32-bit values."""
+    x0, x1, x2, x3 = (np.asarray(c, dtype=np.uint64) & _U32 for c in (c0, c1, c2, c3))
+    m0, m1 = np.uint64(_PHILOX_M[0]), np.uint64(_PHILOX_M[1])
+    ka, kb = int(k0) & 0xFFFFFFFF, int(k1) & 0xFFFFFFFF
+    for _ in range(10):
+        p0 = m0 * x0          # 32 x 32 -> 64 bit, exact in uint64
+        p1 = m1 * x2
+        x0, x1, x2, x3 = (((p1 >> np.uint64(32)) ^ x1 ^ np.uint64(ka)) & _U32, p1 & _U32,
+                          ((p0 >> np.uint64(32)) ^ x3 ^ np.uint64(kb)) & _U32, p0 & _U32)
+        ka = (ka + _PHILOX_W[0]) & 0xFFFFFFFF
+        kb = (kb + _PHILOX_W[1]) & 0xFFFFFFFF
+    return x0, x1, x2, x3
+
+
+def device_cholesky_block(Ks, rows, cols, n_occ: int, n_vir: int, seed: int) -> np.ndarray:
+    """L[K][p][q] for K in Ks, p in rows, q in cols (index arrays), as the
+    library's device generator draws them for a problem with n_occ + n_vir
+    orbitals and the given seed.  Returns float64 (len(Ks), len(rows), len(cols))."""
+    Ks = np.asarray(Ks, dtype=np.int64)
+    rows = np.asarray(rows, dtype=np.int64)
+    cols = np.asarray(cols, dtype=np.int64)
+    n = n_occ + n_vir
+    sigma = chol_scale(n_occ, n_vir)
+    out = np.empty((len(Ks), len(rows), len(cols)))
+    lo = np.minimum(rows[:, None], cols[None, :])
+    hi = np.maximum(rows[:, None], cols[None, :])
+    pq = (lo * n + hi).astype(np.uint64)
+    step = max(1, (1 << 22) // max(1, pq.size))
+    for k0 in range(0, len(Ks), step):
+        kk = Ks[k0:k0 + step]
+        x, y, _, _ = philox4x32_10(pq[None, :, :], kk[:, None, None].astype(np.uint64), 0, 0,
+                                   seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+        u1 = (x.astype(np.float64) + 0.5) * (1.0 / 4294967296.0)
+        u2 = (y.astype(np.float64) + 0.5) * (1.0 / 4294967296.0)
+        z = np.sqrt(-2.0 * np.log(u1)) * np.cos(6.283185307179586 * u2)
+        out[k0:k0 + len(kk)] = (sigma * np.exp(-kk.astype(np.float64) / 10.0))[:, None, None] * z
+    return out
+
+
+# ---------------------------------------------------------------------------
+# AO-basis inputs of the MO Cholesky-vector construction (two-step Cholesky
+# decomposition: pivots first, then the vectors through the RI-like expression)
+# ---------------------------------------------------------------------------
+def pair_index(n_ao: int):
+    """Packed pair index of alpha >= beta: (alpha, beta) arrays of length
+    n_ao (n_ao + 1) / 2, in the order alpha * (alpha + 1) / 2 + beta."""
+    a, b = np.tril_indices(n_ao)
+    return a, b
+
+
+def gen_ao_eri(n_ao: int, n_aux: int, seed: int, decay: float = 0.15):
+    """Synthetic AO electron-repulsion integrals g_(ab)(cd) as a positive
+    semidefinite matrix over packed pairs a >= b: g = sum_P B^P_ab B^P_cd with
+    B^P symmetric, i.i.d. normal entries scaled by exp(-decay P) (a decaying
+    spectrum, as the pivots of a Cholesky decomposition fall), plus the
+    pair-diagonal weight exp(-|a - b| / 4) that makes distant pairs small, as
+    for localized AOs.  Returns (G [npair][npair], Bfull [n_aux][n_ao][n_ao])."""
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((n_aux, n_ao, n_ao))
+    B = np.triu(z) + np.triu(z, 1).transpose(0, 2, 1)
+    idx = np.arange(n_ao)
+    loc = np.exp(-np.abs(idx[:, None] - idx[None, :]) / 4.0)
+    B = B * loc[None] * np.exp(-decay * np.arange(n_aux))[:, None, None] / np.sqrt(n_ao)
+    a, b = pair_index(n_ao)
+    Bp = B[:, a, b]                       # [P][pair]
+    return Bp.T @ Bp, B
+
+
+def gen_mo_coefficients(n_ao: int, n_mo: int, seed: int):
+    """Orthonormal MO coefficients C [n_ao][n_mo] (a random orthogonal matrix's
+    first n_mo columns) whose orbitals are localized on a band of AOs."""
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n_ao, n_mo))
+    idx = np.arange(n_ao)[:, None]
+    centers = np.linspace(0, n_ao - 1, n_mo)[None, :]
+    X = X * np.exp(-np.abs(idx - centers) / (0.25 * n_ao))
+    Q, _ = np.linalg.qr(X)
+    return Q
