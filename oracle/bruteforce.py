@@ -155,8 +155,8 @@ def expm_nilpotent_apply(X, vec, sign=1.0):
 
 
 class BruteForce:
-    """Residuals, energies and Jacobians of CCS, MLCC2 and MLCCSD from their
-    definitions on explicit determinant vectors."""
+    """Residuals, energies and Jacobians of CCS, MLCC2, MLCCSD and three-level
+    MLCCSD from their definitions on explicit determinant vectors."""
 
     def __init__(self, h, g, eps, O, o, v):
         self.n = h.shape[0]
@@ -207,6 +207,43 @@ class BruteForce:
         vec = self.sim(T1, lambda w: self.H @ w) + self.F @ (S2 @ self.hf) - S2 @ (self.F @ self.hf)
         _, om2 = self.S.project(vec)
         return om1, self._act(om2)
+
+    def _ccsd_rows(self, o_t, v_t):
+        """(v,o,v,o) selector of the projections inside the CCSD space of the
+        three-level model: a < v_t, i < o_t, b < v_t and j < o_t."""
+        a = np.arange(self.v)[:, None, None, None]
+        i = np.arange(self.o)[None, :, None, None]
+        b = np.arange(self.v)[None, None, :, None]
+        j = np.arange(self.o)[None, None, None, :]
+        return (a < v_t) & (i < o_t) & (b < v_t) & (j < o_t)
+
+    def omega_mlccsd3(self, t1, x2, o_t, v_t):
+        """Three-level MLCCSD (X = X1 + S2 + T2, x2 = S2 + T2 over the active
+        space): singles and the doubles inside the CCSD space project
+        exp(-X) H exp(X)|HF>; the other active doubles project
+        H~|HF> + [F, X2]|HF>."""
+        T1 = self.S.t1_op(t1)
+        X2 = self.S.t2_op(x2, self.o, self.v)
+        om1, full = self.S.project(self.sim(T1 + X2, lambda w: self.H @ w))
+        vec = self.sim(T1, lambda w: self.H @ w) + self.F @ (X2 @ self.hf) - X2 @ (self.F @ self.hf)
+        _, cc2 = self.S.project(vec)
+        return om1, np.where(self._ccsd_rows(o_t, v_t), self._act(full), self._act(cc2))
+
+    def jacobian_mlccsd3(self, t1, x2, c1, c2, o_t, v_t):
+        """Derivative of omega_mlccsd3 along (c1, c2), from commutators:
+        singles and CCSD-space rows <mu| exp(-X)[H, tau(c)]exp(X) |HF>, the
+        other rows <mu2| exp(-T1)[H, tau(c1)]exp(T1) + [F, tau(c2)] |HF>."""
+        T1 = self.S.t1_op(t1)
+        X2 = self.S.t2_op(x2, self.o, self.v)
+        tau = self._tau(c1, c2)
+        comm = lambda w: self.H @ (tau @ w) - tau @ (self.H @ w)  # noqa: E731
+        s1, full = self.S.project(self.sim(T1 + X2, comm))
+        tau1 = self.S.t1_op(c1)
+        comm1 = lambda w: self.H @ (tau1 @ w) - tau1 @ (self.H @ w)  # noqa: E731
+        tau2 = self.S.t2_op(c2, self.o, self.v)
+        vec = self.sim(T1, comm1) + self.F @ (tau2 @ self.hf) - tau2 @ (self.F @ self.hf)
+        _, cc2 = self.S.project(vec)
+        return s1, np.where(self._ccsd_rows(o_t, v_t), self._act(full), self._act(cc2))
 
     def _tau(self, c1, c2):
         op = self.S.t1_op(c1)

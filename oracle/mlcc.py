@@ -300,6 +300,42 @@ def mlccsd_omega(L, eps, d: Dims, t1, t2, h=None):
     return om1, om2
 
 
+def ccsd_space_mask(d: Dims, o_t, v_t):
+    """True at the doubles (a, i, b, j) whose four indices all lie in the
+    CCSD space: the first v_t active virtuals and the first o_t active
+    occupied orbitals (nested prefixes of the CC2 space)."""
+    pair = (np.arange(d.v)[:, None] < v_t) & (np.arange(d.o)[None, :] < o_t)
+    return pair[:, :, None, None] & pair[None, None, :, :]
+
+
+def mlccsd3_omega(L, eps, d: Dims, o_t, v_t, t1, x2, h=None):
+    """Three-level MLCCSD (CCS/CC2/CCSD) residual, Sec. 2.1 (X = X1 + S2 + T2,
+    S2 in the larger active space and perturbative, T2 in the smaller one and
+    a correction to S2).  The paper prints no equations for this model; the
+    reading used here:
+
+    * x2 holds the doubles over the CC2 space (d.o, d.v): S2 + T2, where T2
+      lives only on the CCSD space;
+    * singles and the doubles projections inside the CCSD space are those of
+      the full similarity transform exp(-X) H exp(X) (CCSD level, including
+      every coupling to the S2 amplitudes outside it);
+    * the remaining doubles projections of the CC2 space keep the CC2 form
+      <mu2| H~ + [F, X2] |HF> = g~_aibj + eps_aibj x_aibj.
+
+    Inside the CCSD space the model reaches CCSD, outside it MLCC2; with an
+    empty CCSD space it is MLCC2, and with the CCSD space equal to the CC2
+    space it is MLCCSD (CCS/CCSD)."""
+    D = dress(L, eps, d, t1, h)
+    om1 = omega_singles(D, d, x2)
+    if d.M == 0:
+        return om1, None
+    om2 = g_aibj(D.Lt, d) + orbital_denominators(eps, d) * x2
+    inner = ccsd_space_mask(d, o_t, v_t)
+    if inner.any():
+        om2 = np.where(inner, ccsd_doubles(D, d, x2), om2)
+    return om1, om2
+
+
 def ccs_omega(L, eps, d: Dims, t1, h=None):
     D = dress(L, eps, d, t1, h)
     return D.Ft[d.vir, d.occ].copy()
@@ -333,15 +369,16 @@ def mp2_energy(L, eps, d: Dims):
 # Ground state: DIIS-accelerated quasi-Newton (Sec. 2.1)
 # --------------------------------------------------------------------------
 
-MODELS = ("ccs", "mlcc2", "mlccsd")
+MODELS = ("ccs", "mlcc2", "mlccsd", "mlccsd3")
 
 
 class Problem:
     """Inputs plus the model; caches h.  fock: the full Fock matrix when the
     basis is semicanonical rather than canonical (eps is then its diagonal,
-    which the denominators use)."""
+    which the denominators use).  mlccsd3: d's active space is the CC2 space
+    and ccsd_space = (o_t, v_t) the CCSD space inside it."""
 
-    def __init__(self, L, eps, d: Dims, model: str, fock=None):
+    def __init__(self, L, eps, d: Dims, model: str, fock=None, ccsd_space=None):
         assert model in MODELS
         self.L = np.asarray(L, dtype=np.float64)
         self.eps = np.asarray(eps, dtype=np.float64)
@@ -349,7 +386,17 @@ class Problem:
         self.model = model
         if model == "ccs":
             self.d = Dims(d.O, d.V, 0, 0)
+        if model == "mlccsd3":
+            o_t, v_t = ccsd_space
+            assert 0 <= o_t <= d.o and 0 <= v_t <= d.v
+            self.ccsd_space = (o_t, v_t)
         self.h = core_hamiltonian(self.L, self.eps, self.d, fock=fock)
+
+    @property
+    def iterated_doubles(self):
+        """Doubles solved by the quasi-Newton/DIIS iteration (MLCCSD models);
+        MLCC2 solves them analytically instead."""
+        return self.model in ("mlccsd", "mlccsd3")
 
     # residual in the independent variables (t1, x2)
     def omega(self, t1, x2):
@@ -359,6 +406,8 @@ class Problem:
             return D.Ft[d.vir, d.occ].copy(), None
         if self.model == "mlcc2":
             return mlcc2_omega(self.L, self.eps, d, t1, x2, self.h)
+        if self.model == "mlccsd3":
+            return mlccsd3_omega(self.L, self.eps, d, *self.ccsd_space, t1, x2, self.h)
         return mlccsd_omega(self.L, self.eps, d, t1, x2, self.h)
 
     def s_analytic(self, t1):
@@ -384,14 +433,16 @@ def _diis_extrapolate(xs, es):
 def ground_state(P: Problem, tol=1e-10, max_iter=200, diis_dim=8, t1_guess=None):
     """Solve Omega = 0.  MLCC2: s is re-solved analytically each iteration and
     DIIS acts on t1; MLCCSD: DIIS on (t1, t2).  Quasi-Newton step
-    dx = -Omega / (eps_A - eps_I)  (and / eps_aibj for t2).
+    dx = -Omega / (eps_A - eps_I)  (and / eps_aibj for t2).  Three-level
+    MLCCSD iterates all its doubles the same way: on the CC2-level entries
+    the step lands on the analytic -g~/eps at once.
 
     Returns dict(t1, x2, energy, iterations, converged, history)."""
     d = P.d
     dai = singles_denominators(P.eps, d)
     daibj = orbital_denominators(P.eps, d) if d.M > 0 else None
     t1 = np.zeros((d.V, d.O)) if t1_guess is None else np.array(t1_guess, float)
-    t2 = np.zeros((d.v, d.o, d.v, d.o)) if (P.model == "mlccsd" and d.M > 0) else None
+    t2 = np.zeros((d.v, d.o, d.v, d.o)) if (P.iterated_doubles and d.M > 0) else None
     xs, es, hist = [], [], []
     converged = False
     E = None
@@ -409,7 +460,7 @@ def ground_state(P: Problem, tol=1e-10, max_iter=200, diis_dim=8, t1_guess=None)
             converged = True
             break
         t1n = t1 - om1 / dai
-        if P.model == "mlccsd" and om2 is not None:
+        if P.iterated_doubles and om2 is not None:
             t2n = t2 - om2 / daibj
             vec = np.concatenate([t1n.ravel(), t2n.ravel()])
             err = np.concatenate([om1.ravel(), om2.ravel()])
@@ -422,7 +473,7 @@ def ground_state(P: Problem, tol=1e-10, max_iter=200, diis_dim=8, t1_guess=None)
             es.pop(0)
         vec = _diis_extrapolate(xs, es)
         t1 = vec[: d.V * d.O].reshape(d.V, d.O)
-        if P.model == "mlccsd" and om2 is not None:
+        if P.iterated_doubles and om2 is not None:
             t2 = vec[d.V * d.O:].reshape(d.v, d.o, d.v, d.o)
     x2 = P.s_analytic(t1) if (P.model == "mlcc2" and d.M > 0) else t2
     return dict(t1=t1, x2=x2, energy=E, iterations=it, converged=converged,
