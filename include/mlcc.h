@@ -72,6 +72,18 @@ typedef int32_t mlcc_status;
 #define MLCC_CCS 0     /* X = X1 */
 #define MLCC_MLCC2 1   /* X = X1 + S2, S2 in the active space, perturbative */
 #define MLCC_MLCCSD 2  /* CCS/CCSD: X = X1 + T2, T2 in the active space */
+/* CCS/CC2/CCSD: X = X1 + S2 + T2 with S2 in the active space and T2 in the
+ * CCSD space (n_occ_ccsd, n_vir_ccsd prefixes of the active space), Sec. 2.1.
+ * The paper gives the cluster operator but no equations for this model; the
+ * library's reading: the doubles x = S2 + T2 span the active space; the
+ * singles and the doubles projections with all four indices in the CCSD
+ * space are those of exp(-X) H exp(X) (CCSD level, coupled to every
+ * amplitude of the active space), the other doubles projections keep the
+ * CC2 form g~_aibj + eps_aibj x_aibj.  Doubles arrays, excitation vectors
+ * and the ground-state and Davidson drivers are those of MLCC_MLCCSD over
+ * the active space.  n_occ_ccsd = n_occ_act and n_vir_ccsd = n_vir_act give
+ * MLCC_MLCCSD; an empty CCSD space gives MLCC2 with iterated doubles. */
+#define MLCC_MLCCSD3 3
 
 /* Arithmetic of the Cholesky-index contractions (the MFMA GEMMs).  Amplitude
  * and denominator updates, DIIS, Davidson and energies are FP64 always. */
@@ -90,7 +102,7 @@ typedef struct mlcc_server mlcc_server;
 typedef struct {
   int32_t n_occ, n_vir, n_chol;   /* N_o, N_v, N_J */
   int32_t n_occ_act, n_vir_act;   /* active prefixes (ignored for MLCC_CCS) */
-  int32_t model;                  /* MLCC_CCS | MLCC_MLCC2 | MLCC_MLCCSD */
+  int32_t model;                  /* MLCC_CCS | MLCC_MLCC2 | MLCC_MLCCSD | MLCC_MLCCSD3 */
   int32_t precision;              /* MLCC_FP64 | MLCC_FP32 | MLCC_BF16X3 */
   const double *L;                /* [n_chol][n][n], symmetric in the last two */
   const double *eps;              /* [n] orbital energies in the order above */
@@ -103,6 +115,10 @@ typedef struct {
                                      mlcc_cnto returns it); eps must be its diagonal,
                                      which the denominators use.  The occupied-virtual
                                      block must vanish (a Hartree-Fock reference). */
+  int32_t n_occ_ccsd, n_vir_ccsd; /* MLCC_MLCCSD3: the CCSD space, prefixes of the
+                                     active space (0 <= n_occ_ccsd <= n_occ_act,
+                                     0 <= n_vir_ccsd <= n_vir_act); ignored by the
+                                     other models */
 } mlcc_problem_desc;
 
 /* flags: L is not read; the library draws synthetic Cholesky vectors on the

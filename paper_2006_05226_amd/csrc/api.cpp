@@ -54,8 +54,13 @@ void check_desc(const mlcc_problem_desc *d) {
   MLCC_REQUIRE((d->flags & ~MLCC_SYNTH_L) == 0, MLCC_E_ARG, "unknown flags");
   MLCC_REQUIRE(d->n_occ >= 1 && d->n_vir >= 1 && d->n_chol >= 1, MLCC_E_ARG,
                "n_occ, n_vir and n_chol must be >= 1");
-  MLCC_REQUIRE(d->model == MLCC_CCS || d->model == MLCC_MLCC2 || d->model == MLCC_MLCCSD,
+  MLCC_REQUIRE(d->model == MLCC_CCS || d->model == MLCC_MLCC2 || d->model == MLCC_MLCCSD ||
+                   d->model == MLCC_MLCCSD3,
                MLCC_E_ARG, "unknown model");
+  if (d->model == MLCC_MLCCSD3)
+    MLCC_REQUIRE(d->n_occ_ccsd >= 0 && d->n_occ_ccsd <= d->n_occ_act && d->n_vir_ccsd >= 0 &&
+                     d->n_vir_ccsd <= d->n_vir_act,
+                 MLCC_E_ARG, "CCSD space not inside the active space");
   MLCC_REQUIRE(d->precision == MLCC_FP64 || d->precision == MLCC_FP32 ||
                    d->precision == MLCC_BF16X3,
                MLCC_E_ARG, "unknown precision");
@@ -352,9 +357,18 @@ mlcc_status mlcc_davidson_solve(mlcc_problem *P, int32_t n_roots, const mlcc_sol
       const int64_t dim = P->dim();
       const int64_t M = P->has_doubles() ? P->d.M : 0;
       const int64_t n1 = P->d.n1;
-      auto apply = [&](int n, const double *in, double *out) { P->transform(n, in, out); };
+      // The doubles live in the subspace symmetric under (ai) <-> (bj); the
+      // transformed vectors and the new directions are projected onto it, so
+      // that rounding-level asymmetry cannot pull the iteration towards the
+      // (unphysical) antisymmetric part of the operator, whose eigenvalues
+      // can lie below the physical roots.
+      auto apply = [&](int n, const double *in, double *out) {
+        P->transform(n, in, out);
+        k::symmetrize(ex, M, out + n1, n, dim);
+      };
       auto pre = [&](double wr, const double *r, double *o) {
         k::precond(ex, n1, M, eps_vo, eps_ai, wr, r, o);
+        k::symmetrize(ex, M, o + n1, 1, dim);
       };
       DavidsonResult dr = davidson(ex, &P->ctx->al, dim, n_roots, n_guess, max_space, max_iter,
                                    opts->tol, gidx, apply, pre, nullptr, 0, 0, 0.0);

@@ -30,6 +30,15 @@
 // ladder contracts (c, d) as (r, k) with rows (a, b) and columns (i, j)).
 // Doubles arrays are [M][M] with pair index a*o + i: strides a: o*M, i: M,
 // b: o, j: 1.
+//
+// Three-level MLCCSD (CCS/CC2/CCSD) uses the same terms with their output
+// restricted to the CCSD space (a, b < vt; i, j < ot) while every summation
+// index runs over the whole active space: the output row and column counts
+// of each call shrink (rows (a, i) become two-level (a < vt, i < ot); terms
+// over three output indices take the leading one as a batch index), and the
+// ladder integrals are kept only for a, b < vt, g_vvvv[(a,c)][(b,d)] with
+// leading dimension vt*v.  The remaining entries are then overwritten with
+// their CC2-level values g~ + eps x (k::cc2_rows).
 
 namespace mlcc {
 struct CcsdState {
@@ -75,7 +84,8 @@ template <typename T> void mlcc_problem::ccsd_integrals_t() {
   s.g_ovov.ensure(al, M * M * sizeof(T));
   s.g_oovv.ensure(al, o * o * v * v * sizeof(T));
   s.g_voov.ensure(al, M * M * sizeof(T));
-  s.g_vvvv.ensure(al, v * v * v * v * sizeof(T));
+  const int64_t vt = d.vt;
+  s.g_vvvv.ensure(al, vt * v * vt * v * sizeof(T));
   G(M, M, J).A(Lvo, 1, M).B(Lvo, M, 1).C(s.g_vovo.p, M, 1).tag("cc_g").run(x, p, o64);
   G(o * o, o * o, J).A(s.Loo.p, 1, o * o).B(s.Loo.p, o * o, 1).C(s.g_oooo.p, o * o, 1)
       .tag("cc_g").run(x, p, o64);
@@ -84,7 +94,8 @@ template <typename T> void mlcc_problem::ccsd_integrals_t() {
   G(o * o, v * v, J).A(s.Loo.p, 1, o * o).B(s.Lvv.p, v * v, 1).C(s.g_oovv.p, v * v, 1)
       .tag("cc_g").run(x, p, o64);
   G(M, M, J).A(Lvo, 1, M).B(s.Lkc.p, M, 1).C(s.g_voov.p, M, 1).tag("cc_g").run(x, p, o64);
-  G(v * v, v * v, J).A(s.Lvv.p, 1, v * v).B(s.Lvv.p, v * v, 1).C(s.g_vvvv.p, v * v, 1)
+  // g_vvvv[(a,c)][(b,d)] = g~_acbd for a, b in the CCSD space (a prefix of the pair order)
+  G(vt * v, vt * v, J).A(s.Lvv.p, 1, v * v).B(s.Lvv.p, v * v, 1).C(s.g_vvvv.p, vt * v, 1)
       .tag("cc_g_vvvv").run(x, p, o64);
   // gX[(c,k)][(d,l)] = g_kdlc = g_ovov[(k,d)][(l,c)], the C2 integral with
   // its reduction pair (d,l) contiguous (symmetric under (c,k) <-> (d,l))
@@ -113,7 +124,8 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
   Exec &x = *ex;
   Alloc *al = &ctx->al;
   CcsdState &s = *cc;
-  const int64_t o = d.o, v = d.v, M = d.M;
+  const int64_t o = d.o, v = d.v, M = d.M, ot = d.ot, vt = d.vt, Mt = ot * vt;
+  const bool full = !d.cc2_rows();  // output over the whole active space
   const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;
   if (!blk[CB_OVOV]) incQ = false;
@@ -123,6 +135,7 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
     const int64_t nn[4] = {1, 1, M, M}, ss[4] = {0, 0, M, 1};
     k::permute4<double, T>(x, sym, static_cast<const T *>(blk[CB_VOVO]), nn, ss, 1.0, 1.0);
   }
+  if (Mt == 0) return;  // no CCSD-level projection
   // tL[c][i][j][d] = tA_cidj: the ladder and E2 reduce over its contiguous d
   if ((ladder && incB) || any) {
     const int64_t nn[4] = {v, o, o, v}, sl[4] = {o * M, M, 1, o};
@@ -130,9 +143,9 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
     k::permute4<T, T>(x, off<T>(s.tL), static_cast<const T *>(tA), nn, sl, 1.0, 0.0);
   }
   if (ladder && incB) {
-    G(v * v, o * o, v, v).A(blk[CB_VVVV], v, 1, v * v).Mhi(v, v * v * v, o * M)
-        .B(s.tL.p, 1, v, o * o * v).Nhi(o, o * v, M).C(sym, o, 1, 0, 1.0, 1.0).tag("cc_ladder")
-        .run(x, p, true);
+    G(vt * vt, ot * ot, v, v).A(blk[CB_VVVV], v, 1, vt * v).Mhi(vt, v * vt * v, o * M)
+        .B(s.tL.p, 1, v, o * o * v).Nhi(ot, o * v, M).C(sym, o, 1, 0, 1.0, 1.0)
+        .tag("cc_ladder").run(x, p, true);
   }
   if (!any) return;
   // --- B2: Q[k][l][i][j] = g_kilj + sum_cd tB_cidj g_kcld ; sym += sum_kl tA_akbl Q_klij
@@ -143,11 +156,11 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
                       incB ? 1.0 : 0.0, 0.0);
   }
   if (incQ)
-    G(o * o, o * o, v, v).A(blk[CB_OVOV], v, 1, M).Mhi(o, v * M, o * o * o)
-        .B(tB, o, 1, o * M).Nhi(o, M, o).C(s.Q.p, o * o, 1, 0, 1.0, 1.0).tag("cc_B2")
+    G(o * o, ot * ot, v, v).A(blk[CB_OVOV], v, 1, M).Mhi(o, v * M, o * o * o)
+        .B(tB, o, 1, o * M).Nhi(ot, M, o).C(s.Q.p, o * o, 1, 0, 1.0, 1.0).tag("cc_B2")
         .run(x, p, o64);
-  G(v * v, o * o, o, o).A(tA, o, 1, M).Mhi(v, o * M, o * M).B(s.Q.p, o * o, 1, o * o * o)
-      .Nhi(o, o, M).C(sym, o, 1, 0, 1.0, 1.0).tag("cc_B2").run(x, p, true);
+  G(vt * vt, ot * ot, o, o).A(tA, o, 1, M).Mhi(vt, o * M, o * M).B(s.Q.p, o * o, 1, o * o * o)
+      .Nhi(ot, o, M).C(sym, o, 1, 0, 1.0, 1.0).tag("cc_B2").run(x, p, true);
   // --- C2: Y[(a,i)][(c,k)] = g_kiac - 1/2 sum_dl tB_aldi g_kdlc ;
   //         X[(a,i)][(b,j)] = sum_ck Y[(a,i)][(c,k)] tA_bkcj ; R += -1/2 X - X(i<->j)
   // Both sums run over one contiguous pair index through the occupied-
@@ -172,11 +185,14 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
         k::permute4<T, T>(x, off<T>(s.xB), static_cast<const T *>(tB), nn, sx, 1.0, 0.0);
         xB = s.xB.p;
       }
-      G(M, M, M).A(xB, M, 1).B(s.gX.p, 1, M).C(s.Y.p, M, 1, 0, -0.5, 1.0).tag("cc_C2")
-          .run(x, p, o64);
+      // rows (a, i) of the CCSD space: two-level (a, i < ot)
+      G(Mt, M, M).A(xB, M, 1).Mhi(ot, o * M, o * M).B(s.gX.p, 1, M)
+          .C(s.Y.p, M, 1, 0, -0.5, 1.0).tag("cc_C2").run(x, p, o64);
     }
   }
-  G(M, M, M).A(s.Y.p, M, 1).B(s.xA.p, 1, M).C(s.X.p, M, 1).tag("cc_C2").run(x, p, true);
+  if (!full) k::fill(x, s.X.as<double>(), M * M, 0.0);
+  G(Mt, Mt, M).A(s.Y.p, M, 1).Mhi(ot, o * M, o * M).B(s.xA.p, 1, M).Nhi(ot, o * M, o)
+      .C(s.X.p, M, 1).tag("cc_C2").run(x, p, true);
   {
     const int64_t nn[4] = {v, o, v, o};
     const int64_t sx[4] = {o * M, 1, o, M}, sid[4] = {o * M, M, o, 1};
@@ -202,10 +218,11 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
     const int64_t s1[4] = {M, v * M, 1, v}, s2[4] = {1, v * M, M, v};
     k::permute4<T, T>(x, off<T>(s.Lld), static_cast<const T *>(blk[CB_OVOV]), nn, s1, 2.0, 0.0);
     k::permute4<T, T>(x, off<T>(s.Lld), static_cast<const T *>(blk[CB_OVOV]), nn, s2, -1.0, 1.0);
-    G(M, M, M).A(uB, M, 1).B(s.Lld.p, 1, M).C(s.Z.p, M, 1, 0, 0.5, 1.0).tag("cc_D2")
-        .run(x, p, o64);
+    G(Mt, M, M).A(uB, M, 1).Mhi(ot, o * M, o * M).B(s.Lld.p, 1, M)
+        .C(s.Z.p, M, 1, 0, 0.5, 1.0).tag("cc_D2").run(x, p, o64);
   }
-  G(M, M, M).A(s.Z.p, M, 1).B(uA, 1, M).C(R, M, 1, 0, 0.5, 1.0).tag("cc_D2").run(x, p, true);
+  G(Mt, Mt, M).A(s.Z.p, M, 1).Mhi(ot, o * M, o * M).B(uA, 1, M).Nhi(ot, o * M, o)
+      .C(R, M, 1, 0, 0.5, 1.0).tag("cc_D2").run(x, p, true);
   // --- E2: Wvv = F_bc - sum uB_bkdl g_ldkc, Woo = F_kj + sum uB_cldj g_kdlc
   s.Wvv.ensure(al, v * v * sizeof(T));
   s.Woo.ensure(al, o * o * sizeof(T));
@@ -224,16 +241,26 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
     const int64_t nn3[4] = {v, o, v, o}, s3[4] = {1, v, M, v * M};   // g3[c][l][d][k]
     k::permute4<T, T>(x, off<T>(s.g2), static_cast<const T *>(blk[CB_OVOV]), nn2, s2, 1.0, 0.0);
     k::permute4<T, T>(x, off<T>(s.g3), static_cast<const T *>(blk[CB_OVOV]), nn3, s3, 1.0, 0.0);
-    G(v, v, o * M).A(uB, o * M, 1).B(s.g2.p, 1, o * M).C(s.Wvv.p, v, 1, 0, -1.0, 1.0)
+    // Wvv rows b and Woo columns j of the CCSD space (prefixes)
+    G(vt, v, o * M).A(uB, o * M, 1).B(s.g2.p, 1, o * M).C(s.Wvv.p, v, 1, 0, -1.0, 1.0)
         .tag("cc_E2").run(x, p, o64);
-    G(o, o, v * o * v).A(s.g3.p, 1, o).B(uB, o, 1).C(s.Woo.p, o, 1, 0, 1.0, 1.0).tag("cc_E2")
-        .run(x, p, o64);
+    G(o, ot, v * o * v).A(s.g3.p, 1, o).B(uB, o, 1).C(s.Woo.p, o, 1, 0, 1.0, 1.0)
+        .tag("cc_E2").run(x, p, o64);
   }
-  // rows (a,i,j) of tL: R[(a,i)][(b,j)] += sum_c tA_aicj Wvv[b][c]
-  G(M * o, v, v).A(s.tL.p, v, 1).Mhi(o, o * v, M).B(s.Wvv.p, 1, v).C(R, 1, o, 0, 1.0, 1.0)
-      .tag("cc_E2").run(x, p, true);
-  G(M * v, o, o).A(tA, o, 1).B(s.Woo.p, o, 1).C(R, o, 1, 0, -1.0, 1.0).tag("cc_E2")
-      .run(x, p, true);
+  if (full) {
+    // rows (a,i,j) of tL: R[(a,i)][(b,j)] += sum_c tA_aicj Wvv[b][c]
+    G(M * o, v, v).A(s.tL.p, v, 1).Mhi(o, o * v, M).B(s.Wvv.p, 1, v).C(R, 1, o, 0, 1.0, 1.0)
+        .tag("cc_E2").run(x, p, true);
+    G(M * v, o, o).A(tA, o, 1).B(s.Woo.p, o, 1).C(R, o, 1, 0, -1.0, 1.0).tag("cc_E2")
+        .run(x, p, true);
+  } else {
+    // the same over the CCSD space, batched over a: rows (i, j) x columns b,
+    // then rows (i, b) x columns j
+    G(ot * ot, vt, v, 1, vt).A(s.tL.p, v, 1, 0, o * o * v).Mhi(ot, o * v, M)
+        .B(s.Wvv.p, 1, v).C(R, 1, o, o * M, 1.0, 1.0).tag("cc_E2").run(x, p, true);
+    G(ot * vt, ot, o, 1, vt).A(tA, o, 1, 0, o * M).Mhi(vt, M, M).B(s.Woo.p, o, 1)
+        .C(R, o, 1, o * M, -1.0, 1.0).tag("cc_E2").run(x, p, true);
+  }
 }
 
 template <typename T> void mlcc_problem::ccsd_omega2_t() {
@@ -252,6 +279,10 @@ template <typename T> void mlcc_problem::ccsd_omega2_t() {
                            s.g_voov.p, s.g_vvvv.p, s.Fvv.p,    s.Foo.p};
   ccsd_terms_t<T>(blk, s.tT.p, u.p, s.tT.p, u.p, true, true, true, true, om2, s.Rb.as<double>());
   k::sym_accum(x, M, s.Rb.as<double>(), om2);
+  // three-level: CC2-level projections outside the CCSD space, g~ + eps x
+  if (d.cc2_rows())
+    k::cc2_rows<T>(x, M, d.o, d.ot, d.vt, off<T>(s.g_vovo), M, false, eps_ai.as<double>(), x2(),
+                   M, om2);
 }
 
 // Jacobian intermediate for the ladder-integral derivative:
@@ -261,12 +292,15 @@ template <typename T> void mlcc_problem::ccsd_prepare_t() {
   Alloc *al = &ctx->al;
   CcsdState &s = *cc;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, o = d.o, v = d.v, M = d.M;
+  const int64_t ot = d.ot, vt = d.vt;
   const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;
+  if (ot * vt == 0) return;  // no CCSD-level projection
   s.LKc.ensure(al, J * O * v * sizeof(T));
   k::pack2d<T, T>(x, off<T>(s.LKc), off<T>(Lt, O), J, n2, O, v, n);
-  s.Gk.ensure(al, (size_t)O * v * v * v * sizeof(T));
-  G(O * v, v * v, J).A(s.LKc.p, 1, O * v).B(s.Lvv.p, v * v, 1).C(s.Gk.p, v * v, 1)
+  // Gk[(K,c)][(b,d)] for b in the CCSD space (leading dimension vt*v)
+  s.Gk.ensure(al, (size_t)O * v * vt * v * sizeof(T));
+  G(O * v, vt * v, J).A(s.LKc.p, 1, O * v).B(s.Lvv.p, v * v, 1).C(s.Gk.p, vt * v, 1)
       .tag("cc_Gk").run(x, p, o64);
   s.Y3.ensure(al, (size_t)O * o * M * sizeof(T));
   {
@@ -274,8 +308,9 @@ template <typename T> void mlcc_problem::ccsd_prepare_t() {
     s.tL.ensure(al, M * M * sizeof(T));
     k::permute4<T, T>(x, off<T>(s.tL), off<T>(s.tT), nn, sl, 1.0, 0.0);
   }
-  G(O * v, o * o, v, v).A(s.Gk.p, v, 1, v * v).Mhi(v, v * v * v, o * M)
-      .B(s.tL.p, 1, v, o * o * v).Nhi(o, o * v, M).C(s.Y3.p, o, 1).tag("cc_Y3").run(x, p, o64);
+  // Y3[K][i][b][j] for i, j < ot and b < vt
+  G(O * vt, ot * ot, v, v).A(s.Gk.p, v, 1, vt * v).Mhi(vt, v * vt * v, o * M)
+      .B(s.tL.p, 1, v, o * o * v).Nhi(ot, o * v, M).C(s.Y3.p, o, 1).tag("cc_Y3").run(x, p, o64);
   s.Gk.release();
 }
 
@@ -358,8 +393,12 @@ void mlcc_problem::ccsd_sigma2_t(const double *c1, const double *c2, const doubl
   k::sym_plus_diag<double>(x, M, Gv, ldg, eps_ai.as<double>(), nullptr, s2);
   k::fill(x, Rp, M * M, 0.0);
   // ladder-integral derivative: R += -sum_K c_aK Y3[K][i][b][j]
-  G(v, o * M, O).A(c1t, O, 1).B(s.Y3.p, o * M, 1).C(Rp, o * M, 1, 0, -1.0, 1.0)
-      .tag("cc_Y3c").run(x, p, true);
+  if (!d.cc2_rows())
+    G(v, o * M, O).A(c1t, O, 1).B(s.Y3.p, o * M, 1).C(Rp, o * M, 1, 0, -1.0, 1.0)
+        .tag("cc_Y3c").run(x, p, true);
+  else  // over the CCSD space, batched over i: rows a x columns (b, j)
+    G(d.vt, (int64_t)d.vt * d.ot, O, 1, d.ot).A(c1t, O, 1, 0, 0).B(s.Y3.p, o * M, 1, 0, M)
+        .Nhi(d.ot, o, o).C(Rp, o * M, 1, M, -1.0, 1.0).tag("cc_Y3c").run(x, p, true);
   const void *dblk[CB_N] = {nullptr, s.dg_oooo.p, nullptr, s.dg_oovv.p,
                             s.dg_voov.p, nullptr, s.dFvv.p, s.dFoo.p};
   const void *blk[CB_N] = {s.g_vovo.p, s.g_oooo.p, s.g_ovov.p, s.g_oovv.p,
@@ -371,4 +410,7 @@ void mlcc_problem::ccsd_sigma2_t(const double *c1, const double *c2, const doubl
   // (g, F; t, c2): terms with two amplitudes, the second replaced
   ccsd_terms_t<T>(blk, s.tT.p, u.p, s.c2T.p, s.cu2.p, false, false, true, false, s2, Rp);
   k::sym_accum(x, M, Rp, s2);
+  // three-level: CC2-level rows outside the CCSD space, dg~ + eps c2
+  if (d.cc2_rows())
+    k::cc2_rows<double>(x, M, d.o, d.ot, d.vt, Gv, ldg, true, eps_ai.as<double>(), c2, M, s2);
 }

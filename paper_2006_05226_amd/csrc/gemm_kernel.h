@@ -36,7 +36,8 @@
 //   result is deterministic.
 // * One-dimensional grid, remapped so that each XCD (consecutive workgroup
 //   ids go round-robin over the 8 XCDs) receives a contiguous range of output
-//   tiles, which share operand rows in that XCD's L2.
+//   tiles, ordered in bands of 8 tile rows (tile_of), so that the blocks
+//   resident on an XCD together share operand panels in its L2.
 #pragma once
 
 #include <algorithm>
@@ -379,6 +380,23 @@ __device__ __forceinline__ void epilogue(const KParams &kp, const Acc4 (&acc)[FM
   }
 }
 
+// Output tile of work item w: (batch, split) planes outermost; inside a plane
+// the tiles go in bands of kGroupM tile rows, column by column within a band,
+// so that the blocks resident on one XCD at a time (a contiguous range of w)
+// share a few A row panels and a few B column panels in that XCD's L2.
+constexpr int64_t kGroupM = 8;
+__device__ __forceinline__ void tile_of(const KParams &kp, int64_t w, int64_t &tm, int64_t &tn,
+                                        int64_t &zs) {
+  const int64_t plane = (int64_t)kp.tiles_m * kp.tiles_n;
+  zs = w / plane;
+  const int64_t q = w - zs * plane, band = kGroupM * kp.tiles_n;
+  const int64_t grp = q / band, first = grp * kGroupM;
+  const int64_t gm = min(kGroupM, (int64_t)kp.tiles_m - first);
+  const int64_t r = q - grp * band;
+  tm = first + r % gm;
+  tn = r / gm;
+}
+
 template <typename T, typename TC, int BM, int BN, bool AKM, bool BKN, bool VONLY>
 __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm(KParams kp) {
   typedef WaveGrid<BM, BN> WG;
@@ -395,10 +413,8 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm(KParams kp) {
   const int64_t L = blockIdx.x;
   const int64_t w = (L % kXcd) * kp.per_xcd + L / kXcd;
   if (w >= kp.nwork) return;
-  const int64_t tn = w % kp.tiles_n;
-  const int64_t t2 = w / kp.tiles_n;
-  const int64_t tm = t2 % kp.tiles_m;
-  const int64_t zs = t2 / kp.tiles_m;
+  int64_t tm, tn, zs;
+  tile_of(kp, w, tm, tn, zs);
   const int64_t z = zs / kp.splits;
   const int split = (int)(zs % kp.splits);
 
@@ -562,10 +578,8 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams k
   const int64_t L = blockIdx.x;
   const int64_t w = (L % kXcd) * kp.per_xcd + L / kXcd;
   if (w >= kp.nwork) return;
-  const int64_t tn = w % kp.tiles_n;
-  const int64_t t2 = w / kp.tiles_n;
-  const int64_t tm = t2 % kp.tiles_m;
-  const int64_t zs = t2 / kp.tiles_m;
+  int64_t tm, tn, zs;
+  tile_of(kp, w, tm, tn, zs);
   const int64_t z = zs / kp.splits;
   const int split = (int)(zs % kp.splits);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;

@@ -245,6 +245,50 @@ __global__ void k_sym_plus_diag(int64_t M, const TG *G, int64_t ldg, const doubl
   }
 }
 
+// x <- (x + x^T) / 2 in place for nz M x M arrays at x + z*ld: each unordered
+// pair (p, q), p < q, belongs to one thread.
+__global__ void k_symmetrize(int64_t M, double *x, int nz, int64_t ld) {
+  const int64_t per = M * M, total = per * nz;
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+       t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t z = t / per, e = t - z * per, p = e / M, q = e - p * M;
+    if (p >= q) continue;
+    double *xz = x + z * ld;
+    const double a = 0.5 * (xz[p * M + q] + xz[q * M + p]);
+    xz[p * M + q] = a;
+    xz[q * M + p] = a;
+  }
+}
+
+// CC2-level rows of three-level MLCCSD: out[ai][bj] = G[ai][bj] (+ G[bj][ai]
+// when addT) + eps_aibj x[ai][bj] for every pair of pairs not both inside the
+// CCSD space (a < vt and i < ot; pair index a*o + i); the other entries are
+// left alone.  32x32 LDS tiles as in k_sym_plus_diag.
+template <typename TG>
+__global__ void k_cc2_rows(int64_t M, int o, int ot, int vt, const TG *G, int64_t ldg, int addT,
+                           const double *eps_ai, const double *x, int64_t ldx, double *out) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  if (addT) {
+    for (int y = ty; y < 32; y += 8) {
+      const int64_t rr = c0 + y, cc = r0 + tx;
+      tile[y][tx] = (rr < M && cc < M) ? (double)G[rr * ldg + cc] : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int64_t r = r0 + y, cc = c0 + tx;
+    if (r < M && cc < M) {
+      const bool rin = r / o < vt && r % o < ot, cin = cc / o < vt && cc % o < ot;
+      if (rin && cin) continue;
+      double v = (double)G[r * ldg + cc];
+      if (addT) v += tile[tx][y];
+      out[r * M + cc] = v + (eps_ai[r] + eps_ai[cc]) * x[r * ldx + cc];
+    }
+  }
+}
+
 template <typename TG, typename TO>
 __global__ void k_sym_div(int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
                           TO *out, int64_t sGz, int64_t ldo) {
@@ -518,6 +562,23 @@ void sym_plus_diag(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *
   MLCC_HIP(hipGetLastError());
 }
 
+void symmetrize(Exec &ex, int64_t M, double *x, int nz, int64_t ld) {
+  if (M == 0 || nz <= 0) return;
+  hipLaunchKernelGGL(k_symmetrize, dim3(blocks_for(M * M * nz)), dim3(TPB), 0, ex.stream, M, x,
+                     nz, ld);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TG>
+void cc2_rows(Exec &ex, int64_t M, int o, int ot, int vt, const TG *G, int64_t ldg, bool addT,
+              const double *eps_ai, const double *x, int64_t ldx, double *out) {
+  if (M == 0 || o <= 0) return;
+  dim3 grid((unsigned)((M + 31) / 32), (unsigned)((M + 31) / 32));
+  hipLaunchKernelGGL((k_cc2_rows<TG>), grid, dim3(256), 0, ex.stream, M, o, ot, vt, G, ldg,
+                     addT ? 1 : 0, eps_ai, x, ldx, out);
+  MLCC_HIP(hipGetLastError());
+}
+
 template <typename TG, typename TO>
 void sym_div(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,
              TO *out, int nz, int64_t sGz, int64_t ldo) {
@@ -638,6 +699,10 @@ template void sym_plus_diag<double>(Exec &, int64_t, const double *, int64_t, co
                                     const double *, double *, int, int64_t, int64_t, int64_t);
 template void sym_plus_diag<float>(Exec &, int64_t, const float *, int64_t, const double *,
                                    const double *, double *, int, int64_t, int64_t, int64_t);
+template void cc2_rows<double>(Exec &, int64_t, int, int, int, const double *, int64_t, bool,
+                               const double *, const double *, int64_t, double *);
+template void cc2_rows<float>(Exec &, int64_t, int, int, int, const float *, int64_t, bool,
+                              const double *, const double *, int64_t, double *);
 template void sym_div<double, double>(Exec &, int64_t, const double *, int64_t, const double *,
                                       double, double *, int, int64_t, int64_t);
 template void sym_div<double, float>(Exec &, int64_t, const double *, int64_t, const double *,

@@ -208,6 +208,14 @@ template <typename TG>
 void sym_plus_diag(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai,
                    const double *c, double *out, int nz = 1, int64_t sGz = 0, int64_t ldc = 0,
                    int64_t ldo = 0);
+// x <- (x + x^T) / 2 in place, nz M x M arrays at x + z*ld
+void symmetrize(Exec &ex, int64_t M, double *x, int nz = 1, int64_t ld = 0);
+// CC2-level rows of three-level MLCCSD: out = G (+ G^T when addT) + d .* x on
+// the entries (ai, bj) with ai or bj outside the CCSD space (a < vt, i < ot);
+// the entries with both inside are not touched
+template <typename TG>
+void cc2_rows(Exec &ex, int64_t M, int o, int ot, int vt, const TG *G, int64_t ldg, bool addT,
+              const double *eps_ai, const double *x, int64_t ldx, double *out);
 // x[ai][bj] = (G + G^T)[ai][bj] / (w - eps_aibj)  (effective singles); nz arrays
 template <typename TG, typename TO>
 void sym_div(Exec &ex, int64_t M, const TG *G, int64_t ldg, const double *eps_ai, double w,

@@ -36,11 +36,16 @@
 namespace mlcc {
 
 // Occupied indices per pair block: nz blocks of (o_b v)^2 values in FP64 (two
-// buffers) and of u in the operand type (two buffers) within kPairBlockBytes.
+// buffers) and of u in the operand type (two buffers) within kPairBlockBytes,
+// balanced so that the blocks along the occupied index are of (nearly) equal
+// size rather than leaving a small last block.
 int pair_block_occ(int o, int v, int nz, int tsize) {
+  if (o <= 0) return 1;
   const double per = (double)nz * (16.0 + 2.0 * (double)tsize);
   const double rows = std::floor(std::sqrt(kPairBlockBytes / per));
-  return (int)std::max(1.0, std::min((double)o, std::floor(rows / std::max(v, 1))));
+  const int cap = (int)std::max(1.0, std::min((double)o, std::floor(rows / std::max(v, 1))));
+  const int blocks = (o + cap - 1) / cap;
+  return (o + blocks - 1) / blocks;
 }
 
 void *Alloc::get(size_t bytes) {
@@ -179,6 +184,15 @@ void mlcc_problem::setup(const mlcc_problem_desc &desc) {
   } else {
     d.o = desc.n_occ_act;
     d.v = desc.n_vir_act;
+  }
+  // three-level MLCCSD runs as MLCCSD over the active space whose CCSD-level
+  // doubles projections are restricted to the CCSD space (ot, vt)
+  d.ot = d.o;
+  d.vt = d.v;
+  if (model == MLCC_MLCCSD3) {
+    model = MLCC_MLCCSD;
+    d.ot = desc.n_occ_ccsd;
+    d.vt = desc.n_vir_ccsd;
   }
   d.M = (int64_t)d.o * d.v;
   d.n1 = (int64_t)d.O * d.V;

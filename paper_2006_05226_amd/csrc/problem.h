@@ -21,8 +21,13 @@ namespace mlcc {
 
 struct Dims {
   int O = 0, V = 0, n = 0, J = 0, o = 0, v = 0;
+  // CCSD space of three-level MLCCSD (prefixes of the active space); equal to
+  // (o, v) for the other models
+  int ot = 0, vt = 0;
   int64_t M = 0, n1 = 0, n2 = 0;  // pairs, singles, n*n
   int64_t dim_full() const { return n1 + M * M; }
+  // some active doubles are projected at the CC2 level (three-level MLCCSD)
+  bool cc2_rows() const { return ot < o || vt < v; }
 };
 
 // Builder for one GEMM-engine call.

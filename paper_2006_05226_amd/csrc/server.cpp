@@ -86,7 +86,10 @@ extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n
   const double M = o * v, MM = M * M;
   const double ts = d->precision == MLCC_FP64 ? 8.0 : 4.0;
   const double nL = J * n * n, n1 = O * V;
-  const bool mlcc2 = d->model == MLCC_MLCC2, ccsd = d->model == MLCC_MLCCSD;
+  const bool mlcc2 = d->model == MLCC_MLCC2;
+  const bool ccsd = d->model == MLCC_MLCCSD || d->model == MLCC_MLCCSD3;
+  // CCSD space of the ladder integrals (three-level MLCCSD: a prefix)
+  const double vt = d->model == MLCC_MLCCSD3 ? std::min<double>(d->n_vir_ccsd, v) : v;
   const bool eff = es && es->effective && mlcc2;
   const double dim = n1 + ((dbl && !eff) ? MM : 0.0);
   // trial vectors per Jacobian batch (the rule of the transformation)
@@ -110,7 +113,7 @@ extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n
   }
   if (ccsd && dbl) {
     run += MM * (8.0 * 2 + ts * 4) + MM * b * (ts + 8.0);  // t2, Omega_2, u, copies; G, u(c2)
-    run += (v * v * v * v + O * v * v * v + O * o * M) * ts + 16.0 * MM * ts;  // integral blocks
+    run += (vt * v * vt * v + O * v * vt * v + O * o * M) * ts + 16.0 * MM * ts;  // integral blocks
   }
   const double space = es && es->max_subspace > 0 ? es->max_subspace : 20.0 * n_roots;
   run += dim * 8.0 * (2.0 * space + 3.0 * (n_roots + 2));  // Davidson

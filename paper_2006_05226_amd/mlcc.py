@@ -18,9 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libmlcc.so")
 
 OK, PENDING = 0, 1
 E_ARG, E_OOM, E_NOCONV, E_NUMERIC, E_DEVICE, E_BUSY, E_STATE = -1, -2, -3, -4, -5, -6, -7
-CCS, MLCC2, MLCCSD = 0, 1, 2
+CCS, MLCC2, MLCCSD, MLCCSD3 = 0, 1, 2, 3
 FP64, FP32 = 0, 1
-MODEL = {"ccs": CCS, "mlcc2": MLCC2, "mlccsd": MLCCSD}
+MODEL = {"ccs": CCS, "mlcc2": MLCC2, "mlccsd": MLCCSD, "mlccsd3": MLCCSD3}
 BF16X3 = 2
 PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
 
@@ -32,7 +32,8 @@ class ProblemDesc(C.Structure):
     _fields_ = [("n_occ", C.c_int32), ("n_vir", C.c_int32), ("n_chol", C.c_int32),
                 ("n_occ_act", C.c_int32), ("n_vir_act", C.c_int32), ("model", C.c_int32),
                 ("precision", C.c_int32), ("L", C.c_void_p), ("eps", C.c_void_p),
-                ("flags", C.c_uint32), ("seed", C.c_uint64), ("fock", C.c_void_p)]
+                ("flags", C.c_uint32), ("seed", C.c_uint64), ("fock", C.c_void_p),
+                ("n_occ_ccsd", C.c_int32), ("n_vir_ccsd", C.c_int32)]
 
 
 SYNTH_L = 1
@@ -270,10 +271,12 @@ class Problem:
     """One MLCC problem on a context (see mlcc_problem_create)."""
 
     def __init__(self, ctx: Context, L, eps, n_occ, n_vir, n_occ_act=None, n_vir_act=None,
-                 model="mlcc2", precision="fp64", n_chol=None, seed=None, fock=None):
+                 model="mlcc2", precision="fp64", n_chol=None, seed=None, fock=None,
+                 ccsd_space=None):
         """L=None with n_chol and seed: Cholesky vectors drawn on the device
         (MLCC_SYNTH_L).  fock: the full [n][n] Fock matrix of a semicanonical
-        basis (eps its diagonal), or None for diag(eps)."""
+        basis (eps its diagonal), or None for diag(eps).  ccsd_space:
+        (n_occ_ccsd, n_vir_ccsd) of model "mlccsd3" (three-level MLCCSD)."""
         self.ctx = ctx
         L = _f64(L)
         eps = _f64(eps)
@@ -285,7 +288,8 @@ class Problem:
                         n_occ if n_occ_act is None else n_occ_act,
                         n_vir if n_vir_act is None else n_vir_act,
                         MODEL[model], PREC[precision], _ptr(L), _ptr(eps),
-                        SYNTH_L if synth else 0, int(seed or 0), _ptr(fock))
+                        SYNTH_L if synth else 0, int(seed or 0), _ptr(fock),
+                        *(ccsd_space or (0, 0)))
         h = C.c_void_p()
         ctx.check(ctx.lib.mlcc_problem_create(ctx.h, C.byref(d), C.byref(h)))
         self._keep = None  # the library copied the inputs
@@ -415,18 +419,21 @@ class Server:
 
     @staticmethod
     def desc(L, eps, n_occ, n_vir, n_occ_act, n_vir_act, model="mlcc2", precision="fp64",
-             n_chol=None, seed=None, fock=None):
+             n_chol=None, seed=None, fock=None, ccsd_space=None):
         """Problem descriptor; L=None with seed set draws L on the device;
-        fock: a full Fock matrix (semicanonical basis) or None."""
+        fock: a full Fock matrix (semicanonical basis) or None; ccsd_space:
+        (n_occ_ccsd, n_vir_ccsd) of model "mlccsd3"."""
         eps = _f64(eps)
         fock = _f64(fock)
         if L is None:
             d = ProblemDesc(n_occ, n_vir, n_chol, n_occ_act, n_vir_act, MODEL[model],
-                            PREC[precision], None, _ptr(eps), SYNTH_L, seed, _ptr(fock))
+                            PREC[precision], None, _ptr(eps), SYNTH_L, seed, _ptr(fock),
+                            *(ccsd_space or (0, 0)))
             return d, (eps, fock)
         L = _f64(L)
         d = ProblemDesc(n_occ, n_vir, L.shape[0], n_occ_act, n_vir_act, MODEL[model],
-                        PREC[precision], _ptr(L), _ptr(eps), 0, 0, _ptr(fock))
+                        PREC[precision], _ptr(L), _ptr(eps), 0, 0, _ptr(fock),
+                        *(ccsd_space or (0, 0)))
         return d, (L, eps, fock)
 
     def submit(self, desc, n_roots, gs_tol=1e-8, es_tol=1e-6, effective=True, max_iter=100):

@@ -65,10 +65,33 @@ def test_noalloc_engine_arguments():
     assert m and int(m.group(1)) << int(m.group(2)) == mlcc.NOALLOC_SCRATCH_BYTES
 
 
-def test_cnto_and_fock_argument_checks():
+def test_cnto_argument_checks():
     """Entry points added with the orbital selection refuse NULL handles
-    without touching a device; the descriptor carries the Fock pointer last."""
+    without touching a device."""
     lib = mlcc.load()
     assert lib.mlcc_cnto(None, 1, None, None, 0, 0, None, None, None, None, None, None) == mlcc.E_ARG
-    names = [f[0] for f in mlcc.ProblemDesc._fields_]
-    assert names[-1] == "fock"
+
+
+def test_problem_descriptor_layout_matches_header():
+    """The binding's mlcc_problem_desc has the header's members in the
+    header's order (names and C types), so the structure layouts agree."""
+    text = open(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                             "include", "mlcc.h")).read()
+    body = re.search(r"typedef struct \{(.*?)\} mlcc_problem_desc;", text, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    members = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        m = re.match(r"(const\s+)?(\w+)\s*(\*?)\s*(.*)", decl)
+        ctype = m.group(2) + m.group(3)
+        for name in m.group(4).split(","):
+            members.append((name.strip().lstrip("*"), "ptr" if ("*" in ctype or "*" in name)
+                            else ctype))
+    ct = {"int32_t": ctypes.c_int32, "uint32_t": ctypes.c_uint32, "uint64_t": ctypes.c_uint64,
+          "ptr": ctypes.c_void_p}
+    fields = mlcc.ProblemDesc._fields_
+    assert [n for n, _ in members] == [f[0] for f in fields]
+    assert all(ct[t] is f[1] for (_, t), f in zip(members, fields))
+    assert mlcc.MODEL["mlccsd3"] == int(re.search(r"#define MLCC_MLCCSD3 (\d+)", text).group(1))

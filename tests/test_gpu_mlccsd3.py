@@ -1,0 +1,109 @@
+"""Three-level MLCCSD (CCS/CC2/CCSD) on the GPU through the C ABI against the
+FP64 oracle: residual and Jacobian transformation with CCSD-space outputs
+restricted inside a larger CC2 space (ragged multi-tile sizes, an empty and a
+one-sided CCSD space), the two-level limits, the ground state and the
+Davidson roots."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+from oracle import mlcc as om  # noqa: E402
+from paper_2006_05226_amd import mlcc  # noqa: E402
+from paper_2006_05226_amd.synth import gen_amplitudes, gen_inputs, gen_vectors  # noqa: E402
+
+from gpu_util import full_vec, rel, tol_chain  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+# (O, V, J, o, v, o_t, v_t): the CCSD space inside the CC2 space
+SIZES = [(9, 30, 70, 7, 11, 4, 6), (4, 13, 40, 3, 5, 2, 3), (6, 20, 50, 5, 9, 5, 2),
+         (6, 20, 50, 5, 9, 1, 9), (5, 16, 40, 4, 7, 0, 0)]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return mlcc.Context(0)
+
+
+def make3(ctx, sz, seed, precision="fp64"):
+    O, V, J, o, v, ot, vt = sz
+    inp = gen_inputs(O, V, J, o, v, seed=seed)
+    P = mlcc.Problem(ctx, inp.L, inp.eps, O, V, o, v, model="mlccsd3", precision=precision,
+                     ccsd_space=(ot, vt))
+    d = om.Dims(O, V, o, v)
+    OP = om.Problem(inp.L, inp.eps, d, "mlccsd3", ccsd_space=(ot, vt))
+    return inp, P, OP, d
+
+
+def tol_of(precision, sz):
+    # longest reductions: J, the pair count M and the ladder's v^2; about
+    # eight chained contractions from L to the doubles
+    O, V, J, o, v, ot, vt = sz
+    return 1e-11 if precision == "fp64" else tol_chain(precision, max(J, o * v, v * v), 8)
+
+
+@pytest.mark.parametrize("sz", SIZES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_residual_parity(ctx, sz, precision):
+    print(f"mlccsd3 residual {sz} {precision}", flush=True)
+    inp, P, OP, d = make3(ctx, sz, 2, precision)
+    t1, t2 = gen_amplitudes(d.O, d.V, d.o, d.v, seed=3, scale1=0.05, scale2=0.05)
+    P.set_amplitudes(t1, t2.reshape(d.M, d.M))
+    om1, om2, _, e = P.residual()
+    r1, r2 = OP.omega(t1, t2)
+    tol = tol_of(precision, sz)
+    assert rel(om1, r1) < tol
+    assert rel(om2, r2.reshape(d.M, d.M)) < tol
+    assert abs(e - OP.energy(t1, t2)) < tol * abs(OP.energy(t1, t2))
+
+
+@pytest.mark.parametrize("sz", SIZES)
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_jacobian_parity(ctx, sz, precision):
+    print(f"mlccsd3 jacobian {sz} {precision}", flush=True)
+    inp, P, OP, d = make3(ctx, sz, 4, precision)
+    t1, t2 = gen_amplitudes(d.O, d.V, d.o, d.v, seed=5, scale1=0.05, scale2=0.05)
+    P.set_amplitudes(t1, t2.reshape(d.M, d.M))
+    c1, c2 = gen_vectors(3, d.O, d.V, d.M, seed=6)
+    c = np.stack([full_vec(c1[i], c2[i]) for i in range(3)])
+    sig = P.jacobian_transform(c)
+    tol = 10.0 * tol_of(precision, sz)
+    for i in range(3):
+        r1, r2 = om.jacobian_transform(OP, t1, t2, c1[i], c2[i].reshape(d.v, d.o, d.v, d.o))
+        ref = full_vec(r1, r2)
+        assert rel(sig[i], ref) < tol
+
+
+def test_limits_are_the_two_level_models(ctx):
+    """CCSD space = CC2 space: bit-identical to MLCC_MLCCSD; empty CCSD space:
+    the MLCC2 residual at the same (independent) doubles."""
+    print("mlccsd3 limits", flush=True)
+    O, V, J, o, v = 6, 18, 44, 4, 8
+    inp = gen_inputs(O, V, J, o, v, seed=8)
+    t1, t2 = gen_amplitudes(O, V, o, v, seed=9, scale1=0.05, scale2=0.05)
+    M = o * v
+    outs = []
+    for model, space in (("mlccsd3", (o, v)), ("mlccsd", None)):
+        P = mlcc.Problem(ctx, inp.L, inp.eps, O, V, o, v, model=model, ccsd_space=space)
+        P.set_amplitudes(t1, t2.reshape(M, M))
+        outs.append(P.residual()[:2])
+        P.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    P = mlcc.Problem(ctx, inp.L, inp.eps, O, V, o, v, model="mlccsd3", ccsd_space=(0, 0))
+    P.set_amplitudes(t1, t2.reshape(M, M))
+    om1, om2, _, _ = P.residual()
+    r1, r2 = om.Problem(inp.L, inp.eps, om.Dims(O, V, o, v), "mlcc2").omega(t1, t2)
+    assert rel(om1, r1) < 1e-11 and rel(om2, r2.reshape(M, M)) < 1e-11
+
+
+def test_ground_state_and_roots(ctx):
+    print("mlccsd3 ground state and roots", flush=True)
+    inp, P, OP, d = make3(ctx, (5, 14, 36, 4, 8, 2, 4), 7)
+    ref = om.ground_state(OP, tol=1e-11)
+    r = P.ground_state(tol=1e-11)
+    assert r["converged"]
+    assert abs(r["energy"] - ref["energy"]) < 1e-10
+    dav = P.davidson(3, tol=1e-8)
+    assert dav["converged"]
+    ev = om.davidson(OP, ref["t1"], ref["x2"], 3, tol=1e-9)
+    assert np.abs(dav["omega"] - ev["omega"]).max() < 1e-8
