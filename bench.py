@@ -166,27 +166,35 @@ def _profiled_traffic(tag: str, config: str, precision: str):
     return float(fields["traffic_bytes_per_launch"])
 
 
-def _mlccsd_leg(mlcc, steps, warmup, precisions, config="mlccsd_60_600_2000", nvec=3):
-    """MLCCSD (CCS/CCSD) at its full-size workload: ground state, Jacobian
-    transforms/s for a batch of nvec trial vectors, and a Davidson solve, per
-    precision; Cholesky vectors drawn on the device (seed 0)."""
+def _mlccsd_leg(mlcc, steps, warmup, precisions, config="mlccsd_60_600_2000", nvec=3,
+                model="mlccsd"):
+    """MLCCSD (CCS/CCSD, or three-level CCS/CC2/CCSD with model "mlccsd3") at
+    its full-size workload: ground state, Jacobian transforms/s for a batch of
+    nvec trial vectors, and a Davidson solve, per precision; Cholesky vectors
+    drawn on the device (seed 0)."""
     import torch
     from paper_2006_05226_amd.synth import CONFIGS, gen_eps, gen_vectors
 
     c = CONFIGS[config]
     O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
+    space = (c["n_occ_ccsd"], c["n_vir_ccsd"]) if model == "mlccsd3" else None
     M = o * v
     eps = gen_eps(O, V, o, seed=0)
     c1, c2 = gen_vectors(nvec, O, V, M, seed=1)
     import numpy as np
     cvec = np.concatenate([c1.reshape(nvec, -1), c2.reshape(nvec, -1)], axis=1)
-    out = {"workload": f"MLCCSD (CCS/CCSD), n_occ={O} n_vir={V} n_chol={J}, CCSD active {o}/{v}, "
-                       f"device-drawn Cholesky vectors, batch of {nvec} trial vectors"}
+    del c1, c2
+    if space:
+        what = (f"three-level MLCCSD (CCS/CC2/CCSD), n_occ={O} n_vir={V} n_chol={J}, CC2 space "
+                f"{o}/{v}, CCSD space {space[0]}/{space[1]}")
+    else:
+        what = f"MLCCSD (CCS/CCSD), n_occ={O} n_vir={V} n_chol={J}, CCSD active {o}/{v}"
+    out = {"workload": f"{what}, device-drawn Cholesky vectors, batch of {nvec} trial vectors"}
     for prec in precisions:
-        print(f"mlccsd: {prec}", file=sys.stderr, flush=True)
+        print(f"{model}: {prec}", file=sys.stderr, flush=True)
         ctx = mlcc.Context(0)
-        P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlccsd", precision=prec, n_chol=J,
-                         seed=0)
+        P = mlcc.Problem(ctx, None, eps, O, V, o, v, model=model, precision=prec, n_chol=J,
+                         seed=0, ccsd_space=space)
         t0 = time.perf_counter()
         gs = P.ground_state(tol=1e-8 if prec == "fp64" else 1e-6)
         t_gs = time.perf_counter() - t0
@@ -567,6 +575,7 @@ def main():
     ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
     ap.add_argument("--no-c2", action="store_true", help="skip the 40/400/1200 full-space leg")
     ap.add_argument("--no-mlccsd", action="store_true", help="skip the MLCCSD leg")
+    ap.add_argument("--no-mlccsd3", action="store_true", help="skip the three-level MLCCSD leg")
     ap.add_argument("--no-cnto", action="store_true", help="skip the orbital-selection leg")
     ap.add_argument("--no-cholesky", action="store_true",
                     help="skip the two-step Cholesky decomposition leg")
@@ -628,6 +637,9 @@ def main():
         extra["c2"] = _c2_leg(mlcc, max(5, 5 * args.steps), 2, precs, solves=not args.no_solves)
     if not args.no_mlccsd:
         extra["mlccsd"] = _mlccsd_leg(mlcc, max(3, args.steps), 1, precs)
+    if not args.no_mlccsd3:
+        extra["mlccsd3"] = _mlccsd_leg(mlcc, max(3, args.steps), 1, precs,
+                                       config="mlccsd3_60_600_2000", model="mlccsd3")
     if not args.no_cnto:
         extra["cnto"] = _cnto_leg(mlcc, [p for p in ("fp64", "bf16x3") if p in precs])
     if not args.no_cholesky:

@@ -142,6 +142,10 @@ CONFIGS = {
     "mlcc2_40_400_1200": dict(n_occ=40, n_vir=400, n_chol=1200, n_occ_act=15, n_vir_act=150),
     # MLCCSD (CCS/CCSD) 60/600/2000 with CCSD active 12/120
     "mlccsd_60_600_2000": dict(n_occ=60, n_vir=600, n_chol=2000, n_occ_act=12, n_vir_act=120),
+    # three-level MLCCSD (CCS/CC2/CCSD) on the same system: CC2 space 30/300,
+    # CCSD space 12/120 inside it
+    "mlccsd3_60_600_2000": dict(n_occ=60, n_vir=600, n_chol=2000, n_occ_act=30, n_vir_act=300,
+                                n_occ_ccsd=12, n_vir_ccsd=120),
     # large MLCC2 reduced-space run, active 50/500
     "mlcc2_150_1200_3600": dict(n_occ=150, n_vir=1200, n_chol=3600, n_occ_act=50, n_vir_act=500),
 }
