@@ -156,6 +156,10 @@ typedef struct {
  * the device (0 = no limit beyond the device's free memory). */
 mlcc_status mlcc_context_create(int device, void *hip_stream, uint64_t hbm_budget,
                                 mlcc_context **ctx);
+/* Drops the caller's handle.  Problems and servers created on the context
+ * keep it alive: its device memory, stream and pinned buffers are freed when
+ * the last of them is destroyed, so the handles may be destroyed in any
+ * order; no call may be made on ctx itself after this one. */
 mlcc_status mlcc_context_destroy(mlcc_context *ctx);
 /* Message of the last error on this context (or of the last failed create when
  * ctx is NULL).  Valid until the next call on the context. */
@@ -227,6 +231,9 @@ typedef struct {
   int32_t max_slots;        /* requests on the device at once (0 -> 8) */
   int32_t max_queue;        /* waiting requests before MLCC_E_BUSY (0 -> 1024) */
   uint64_t hbm_budget;      /* bytes for admitted requests (0 -> context budget) */
+  uint64_t host_budget;     /* host bytes that the input copies of waiting (and
+                               admitted, until staged on the device) requests may
+                               hold (0 -> a quarter of the host's physical memory) */
 } mlcc_server_opts;
 
 typedef struct {
@@ -243,8 +250,12 @@ mlcc_status mlcc_server_create(mlcc_context *ctx, const mlcc_server_opts *opts,
 /* Drains admitted work, cancels waiting requests, joins the thread. */
 mlcc_status mlcc_server_destroy(mlcc_server *srv);
 /* Copies the request's inputs (host or device) and queues it.  MLCC_E_BUSY if
- * the queue is full; MLCC_E_OOM if its footprint exceeds the server budget
- * (it could never be admitted); MLCC_E_ARG for invalid descriptors. */
+ * the queue is full or its input copies would pass the host budget (try
+ * again later); MLCC_E_OOM if its footprint exceeds the server's HBM budget
+ * or its inputs alone the host budget (it could never be admitted);
+ * MLCC_E_ARG for invalid descriptors.  The host copy of the Cholesky vectors
+ * is dropped as soon as the admitted request has staged them on the device;
+ * requests with MLCC_SYNTH_L hold none. */
 mlcc_status mlcc_submit(mlcc_server *srv, const mlcc_problem_desc *desc, int32_t n_roots,
                         const mlcc_solver_opts *gs_opts, const mlcc_solver_opts *es_opts,
                         uint64_t *ticket);

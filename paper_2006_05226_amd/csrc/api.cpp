@@ -119,13 +119,7 @@ mlcc_status mlcc_context_create(int device, void *hip_stream, uint64_t hbm_budge
 
 mlcc_status mlcc_context_destroy(mlcc_context *ctx) {
   if (!ctx) return MLCC_E_ARG;
-  (void)hipSetDevice(ctx->device);
-  (void)hipStreamSynchronize(ctx->ex.stream);
-  ctx->ex.work.release();
-  ctx->ex.red.release();
-  if (ctx->own_stream) (void)hipStreamDestroy(ctx->ex.stream);
-  if (ctx->ex.pinned) (void)hipHostFree(ctx->ex.pinned);
-  delete ctx;
+  context_unref(ctx);
   return MLCC_OK;
 }
 
@@ -138,6 +132,17 @@ uint64_t mlcc_context_bytes(mlcc_context *ctx) { return ctx ? ctx->al.used : 0; 
 }  // extern "C"
 
 namespace mlcc {
+void context_unref(mlcc_context *ctx) {
+  if (ctx->refs.fetch_sub(1) != 1) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->ex.stream);
+  ctx->ex.work.release();
+  ctx->ex.red.release();
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->ex.stream);
+  if (ctx->ex.pinned) (void)hipHostFree(ctx->ex.pinned);
+  delete ctx;
+}
+
 mlcc_problem *problem_new(mlcc_context *ctx, Exec *ex, const mlcc_problem_desc *desc) {
   check_desc(desc);
   MLCC_HIP(hipSetDevice(ctx->device));
@@ -163,14 +168,17 @@ mlcc_status mlcc_problem_create(mlcc_context *ctx, const mlcc_problem_desc *desc
   return guarded(ctx, [&]() -> mlcc_status {
     MLCC_REQUIRE(prob != nullptr, MLCC_E_ARG, "NULL output pointer");
     *prob = problem_new(ctx, &ctx->ex, desc);
+    ctx->refs.fetch_add(1);
     return MLCC_OK;
   });
 }
 
 mlcc_status mlcc_problem_destroy(mlcc_problem *prob) {
   if (!prob) return MLCC_E_ARG;
+  mlcc_context *ctx = prob->ctx;
   (void)hipStreamSynchronize(prob->ex->stream);
   delete prob;
+  context_unref(ctx);
   return MLCC_OK;
 }
 

@@ -175,12 +175,15 @@ DavidsonResult davidson(Exec &ex, Alloc *al, int64_t dim, int n_roots, int n_gue
     for (int w = 0; w < nw; ++w) {
       double *wv = W + (int64_t)w * dim;
       double nrm = 0.0;
-      for (int pass = 0; pass < 2; ++pass) {
-        for (int j = k_old; j < k; ++j) {
-          k::dot(ex, dim, V + (int64_t)j * dim, wv, small.as<double>());
-          fetch(small.as<double>(), 1);
-          k::axpby(ex, dim, -hbuf[0], V + (int64_t)j * dim, 1.0, wv);
-        }
+      // against the vectors this block has added so far: c = V_new w and
+      // w -= V_new^T c on the device (two passes), one fetch for the norm
+      const int nn = k - k_old;
+      double *cv = small.as<double>() + 32;
+      for (int pass = 0; pass < 2 && nn > 0; ++pass) {
+        G(nn, 1, dim).A(V + (int64_t)k_old * dim, dim, 1).B(wv, 1, 0).C(cv, 1, 0)
+            .run(ex, Prec::F64, true);
+        G(1, dim, nn).A(cv, 0, 1).B(V + (int64_t)k_old * dim, dim, 1).C(wv, 0, 1, 0, -1.0, 1.0)
+            .run(ex, Prec::F64, true);
       }
       k::dot(ex, dim, wv, wv, small.as<double>());
       fetch(small.as<double>(), 1);

@@ -1,12 +1,17 @@
 // The context and problem objects behind the C ABI.
 #pragma once
 
+#include <atomic>
 #include <memory>
 #include <string>
 
 #include "mlcc_internal.h"
 
 struct mlcc_context {
+  // references: the creator's, one per problem created on it and one per
+  // server; the context is freed when the last one is dropped, so that
+  // destroying it before its problems is safe
+  std::atomic<int> refs{1};
   int device = 0;
   mlcc::Profiler prof;
   bool own_stream = false;
@@ -18,6 +23,9 @@ struct mlcc_context {
 };
 
 namespace mlcc {
+
+// Drops one reference on a context; the last one frees it.
+void context_unref(mlcc_context *ctx);
 
 struct Dims {
   int O = 0, V = 0, n = 0, J = 0, o = 0, v = 0;

@@ -1,14 +1,17 @@
 // Serving loop: continuous batching of MLCC excitation solves of uneven size
 // on one GPU.
 //
-// * mlcc_submit (any host thread) validates the request, copies its inputs to
-//   host memory owned by the request and queues it with a ticket.
+// * mlcc_submit (any host thread) validates the request, reserves its host
+//   bytes against the host budget, copies its inputs to host memory owned by
+//   the request and queues it with a ticket.
 // * max_slots execution lanes, each with its own HIP stream (default priority)
 //   and its own scratch, run admitted requests concurrently, so the kernels of
 //   requests of different sizes overlap on the device.  A lane takes the
 //   first queued request whose HBM footprint estimate fits in what the budget
-//   has left (FIFO with backfill); memory and the slot are returned when the
-//   request finishes and waiting requests are admitted at once.
+//   has left (FIFO with backfill, admission.h); the host copy of the inputs
+//   is dropped once the problem holds them on the device, and memory and the
+//   slot are returned when the request finishes and waiting requests are
+//   admitted at once.
 // * Each request runs its ground state, then the Davidson solve for its roots;
 //   the result and the submit / admit / done times go to the ticket table that
 //   mlcc_poll reads.  The kernels and reductions are deterministic, so a
@@ -21,7 +24,9 @@
 #include <memory>
 #include <thread>
 #include <unordered_map>
+#include <unistd.h>
 
+#include "admission.h"
 #include "drivers.h"
 
 namespace mlcc {
@@ -34,6 +39,7 @@ struct Request {
   int32_t n_roots = 0;
   mlcc_solver_opts gs{}, es{};
   uint64_t footprint = 0;
+  uint64_t host_bytes = 0;  // of the copies above, counted against the host budget
   bool done = false;
   mlcc_result res{};
 };
@@ -54,15 +60,11 @@ using namespace mlcc;
 struct mlcc_server {
   mlcc_context *ctx = nullptr;
   int max_slots = 8;
-  size_t max_queue = 1024;
-  uint64_t budget = 0;
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Request *> queue;
+  std::unique_ptr<Admission<Request>> adm;  // under mu
   std::unordered_map<uint64_t, Request *> table;
   uint64_t next_ticket = 1;
-  uint64_t in_use = 0;
-  bool stop = false;
   std::vector<std::unique_ptr<Lane>> lanes;
   std::vector<std::thread> workers;
   std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -128,20 +130,24 @@ void mlcc_server::work(Lane *lane) {
     {
       std::unique_lock<std::mutex> lk(mu);
       for (;;) {
-        if (stop) return;
-        for (auto it = queue.begin(); it != queue.end(); ++it) {
-          if ((*it)->footprint <= budget - in_use) {
-            r = *it;
-            queue.erase(it);
-            break;
-          }
-        }
+        if (adm->stopped()) return;
+        r = adm->admit();
         if (r) break;
         cv.wait(lk);
       }
-      in_use += r->footprint;
       r->res.t_admit = now_s(t0);
     }
+    bool host_held = true;
+    auto drop_host = [&]() {
+      if (!host_held) return;
+      r->L.clear();
+      r->L.shrink_to_fit();
+      r->fock.clear();
+      r->fock.shrink_to_fit();
+      std::lock_guard<std::mutex> lk(mu);
+      adm->drop_host(r->host_bytes);
+      host_held = false;
+    };
     mlcc_status st = MLCC_OK;
     mlcc_result &out = r->res;
     out.n_roots = r->n_roots;
@@ -151,6 +157,7 @@ void mlcc_server::work(Lane *lane) {
       d.eps = r->eps.data();
       d.fock = r->fock.empty() ? nullptr : r->fock.data();
       std::unique_ptr<mlcc_problem> P(problem_new(ctx, &lane->ex, &d));
+      drop_host();  // the problem holds its own device copies now
       mlcc_info gi{};
       mlcc_status gs = ground_state(*P, r->gs, gi);
       out.e_corr = gi.energy;
@@ -172,14 +179,13 @@ void mlcc_server::work(Lane *lane) {
     (void)hipStreamSynchronize(lane->ex.stream);
     lane->ex.work.release();
     lane->ex.red.release();
+    drop_host();
     {
       std::lock_guard<std::mutex> lk(mu);
-      in_use -= r->footprint;
+      adm->release(r->footprint);
       out.status = st;
       out.t_done = now_s(t0);
       r->done = true;
-      r->L.clear();
-      r->L.shrink_to_fit();
     }
     cv.notify_all();
   }
@@ -192,48 +198,61 @@ mlcc_status mlcc_server_create(mlcc_context *ctx, const mlcc_server_opts *opts,
   if (!ctx || !out) return MLCC_E_ARG;
   auto *s = new mlcc_server();
   s->ctx = ctx;
+  size_t max_queue = 1024;
+  uint64_t budget = 0, host_budget = 0;
   if (opts) {
     if (opts->max_slots > 0) s->max_slots = opts->max_slots;
-    if (opts->max_queue > 0) s->max_queue = (size_t)opts->max_queue;
-    s->budget = opts->hbm_budget;
+    if (opts->max_queue > 0) max_queue = (size_t)opts->max_queue;
+    budget = opts->hbm_budget;
+    host_budget = opts->host_budget;
   }
-  if (s->budget == 0) s->budget = ctx->al.budget;
-  if (s->budget == 0) {
+  if (budget == 0) budget = ctx->al.budget;
+  if (budget == 0) {
     size_t fr = 0, tot = 0;
     if (hipSetDevice(ctx->device) != hipSuccess || hipMemGetInfo(&fr, &tot) != hipSuccess) {
       (void)hipGetLastError();
       delete s;
       return MLCC_E_DEVICE;
     }
-    s->budget = (uint64_t)(fr * 0.9);
+    budget = (uint64_t)(fr * 0.9);
   }
+  if (host_budget == 0) {
+    const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGE_SIZE);
+    host_budget = pages > 0 && page > 0 ? (uint64_t)pages * (uint64_t)page / 4 : (16ull << 30);
+  }
+  s->adm = std::make_unique<Admission<Request>>(budget, host_budget, max_queue);
   for (int i = 0; i < s->max_slots; ++i) {
     auto lane = std::make_unique<Lane>();
     lane->ex.al = &ctx->al;
-    if (hipStreamCreateWithFlags(&lane->ex.stream, hipStreamNonBlocking) != hipSuccess ||
-        hipHostMalloc((void **)&lane->ex.pinned, 512 * sizeof(double), hipHostMallocDefault) !=
-            hipSuccess) {
+    const bool ok =
+        hipStreamCreateWithFlags(&lane->ex.stream, hipStreamNonBlocking) == hipSuccess &&
+        hipHostMalloc((void **)&lane->ex.pinned, 512 * sizeof(double), hipHostMallocDefault) ==
+            hipSuccess;
+    s->lanes.push_back(std::move(lane));
+    if (!ok) {
       (void)hipGetLastError();
+      for (auto &l : s->lanes) {
+        if (l->ex.stream) (void)hipStreamDestroy(l->ex.stream);
+        if (l->ex.pinned) (void)hipHostFree(l->ex.pinned);
+      }
       delete s;
       return MLCC_E_DEVICE;
     }
-    s->lanes.push_back(std::move(lane));
   }
   for (auto &l : s->lanes) s->workers.emplace_back(&mlcc_server::work, s, l.get());
+  ctx->refs.fetch_add(1);  // dropped by mlcc_server_destroy
   *out = s;
   return MLCC_OK;
 }
 
 mlcc_status mlcc_server_destroy(mlcc_server *s) {
   if (!s) return MLCC_E_ARG;
-  {
+  if (s->adm) {
     std::lock_guard<std::mutex> lk(s->mu);
-    s->stop = true;
-    for (Request *r : s->queue) {
-      s->table.erase(r->ticket);
-      delete r;
+    for (auto &item : s->adm->stop()) {
+      s->table.erase(item.req->ticket);
+      delete item.req;
     }
-    s->queue.clear();
   }
   s->cv.notify_all();
   for (auto &t : s->workers) t.join();
@@ -244,7 +263,9 @@ mlcc_status mlcc_server_destroy(mlcc_server *s) {
     if (l->ex.stream) (void)hipStreamDestroy(l->ex.stream);
     if (l->ex.pinned) (void)hipHostFree(l->ex.pinned);
   }
+  mlcc_context *ctx = s->ctx;
   delete s;
+  context_unref(ctx);
   return MLCC_OK;
 }
 
@@ -264,13 +285,29 @@ mlcc_status mlcc_submit(mlcc_server *s, const mlcc_problem_desc *desc, int32_t n
   r->gs = *gs;
   r->es = *es;
   r->footprint = mlcc_request_footprint(desc, n_roots, es);
-  if (r->footprint > s->budget) return MLCC_E_OOM;
+  const int64_t n = (int64_t)desc->n_occ + desc->n_vir;
+  r->host_bytes = sizeof(double) * ((uint64_t)n + (desc->fock ? (uint64_t)(n * n) : 0) +
+                                    ((desc->flags & MLCC_SYNTH_L) ? 0 : (uint64_t)desc->n_chol * n * n));
+  auto status_of = [](AdmitStatus a) -> mlcc_status {
+    switch (a) {
+      case AdmitStatus::ok: return MLCC_OK;
+      case AdmitStatus::too_large_hbm:
+      case AdmitStatus::too_large_host: return MLCC_E_OOM;
+      case AdmitStatus::busy: return MLCC_E_BUSY;
+      default: return MLCC_E_STATE;
+    }
+  };
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->queue.size() >= s->max_queue) return MLCC_E_BUSY;
+    const AdmitStatus a = s->adm->reserve(r->footprint, r->host_bytes);
+    if (a != AdmitStatus::ok) return status_of(a);
   }
+  auto cancel = [&](mlcc_status st) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->adm->cancel(r->host_bytes);
+    return st;
+  };
   // copy the inputs (host or device memory) before returning
-  const int64_t n = (int64_t)desc->n_occ + desc->n_vir;
   auto copy_in = [&](std::vector<double> &dst, const double *src, int64_t cnt) -> bool {
     dst.resize(cnt);
     hipPointerAttribute_t at;
@@ -282,22 +319,25 @@ mlcc_status mlcc_submit(mlcc_server *s, const mlcc_problem_desc *desc, int32_t n
     return true;
   };
   try {
-    if (!copy_in(r->eps, desc->eps, n)) return MLCC_E_DEVICE;
-    if (desc->fock && !copy_in(r->fock, desc->fock, n * n)) return MLCC_E_DEVICE;
+    if (!copy_in(r->eps, desc->eps, n)) return cancel(MLCC_E_DEVICE);
+    if (desc->fock && !copy_in(r->fock, desc->fock, n * n)) return cancel(MLCC_E_DEVICE);
     if (!(desc->flags & MLCC_SYNTH_L) && !copy_in(r->L, desc->L, (int64_t)desc->n_chol * n * n))
-      return MLCC_E_DEVICE;
+      return cancel(MLCC_E_DEVICE);
   } catch (const std::bad_alloc &) {
-    return MLCC_E_OOM;
+    return cancel(MLCC_E_OOM);
   }
   {
     std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return MLCC_E_STATE;
-    if (s->queue.size() >= s->max_queue) return MLCC_E_BUSY;
-    r->ticket = s->next_ticket++;
-    r->res.t_submit = now_s(s->t0);
-    *ticket = r->ticket;
-    s->table[r->ticket] = r.get();
-    s->queue.push_back(r.release());
+    const AdmitStatus a = s->adm->enqueue(r.get(), r->footprint, r->host_bytes);
+    if (a != AdmitStatus::ok) {
+      s->adm->cancel(r->host_bytes);
+      return status_of(a);
+    }
+    Request *q = r.release();
+    q->ticket = s->next_ticket++;
+    q->res.t_submit = now_s(s->t0);
+    *ticket = q->ticket;
+    s->table[q->ticket] = q;
   }
   s->cv.notify_all();
   return MLCC_OK;

@@ -50,7 +50,8 @@ class Info(C.Structure):
 
 
 class ServerOpts(C.Structure):
-    _fields_ = [("max_slots", C.c_int32), ("max_queue", C.c_int32), ("hbm_budget", C.c_uint64)]
+    _fields_ = [("max_slots", C.c_int32), ("max_queue", C.c_int32), ("hbm_budget", C.c_uint64),
+                ("host_budget", C.c_uint64)]
 
 
 class Result(C.Structure):
@@ -409,10 +410,10 @@ class Problem:
 class Server:
     """Continuous-batching server on a context (mlcc_server_create)."""
 
-    def __init__(self, ctx: Context, max_slots=0, max_queue=0, hbm_budget=0):
+    def __init__(self, ctx: Context, max_slots=0, max_queue=0, hbm_budget=0, host_budget=0):
         self.ctx = ctx
         h = C.c_void_p()
-        o = ServerOpts(max_slots, max_queue, hbm_budget)
+        o = ServerOpts(max_slots, max_queue, hbm_budget, host_budget)
         ctx.check(ctx.lib.mlcc_server_create(ctx.h, C.byref(o), C.byref(h)))
         self.h = h
         self._keep = {}

@@ -44,3 +44,11 @@ def tol_chain(prec, K, stages=4):
     equal error of the FP64 oracle's different order (FP64 only)."""
     t = 5.0 * np.sqrt(stages) * (U_PRODUCT[prec] + U_ACC[prec] * (np.sqrt(K) + 1.0))
     return 2.0 * t if prec == "fp64" else t
+
+
+def bar(prec, K, stages, fp64=1e-11):
+    """Parity bar of a model quantity: FP64 keeps a fixed bar (only the
+    rounding order differs from the oracle); FP32 and split BF16 take
+    tol_chain over the longest reduction K and the number of chained
+    contractions from L to the quantity."""
+    return fp64 if prec == "fp64" else tol_chain(prec, K, stages)

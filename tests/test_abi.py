@@ -5,6 +5,8 @@ import glob
 import os
 import re
 
+import pytest
+
 from paper_2006_05226_amd import mlcc
 
 
@@ -95,3 +97,22 @@ def test_problem_descriptor_layout_matches_header():
     assert [n for n, _ in members] == [f[0] for f in fields]
     assert all(ct[t] is f[1] for (_, t), f in zip(members, fields))
     assert mlcc.MODEL["mlccsd3"] == int(re.search(r"#define MLCC_MLCCSD3 (\d+)", text).group(1))
+
+
+def test_plain_c_client(tmp_path):
+    """include/mlcc.h compiles as C99 with warnings as errors, and a C client
+    linked against the library gets the documented argument errors and
+    footprint estimates without a device (tests/c/abi_driver.c)."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    pkg = os.path.join(root, "paper_2006_05226_amd")
+    exe = str(tmp_path / "abi_driver")
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                    f"-I{os.path.join(root, 'include')}", os.path.join(root, "tests", "c", "abi_driver.c"),
+                    f"-L{pkg}", "-lmlcc", f"-Wl,-rpath,{pkg}", "-lm", "-o", exe],
+                   check=True, capture_output=True, text=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr

@@ -1,5 +1,6 @@
 """Serving (continuous batching of excitation solves) on the GPU: each result
-alone equals its result in a mix of concurrent requests of different sizes;
+alone equals its result in a mix of concurrent requests of different sizes,
+and every served energy and root of that mix matches the FP64 oracle;
 admission, queue and ticket errors; the device-side synthetic inputs."""
 import math
 import time
@@ -58,6 +59,19 @@ def test_alone_equals_mix(ctx):
     # the solves overlapped: some request was admitted before another finished
     spans = sorted((r["t_admit"], r["t_done"]) for r in res)
     assert any(spans[i + 1][0] < spans[i][1] for i in range(len(spans) - 1))
+    # every served energy and root against the FP64 oracle (its ground state
+    # and full-space Davidson on the same inputs); bars: FP64 requests 1e-9 Eh
+    # (energy) and 1e-6 Eh (roots, solved to a residual of 1e-7), FP32
+    # requests 1e-6 Eh and 1e-5 eV
+    for r, inp, (O, V, J, o, v, model, prec) in zip(res, inputs, MIX):
+        OP = om.Problem(inp.L, inp.eps, om.Dims(O, V, o, v), model)
+        g = om.ground_state(OP, tol=1e-11)
+        w = om.davidson(OP, g["t1"], g["x2"], 3, tol=1e-9)["omega"]
+        be, bw = (1e-9, 1e-6) if prec == "fp64" else (1e-6, 1e-5 / 27.211386245988)
+        print(f"{model} {prec} {O}/{V}/{J} active {o}/{v}: dE={r['e_corr'] - g['energy']:.1e} "
+              f"dw={np.abs(np.array(r['omega'][:3]) - w).max():.1e}")
+        assert abs(r["e_corr"] - g["energy"]) < be
+        assert np.abs(np.array(r["omega"][:3]) - w).max() < bw
 
 
 def test_mix_matches_oracle_energy(ctx):
