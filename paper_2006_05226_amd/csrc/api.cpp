@@ -20,7 +20,7 @@ struct In {
     if (is_device_ptr(src)) {
       p = src;
     } else {
-      buf.alloc(&P.ctx->al, n * sizeof(double));
+      buf.alloc(P.ex->al, n * sizeof(double));
       MLCC_HIP(hipMemcpyAsync(buf.p, src, n * sizeof(double), hipMemcpyHostToDevice,
                               P.ex->stream));
       p = buf.as<double>();
@@ -37,7 +37,7 @@ struct Out {
     if (is_device_ptr(d)) {
       p = d;
     } else {
-      buf.alloc(&P.ctx->al, n * sizeof(double));
+      buf.alloc(P.ex->al, n * sizeof(double));
       p = buf.as<double>();
     }
   }
@@ -103,6 +103,7 @@ mlcc_status mlcc_context_create(int device, void *hip_stream, uint64_t hbm_budge
       }
       c->own_stream = true;
     }
+    c->al.stream = c->ex.stream;
     if (hipHostMalloc((void **)&c->ex.pinned, 512 * sizeof(double), hipHostMallocDefault) !=
         hipSuccess) {
       (void)hipGetLastError();
@@ -138,6 +139,7 @@ void context_unref(mlcc_context *ctx) {
   (void)hipStreamSynchronize(ctx->ex.stream);
   ctx->ex.work.release();
   ctx->ex.red.release();
+  ctx->al.release_all();
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->ex.stream);
   if (ctx->ex.pinned) (void)hipHostFree(ctx->ex.pinned);
   delete ctx;
@@ -378,7 +380,7 @@ mlcc_status mlcc_davidson_solve(mlcc_problem *P, int32_t n_roots, const mlcc_sol
         k::precond(ex, n1, M, eps_vo, eps_ai, wr, r, o);
         k::symmetrize(ex, M, o + n1, 1, dim);
       };
-      DavidsonResult dr = davidson(ex, &P->ctx->al, dim, n_roots, n_guess, max_space, max_iter,
+      DavidsonResult dr = davidson(ex, P->ex->al, dim, n_roots, n_guess, max_space, max_iter,
                                    opts->tol, gidx, apply, pre, nullptr, 0, 0, 0.0);
       w = dr.omega;
       converged = dr.converged;
@@ -400,25 +402,25 @@ mlcc_status mlcc_davidson_solve(mlcc_problem *P, int32_t n_roots, const mlcc_sol
       P->fetch_n(eps_vo, d0.data(), (int)n1);
       double w0 = *std::min_element(d0.begin(), d0.end());
       auto apply0 = [&](int n, const double *in, double *out) { P->transform_eff(w0, n, in, out); };
-      DavidsonResult d0r = davidson(ex, &P->ctx->al, n1, n_roots, n_guess, max_space, max_iter,
+      DavidsonResult d0r = davidson(ex, P->ex->al, n1, n_roots, n_guess, max_space, max_iter,
                                     opts->tol, gidx, apply0, pre, nullptr, 0, 0, 0.0);
       inf.transforms += d0r.transforms;
       inf.iterations += d0r.iterations;
-      X.alloc(&P->ctx->al, (size_t)n_roots * n1 * sizeof(double));
+      X.alloc(P->ex->al, (size_t)n_roots * n1 * sizeof(double));
       converged = true;
       double worst = 0.0;
       for (int r = 0; r < n_roots; ++r) {
         double wr = d0r.omega[r];
         const double *start = d0r.X.as<double>() + (int64_t)r * n1;
         DBuf cur;
-        cur.alloc(&P->ctx->al, n1 * sizeof(double));
+        cur.alloc(P->ex->al, n1 * sizeof(double));
         MLCC_HIP(hipMemcpyAsync(cur.p, start, n1 * sizeof(double), hipMemcpyDeviceToDevice,
                                 ex.stream));
         bool ok = false;
         double resid = 0.0;
         for (int outer = 0; outer < 30; ++outer) {
           auto apply = [&](int n, const double *in, double *out) { P->transform_eff(wr, n, in, out); };
-          DavidsonResult dr = davidson(ex, &P->ctx->al, n1, 1, 0, std::max(8, max_space / n_roots),
+          DavidsonResult dr = davidson(ex, P->ex->al, n1, 1, 0, std::max(8, max_space / n_roots),
                                        max_iter, opts->tol, {}, apply, pre, cur.as<double>(), 1, 1,
                                        wr);
           inf.transforms += dr.transforms;
@@ -565,7 +567,7 @@ mlcc_status mlcc_debug_get(mlcc_problem *P, int32_t which, double *out) {
     const int64_t n2 = P->d.n2, J = P->d.J, MM = P->d.M * P->d.M;
     DBuf tmp;
     auto get = [&](const void *src, int64_t n, bool isf32) {
-      tmp.alloc(&P->ctx->al, n * sizeof(double));
+      tmp.alloc(P->ex->al, n * sizeof(double));
       if (isf32) k::convert<double, float>(ex, tmp.as<double>(), (const float *)src, n);
       else MLCC_HIP(hipMemcpyAsync(tmp.p, src, n * 8, hipMemcpyDeviceToDevice, ex.stream));
       MLCC_HIP(hipMemcpyAsync(out, tmp.p, n * 8, hipMemcpyDeviceToHost, ex.stream));

@@ -63,7 +63,7 @@ mlcc_problem::~mlcc_problem() { delete cc; }
 // Integral blocks of the active space from the current L~ and F~.
 template <typename T> void mlcc_problem::ccsd_integrals_t() {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   if (!cc) cc = new CcsdState();
   CcsdState &s = *cc;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, o = d.o, v = d.v, M = d.M;
@@ -122,7 +122,7 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
                                 const void *tB, const void *uB, bool incL, bool incB, bool incQ,
                                 bool ladder, double *sym, double *R) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   CcsdState &s = *cc;
   const int64_t o = d.o, v = d.v, M = d.M, ot = d.ot, vt = d.vt, Mt = ot * vt;
   const bool full = !d.cc2_rows();  // output over the whole active space
@@ -265,7 +265,7 @@ void mlcc_problem::ccsd_terms_t(const void *const *blk, const void *tA, const vo
 
 template <typename T> void mlcc_problem::ccsd_omega2_t() {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t M = d.M;
   ccsd_integrals_t<T>();
   CcsdState &s = *cc;
@@ -289,7 +289,7 @@ template <typename T> void mlcc_problem::ccsd_omega2_t() {
 //   Y3[K][i][b][j] = sum_cd g~_Kcbd t_cidj,  g~_Kcbd = sum_J L~^J_Kc L~^J_bd
 template <typename T> void mlcc_problem::ccsd_prepare_t() {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   CcsdState &s = *cc;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, o = d.o, v = d.v, M = d.M;
   const int64_t ot = d.ot, vt = d.vt;
@@ -318,7 +318,7 @@ template <typename T>
 void mlcc_problem::ccsd_sigma2_t(const double *c1, const double *c2, const double *Gv,
                                  int64_t ldg, const void *dLvo, int64_t ldl, double *s2) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   CcsdState &s = *cc;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
   const int64_t n1 = d.n1;

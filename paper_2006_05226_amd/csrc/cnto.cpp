@@ -172,7 +172,7 @@ void mlcc_problem::cnto_t(int ns, const double *R, const double *w, int o_act, i
                           double *m_eig, double *n_eig, double *C_out, double *eps_out,
                           double *fock_out, double *L_out, bool L_out_dev) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t O = d.O, V = d.V, J = d.J, n = d.n, n2 = d.n2, n1 = d.n1;
   const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;

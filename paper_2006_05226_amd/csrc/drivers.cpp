@@ -33,7 +33,7 @@ void gram(Exec &ex, int64_t mX, int64_t nY, int64_t len, const double *X, const 
 // ---------------------------------------------------------------------------
 mlcc_status ground_state(mlcc_problem &P, const mlcc_solver_opts &o, mlcc_info &info) {
   Exec &ex = *P.ex;
-  Alloc *al = &P.ctx->al;
+  Alloc *al = P.ex->al;
   const bool diis_doubles = P.model == MLCC_MLCCSD && P.has_doubles();
   const int64_t len = P.d.n1 + (diis_doubles ? P.d.M * P.d.M : 0);
   const int m = o.diis_dim > 0 ? o.diis_dim : 8;

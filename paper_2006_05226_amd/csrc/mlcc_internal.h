@@ -40,19 +40,45 @@ struct Error {
 // ---------------------------------------------------------------------------
 // device memory accounting
 // ---------------------------------------------------------------------------
-// Device allocations of a context.  Every allocation has kSlack readable
-// bytes past its end, so a 16-byte load that runs past a row's last element
-// stays inside it; owns() tells whether a pointer lies in a live allocation.
+// Device allocations of a context, cached.  Every allocation has kSlack
+// readable bytes past its end, so a 16-byte load that runs past a row's last
+// element stays inside it; owns() tells whether a pointer lies in a live
+// allocation.
+//
+// Freeing device memory synchronises the whole device, which stalls every
+// stream, so blocks are not returned to the device when released but kept:
+// * each allocator serves one stream (the context's, or one serving lane's,
+//   with the context's allocator as root); a block released on it goes to
+//   its own cache and is reused only by it, which stream order makes safe;
+// * once the stream has finished all its work (quiesce(), called after the
+//   stream is synchronised), its cached blocks become idle in the root,
+//   where any allocator may take them;
+// * idle blocks are returned to the device only when an allocation would
+//   pass the budget or the device is out of memory (trim()), and at the end.
+// The root keeps the accounting: used = bytes of live blocks, held = bytes
+// taken from the device (live, cached and idle), budget bounds held.
 constexpr size_t kSlack = 256;
 struct Alloc {
   int device = 0;
-  uint64_t budget = 0;  // 0: unlimited
-  uint64_t used = 0;
+  uint64_t budget = 0;  // root: bound on held bytes (0: unlimited)
+  uint64_t used = 0;    // root: bytes of live blocks (their capacity)
+  uint64_t held = 0;    // root: bytes allocated from the device
+  Alloc *root = this;   // a lane's allocator points to the context's
+  hipStream_t stream = nullptr;  // the stream this allocator serves
   std::mutex mu;
-  std::map<uintptr_t, size_t> live;  // base -> requested bytes
+  std::map<uintptr_t, size_t> live;         // root: base -> capacity
+  std::multimap<size_t, void *> cache;      // capacity -> block, released on this stream
+  std::multimap<size_t, void *> idle;       // root: capacity -> block no pending work uses
   void *get(size_t bytes);
   void put(void *p, size_t bytes);
   bool owns(const void *p);
+  void quiesce();  // this allocator's stream is idle: cached blocks become idle in the root
+  void trim();     // root: idle blocks back to the device
+  void reclaim();  // under memory pressure: wait for this stream, then quiesce and trim
+  void release_all();  // root, at the end: every cached and idle block back to the device
+  Alloc() = default;
+  Alloc(const Alloc &) = delete;
+  Alloc &operator=(const Alloc &) = delete;
 };
 
 // RAII device buffer accounted against an Alloc.

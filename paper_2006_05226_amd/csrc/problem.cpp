@@ -48,43 +48,135 @@ int pair_block_occ(int o, int v, int nz, int tsize) {
   return (o + blocks - 1) / blocks;
 }
 
+namespace {
+// Capacity of a block for a request of n bytes (plus slack): 4 KiB granules
+// below 2 MiB, 2 MiB granules above, so that repeated sizes find their blocks.
+size_t block_capacity(size_t n) {
+  const size_t g = n < (2u << 20) ? (4u << 10) : (2u << 20);
+  return (n + g - 1) / g * g;
+}
+// A cached block of capacity cap serves a request needing want bytes when
+// it is at most twice as large.
+bool fits(size_t cap, size_t want) { return cap >= want && cap <= 2 * want; }
+}  // namespace
+
 void *Alloc::get(size_t bytes) {
-  const size_t total = bytes + kSlack;
+  const size_t want = block_capacity(bytes + kSlack);
+  void *p = nullptr;
+  size_t cap = 0;
   {
     std::lock_guard<std::mutex> lk(mu);
-    if (budget && used + total > budget)
-      throw Error{MLCC_E_OOM, "HBM budget exceeded: need " + std::to_string(total) +
-                                  " bytes, " + std::to_string(budget - used) + " left"};
-    used += total;
+    auto it = cache.lower_bound(want);
+    if (it != cache.end() && fits(it->first, want)) {
+      cap = it->first;
+      p = it->second;
+      cache.erase(it);
+    }
   }
-  void *p = nullptr;
-  hipError_t e = hipMalloc(&p, total);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    std::lock_guard<std::mutex> lk(mu);
-    used -= total;
-    throw Error{e == hipErrorOutOfMemory ? MLCC_E_OOM : MLCC_E_DEVICE,
-                std::string("hipMalloc: ") + hipGetErrorString(e)};
+  Alloc *r = root;
+  if (!p) {
+    std::lock_guard<std::mutex> lk(r->mu);
+    auto it = r->idle.lower_bound(want);
+    if (it != r->idle.end() && fits(it->first, want)) {
+      cap = it->first;
+      p = it->second;
+      r->idle.erase(it);
+    }
   }
-  std::lock_guard<std::mutex> lk(mu);
-  live[reinterpret_cast<uintptr_t>(p)] = bytes;
+  if (!p) {
+    bool over;
+    {
+      std::lock_guard<std::mutex> lk(r->mu);
+      over = r->budget && r->held + want > r->budget;
+    }
+    if (over) reclaim();
+    {
+      std::lock_guard<std::mutex> lk(r->mu);
+      if (r->budget && r->held + want > r->budget)
+        throw Error{MLCC_E_OOM, "HBM budget exceeded: need " + std::to_string(want) + " bytes, " +
+                                    std::to_string(r->budget - r->held) + " left"};
+      r->held += want;  // reserved while the allocation is made
+    }
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipErrorOutOfMemory) {
+      (void)hipGetLastError();
+      reclaim();
+      e = hipMalloc(&p, want);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      std::lock_guard<std::mutex> lk(r->mu);
+      r->held -= want;
+      throw Error{e == hipErrorOutOfMemory ? MLCC_E_OOM : MLCC_E_DEVICE,
+                  std::string("hipMalloc: ") + hipGetErrorString(e)};
+    }
+    cap = want;
+  }
+  std::lock_guard<std::mutex> lk(r->mu);
+  r->live[reinterpret_cast<uintptr_t>(p)] = cap;
+  r->used += cap;
   return p;
 }
 
-void Alloc::put(void *p, size_t bytes) {
-  (void)hipFree(p);
+void Alloc::put(void *p, size_t) {
+  Alloc *r = root;
+  size_t cap = 0;
+  {
+    std::lock_guard<std::mutex> lk(r->mu);
+    auto it = r->live.find(reinterpret_cast<uintptr_t>(p));
+    if (it == r->live.end()) return;
+    cap = it->second;
+    r->live.erase(it);
+    r->used -= cap;
+  }
   std::lock_guard<std::mutex> lk(mu);
-  live.erase(reinterpret_cast<uintptr_t>(p));
-  used -= bytes + kSlack;
+  cache.emplace(cap, p);
+}
+
+void Alloc::quiesce() {
+  std::multimap<size_t, void *> blocks;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    blocks.swap(cache);
+  }
+  std::lock_guard<std::mutex> lk(root->mu);
+  root->idle.insert(blocks.begin(), blocks.end());
+}
+
+void Alloc::trim() {
+  std::multimap<size_t, void *> blocks;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    blocks.swap(idle);
+  }
+  size_t freed = 0;
+  for (auto &b : blocks) {
+    (void)hipFree(b.second);
+    freed += b.first;
+  }
+  std::lock_guard<std::mutex> lk(mu);
+  held -= freed;
+}
+
+void Alloc::reclaim() {
+  if (stream) (void)hipStreamSynchronize(stream);
+  quiesce();
+  root->trim();
+}
+
+void Alloc::release_all() {
+  quiesce();
+  trim();
 }
 
 bool Alloc::owns(const void *p) {
   const uintptr_t a = reinterpret_cast<uintptr_t>(p);
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = live.upper_bound(a);
-  if (it == live.begin()) return false;
+  Alloc *r = root;
+  std::lock_guard<std::mutex> lk(r->mu);
+  auto it = r->live.upper_bound(a);
+  if (it == r->live.begin()) return false;
   --it;
-  return a < it->first + it->second;
+  return a < it->first + it->second - kSlack;
 }
 
 }  // namespace mlcc
@@ -109,7 +201,7 @@ void mlcc_problem::fetch_n(const double *dev, double *host, int n) {
 template <typename T>
 void mlcc_problem::setup_t(const double *Lsrc, bool dev, const uint64_t *synth_seed) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O;
   const size_t nL = (size_t)J * n2;
   // FP64 staging copy of L (the input), used for h and converted if FP32
@@ -171,7 +263,7 @@ __global__ void k_add_diag(int64_t n, const double *eps, double *h) {
 
 void mlcc_problem::setup(const mlcc_problem_desc &desc) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   d.O = desc.n_occ;
   d.V = desc.n_vir;
   d.J = desc.n_chol;
@@ -283,7 +375,7 @@ void x1_blocks(Exec &x, Prec p, const Dims &d, const T *src, T *dst, int64_t Z, 
 
 template <typename T> void mlcc_problem::dress_t(bool full_fock) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v;
   const Prec p = gemm_prec<T>();
   t1T.ensure(al, d.n1 * sizeof(T));
@@ -327,7 +419,7 @@ template <typename T> void mlcc_problem::dress_t(bool full_fock) {
 // u = 2x - x(i<->j) and Z^K_ai = sum_bj u_ai,bj L^K_bj.
 template <typename T> void mlcc_problem::doubles_mlcc2_t() {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, M = d.M;
   const Prec p = gemm_prec<T>();
   u.ensure(al, (size_t)M * M * sizeof(T));
@@ -368,7 +460,7 @@ int mlcc_problem::occ_batch(int nz) const {
 // writes s to the full a-major s2 array.
 template <typename T> void mlcc_problem::doubles_pairblocks_t(bool keep_u) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, M = d.M, o = d.o, v = d.v;
   const Prec p = gemm_prec<T>();
   // L~_ai pair-major, LaiT[ai][K] (reduction index contiguous)
@@ -426,7 +518,7 @@ template <typename T> void mlcc_problem::doubles_pairblocks_t(bool keep_u) {
 template <typename T>
 void mlcc_problem::omega_singles_t(const void *Zb, const void *ub, double *om1, bool add_fock) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
   const Prec p = gemm_prec<T>();
   if (add_fock) k::pack2d<double, double>(x, om1, Ft.as<double>() + O * n, 1, 0, V, O, n);
@@ -508,7 +600,7 @@ void mlcc_problem::compute_state(bool full_fock, bool keep_u) {
 // ---------------------------------------------------------------------------
 template <typename T> void mlcc_problem::prepare_jacobian_t() {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
   const Prec p = gemm_prec<T>();
   compute_state_t<T>(true, true);
@@ -543,7 +635,7 @@ template <typename T>
 void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool has_c2,
                                      double *sigma, double w_eff) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, n = d.n, n2 = d.n2, O = d.O, V = d.V, o = d.o, v = d.v, M = d.M;
   const int64_t n1 = d.n1, b = nb;
   const Prec p = gemm_prec<T>();
@@ -658,7 +750,7 @@ void mlcc_problem::transform_batch_t(int nb, const double *c, int64_t ld, bool h
 // Zc_J += L_I u_JI^T.  Zc[K][vec][i][a] (K = J: the F~_jb row).
 template <typename T> void mlcc_problem::eff_doubles_pairblocks_t(int nb, double w) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, M = d.M, o = d.o, v = d.v, b = nb;
   const Prec p = gemm_prec<T>();
   const int ob = occ_batch(nb);
@@ -711,7 +803,7 @@ template <typename T>
 void mlcc_problem::full_doubles_to_singles_t(int nb, const double *c, int64_t ld, bool has_c2,
                                             double *sigma, double w_eff) {
   Exec &x = *ex;
-  Alloc *al = &ctx->al;
+  Alloc *al = ex->al;
   const int64_t J = d.J, n = d.n, O = d.O, M = d.M, n1 = d.n1, b = nb;
   const Prec p = gemm_prec<T>();
   const bool o64 = sizeof(T) == 8;

@@ -164,8 +164,8 @@ struct mlcc_problem {
   }
   void ensure_doubles() {
     if (model == MLCC_MLCC2 && d.M > 0) {
-      s2.ensure(&ctx->al, (size_t)d.M * d.M * sizeof(double));
-      o2.ensure(&ctx->al, (size_t)d.M * d.M * sizeof(double));
+      s2.ensure(ex->al, (size_t)d.M * d.M * sizeof(double));
+      o2.ensure(ex->al, (size_t)d.M * d.M * sizeof(double));
     }
   }
   // occupied indices per block of the pair-blocked doubles, for nz vectors

@@ -46,6 +46,7 @@ struct Request {
 
 struct Lane {
   Exec ex;
+  Alloc al;  // the lane's stream-ordered cache over the context's allocator
 };
 
 double now_s(std::chrono::steady_clock::time_point t0) {
@@ -175,10 +176,12 @@ void mlcc_server::work(Lane *lane) {
     } catch (...) {
       st = MLCC_E_DEVICE;
     }
-    // the lane's split and reduction scratch go back with the request's footprint
+    // the lane's split and reduction scratch go back with the request's
+    // footprint; with the stream idle, its cached blocks serve every lane
     (void)hipStreamSynchronize(lane->ex.stream);
     lane->ex.work.release();
     lane->ex.red.release();
+    lane->al.quiesce();
     drop_host();
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -223,11 +226,14 @@ mlcc_status mlcc_server_create(mlcc_context *ctx, const mlcc_server_opts *opts,
   s->adm = std::make_unique<Admission<Request>>(budget, host_budget, max_queue);
   for (int i = 0; i < s->max_slots; ++i) {
     auto lane = std::make_unique<Lane>();
-    lane->ex.al = &ctx->al;
+    lane->al.root = &ctx->al;
+    lane->al.device = ctx->device;
+    lane->ex.al = &lane->al;
     const bool ok =
         hipStreamCreateWithFlags(&lane->ex.stream, hipStreamNonBlocking) == hipSuccess &&
         hipHostMalloc((void **)&lane->ex.pinned, 512 * sizeof(double), hipHostMallocDefault) ==
             hipSuccess;
+    lane->al.stream = lane->ex.stream;
     s->lanes.push_back(std::move(lane));
     if (!ok) {
       (void)hipGetLastError();
@@ -258,8 +264,10 @@ mlcc_status mlcc_server_destroy(mlcc_server *s) {
   for (auto &t : s->workers) t.join();
   for (auto &kv : s->table) delete kv.second;
   for (auto &l : s->lanes) {
+    if (l->ex.stream) (void)hipStreamSynchronize(l->ex.stream);
     l->ex.work.release();
     l->ex.red.release();
+    l->al.quiesce();
     if (l->ex.stream) (void)hipStreamDestroy(l->ex.stream);
     if (l->ex.pinned) (void)hipHostFree(l->ex.pinned);
   }
