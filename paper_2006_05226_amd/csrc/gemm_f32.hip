@@ -2,6 +2,7 @@
 // 16-byte groups throughout (FP32 MFMA, or split products on the BF16
 // matrix cores).
 #include "gemm_kernel.h"
+#include "gemm_split.h"
 
 namespace mlcc {
 namespace {
