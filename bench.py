@@ -624,7 +624,8 @@ def main():
         x = {k: val for k, val in e.items() if k != "stats"}
         x["contractions"] = _contractions(e["stats"], args.steps)
         x["sustained_tflops"] = flops_vec * e["transforms_per_s"] / 1e12
-        _, x["roofline"] = _dominant_roofline(e["stats"], p)
+        dom_p, x["roofline"] = _dominant_roofline(e["stats"], p)
+        x["roofline"]["traffic"] = _profiled_traffic(dom_p, C4, p)
         extra[p] = x
     for p in ("fp32", "bf16x3"):
         if p in res and "fp64" in res:
