@@ -50,9 +50,11 @@ sys.path.insert(0, ROOT)
 # dense MFMA peaks of MI355X; a split-BF16 product is three dense BF16 MFMAs
 # (2.5 PFLOP/s), so its FP32-equivalent peak is 2500 / 3
 BF16_DENSE_TFLOPS = 2500.0
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": BF16_DENSE_TFLOPS / 3.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": BF16_DENSE_TFLOPS / 3.0,
+               "bf16": BF16_DENSE_TFLOPS}
 PEAK_NOTE = {"fp64": "FP64 MFMA", "fp32": "FP32 MFMA",
-             "bf16x3": "BF16 MFMA / 3 (each FP32-accurate product is hi*hi + hi*lo + lo*hi)"}
+             "bf16x3": "BF16 MFMA / 3 (each FP32-accurate product is hi*hi + hi*lo + lo*hi)",
+             "bf16": "BF16 MFMA (the dominant contraction is on the plain-BF16 map: one product)"}
 C4 = "mlcc2_150_1200_3600"
 # the CPU-baseline sample: the same model family at a size the oracle runs in seconds
 SAMPLE = dict(n_occ=30, n_vir=240, n_chol=720, n_occ_act=10, n_vir_act=100)
@@ -229,11 +231,62 @@ def _mlccsd_leg(mlcc, steps, warmup, precisions, config="mlccsd_60_600_2000", nv
         ctx.close()
         del cd, sd
         torch.cuda.empty_cache()
-    if "fp64" in out and "fp32" in out:
-        out["speedup_fp32_vs_fp64"] = out["fp32"]["transforms_per_s"] / out["fp64"]["transforms_per_s"]
-        out["fp32_minus_fp64"] = dict(
-            e_corr=out["fp32"]["e_corr"] - out["fp64"]["e_corr"],
-            omega=[a - b for a, b in zip(out["fp32"]["omega"], out["fp64"]["omega"])])
+    for p in ("fp32", "bf16x3", "bf16"):
+        if "fp64" in out and p in out:
+            out[f"speedup_{p}_vs_fp64"] = out[p]["transforms_per_s"] / out["fp64"]["transforms_per_s"]
+            out[f"{p}_minus_fp64"] = dict(
+                e_corr=out[p]["e_corr"] - out["fp64"]["e_corr"],
+                omega=[a - b for a, b in zip(out[p]["omega"], out["fp64"]["omega"])])
+    return out
+
+
+def _bf16_study(mlcc, configs=("mlcc2_40_400_1200", "mlccsd_60_600_2000"), gs_tol=1e-6, es_tol=1e-6):
+    """Which contractions may run plain BF16 products (precision "bf16")?
+    For each workload with FP64 oracle reference values (tests/golden), every
+    contraction seen in a split-BF16 solve is run alone in plain BF16 (its
+    operands rounded to BF16, one product, FP32 accumulation) and the ground
+    state energy and roots are compared with the references; then all that
+    pass together.  Bar: 1e-6 Eh and 1e-5 eV."""
+    import numpy as np
+    from paper_2006_05226_amd.synth import CONFIGS, gen_inputs
+    ev = 27.211386245988
+    out = {}
+    for name in configs:
+        with open(os.path.join(ROOT, "tests", "golden", f"reference_{name}.json")) as f:
+            ref = json.load(f)
+        c = CONFIGS[name]
+        inp = gen_inputs(seed=0, **c)
+        assert inp.digest() == ref["inputs_sha256_16"]
+        ctx = mlcc.Context(0)
+
+        def solve(tags):
+            ctx.bf16_map(tags)
+            P = mlcc.Problem(ctx, inp.L, inp.eps, c["n_occ"], c["n_vir"], c["n_occ_act"],
+                             c["n_vir_act"], model=ref["model"], precision="bf16")
+            t0 = time.perf_counter()
+            g = P.ground_state(tol=gs_tol)
+            d = P.davidson(len(ref["omega"]), tol=es_tol)
+            sec = time.perf_counter() - t0
+            P.close()
+            de = abs(g["energy"] - ref["e_corr"])
+            dw = float(np.abs(np.array(d["omega"]) - np.array(ref["omega"])).max())
+            return dict(d_e_eh=de, d_omega_ev=dw * ev, seconds=sec,
+                        ok=bool(g["converged"] and d["converged"] and de < 1e-6 and dw * ev < 1e-5))
+
+        ctx.profile(True)
+        base = solve([])
+        tags = sorted(k for k in ctx.profile_stats() if k != "gemm")
+        ctx.profile(False)
+        rows = {"(none: split BF16 throughout)": base}
+        for tag in tags:
+            print(f"bf16 study {name}: {tag}", file=sys.stderr, flush=True)
+            rows[tag] = solve([tag])
+        passing = [t for t in tags if rows[t]["ok"]]
+        rows["(all passing together)"] = solve(passing)
+        out[name] = dict(rows=rows, passing=passing)
+        ctx.close()
+    common = sorted(set.intersection(*[set(v["passing"]) for v in out.values()]))
+    out["passing_everywhere"] = common
     return out
 
 
@@ -416,7 +469,7 @@ def _c2_leg(mlcc, steps, warmup, precisions, nvec=4, solves=True):
         ctx.close()
         del cd, sd
         torch.cuda.empty_cache()
-    for p in ("fp32", "bf16x3"):
+    for p in ("fp32", "bf16x3", "bf16"):
         if p in out and "fp64" in out:
             out[f"speedup_{p}_vs_fp64"] = out[p]["transforms_per_s"] / out["fp64"]["transforms_per_s"]
     return out
@@ -441,14 +494,15 @@ def _cholesky_leg(mlcc, precisions, n_ao=160, n_aux=480, n_mo=120, n_act=40, rel
     ctx = mlcc.Context(0)
     Gd = torch.tensor(G, device="cuda")
     Cd = torch.tensor(Cmo, device="cuda")
+    cap = n_aux + 64  # the integrals have rank n_aux
     for name, w in (("standard", None), ("mo_screened", nu)):
         print(f"cholesky basis: {name}", file=sys.stderr, flush=True)
-        ctx.cholesky_basis(n_ao, Gd, tau, nu=w)   # warm-up (library start-up)
+        ctx.cholesky_basis(n_ao, Gd, tau, nu=w, max_vectors=cap)   # warm-up (library start-up)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        piv, QiT = ctx.cholesky_basis(n_ao, Gd, tau, nu=w)
+        piv, QiT = ctx.cholesky_basis(n_ao, Gd, tau, nu=w, max_vectors=cap)
         out[f"basis_{name}"] = dict(n_vectors=len(piv), seconds=time.perf_counter() - t0)
-    piv, QiT = ctx.cholesky_basis(n_ao, Gd, tau)
+    piv, QiT = ctx.cholesky_basis(n_ao, Gd, tau, max_vectors=cap)
     nJ = len(piv)
     flops = nJ * (2.0 * n_mo * n_ao * n_ao + 2.0 * n_mo * n_mo * n_ao) + 2.0 * nJ * nJ * n_mo * n_mo
     out["algorithm1_flops"] = flops
@@ -573,7 +627,7 @@ def main():
     ap.add_argument("--nvec", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-solves", action="store_true", help="skip the Davidson solves")
-    ap.add_argument("--precisions", default="fp64,fp32,bf16x3")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16x3,bf16")
     ap.add_argument("--no-c2", action="store_true", help="skip the 40/400/1200 full-space leg")
     ap.add_argument("--no-mlccsd", action="store_true", help="skip the MLCCSD leg")
     ap.add_argument("--no-mlccsd3", action="store_true", help="skip the three-level MLCCSD leg")
@@ -585,6 +639,8 @@ def main():
     ap.add_argument("--serve", type=int, default=256,
                     help="requests in the serving stream (0 = skip; 256 = the full stream)")
     ap.add_argument("--slots", type=int, default=8)
+    ap.add_argument("--bf16-study", action="store_true",
+                    help="only the per-contraction plain-BF16 accuracy study (prints its JSON)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -596,6 +652,10 @@ def main():
     import torch
 
     from paper_2006_05226_amd import mlcc
+
+    if args.bf16_study:
+        print(json.dumps(_bf16_study(mlcc)))
+        return
 
     if args.copy_calibration:
         src = torch.ones(1 << 26, dtype=torch.float64, device="cuda")  # 512 MiB
@@ -627,7 +687,7 @@ def main():
         dom_p, x["roofline"] = _dominant_roofline(e["stats"], p)
         x["roofline"]["traffic"] = _profiled_traffic(dom_p, C4, p)
         extra[p] = x
-    for p in ("fp32", "bf16x3"):
+    for p in ("fp32", "bf16x3", "bf16"):
         if p in res and "fp64" in res:
             extra[f"speedup_{p}_vs_fp64"] = res[p]["transforms_per_s"] / res["fp64"]["transforms_per_s"]
             d = dict(e_corr_eh=res[p]["e_corr"] - res["fp64"]["e_corr"])

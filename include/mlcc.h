@@ -94,6 +94,13 @@ typedef int32_t mlcc_status;
  * hi*hi + hi*lo + lo*hi (x = hi + lo, hi = bf16(x), lo = bf16(x - hi); FP32
  * accumulation), the others on FP32 MFMA; FP64 elsewhere as for MLCC_FP32. */
 #define MLCC_BF16X3 2
+/* As MLCC_BF16X3, except that the contractions named in the context's BF16
+ * map (mlcc_bf16_map, include/mlcc_engine.h) run one BF16 product of
+ * operands rounded to BF16 (FP32 accumulation) instead of three.  The
+ * built-in map holds the contractions whose plain BF16 products keep the
+ * energies within 1e-6 Eh and the excitation energies within 1e-5 eV of FP64
+ * on the 40/400/1200 MLCC2 and 60/600/2000 MLCCSD workloads. */
+#define MLCC_BF16 3
 
 typedef struct mlcc_context mlcc_context;
 typedef struct mlcc_problem mlcc_problem;
@@ -103,7 +110,7 @@ typedef struct {
   int32_t n_occ, n_vir, n_chol;   /* N_o, N_v, N_J */
   int32_t n_occ_act, n_vir_act;   /* active prefixes (ignored for MLCC_CCS) */
   int32_t model;                  /* MLCC_CCS | MLCC_MLCC2 | MLCC_MLCCSD | MLCC_MLCCSD3 */
-  int32_t precision;              /* MLCC_FP64 | MLCC_FP32 | MLCC_BF16X3 */
+  int32_t precision;              /* MLCC_FP64 | MLCC_FP32 | MLCC_BF16X3 | MLCC_BF16 */
   const double *L;                /* [n_chol][n][n], symmetric in the last two */
   const double *eps;              /* [n] orbital energies in the order above */
   uint32_t flags;                 /* MLCC_SYNTH_L, or 0 */

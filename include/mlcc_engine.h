@@ -46,6 +46,14 @@ mlcc_status mlcc_gemm2(mlcc_context *ctx, int32_t prec, int64_t M, int64_t N, in
                        const void *B, const int64_t sB[4], double beta, void *C,
                        const int64_t sC[3], const int64_t lvl[6]);
 
+/* ---- the plain-BF16 map of MLCC_BF16 -------------------------------------
+ * tags: comma-separated contraction names (as mlcc_profile_get reports them)
+ * whose products run as one BF16 product in MLCC_BF16 on this context, ""
+ * for none, or NULL for the built-in map.  For tuning and for the accuracy
+ * study that chose the built-in map.  Applies to problems and servers
+ * created after the call; MLCC_E_ARG for a NULL context. */
+mlcc_status mlcc_bf16_map(mlcc_context *ctx, const char *tags);
+
 /* ---- the engine without allocation ----------------------------------------
  * For callers that cannot allocate device memory while they run: code being
  * captured into a HIP graph, tight serving loops, hosts that forbid

@@ -47,6 +47,18 @@ struct Out {
   }
 };
 
+// Contractions whose plain BF16 products keep the energies within 1e-6 Eh and
+// the excitation energies within 1e-5 eV of FP64 on the 40/400/1200 MLCC2
+// and 60/600/2000 MLCCSD workloads (the study that picked them is
+// bench.py --bf16-study), each alone and all together.  Left out: the
+// MLCCSD E2 term (with it in plain BF16 the ground state no longer reaches
+// 1e-6), and untagged and orbital-selection products.
+const std::vector<std::string> kBf16Map = {
+    "x1_vv",  "x1_vo",   "fock_exch", "g_aibj", "Z_uL",     "ccs_Xk",    "ccs_coul",  "ccs_W",
+    "ccs_vv", "jac_X",   "jac_Y",     "jac_q",  "jac_P",    "jac_r",     "jac_uw",    "dLai",
+    "sigma2_LdL", "Zc_uL", "d2s_A1",  "d2s_B1", "cc_g",     "cc_g_vvvv", "cc_ladder", "cc_B2",
+    "cc_C2",  "cc_D2",   "cc_Gk",     "cc_Y3",  "cc_Y3c",   "cc_dL",     "cc_dg",     "cc_dF"};
+
 void check_desc(const mlcc_problem_desc *d) {
   MLCC_REQUIRE(d != nullptr, MLCC_E_ARG, "NULL problem descriptor");
   MLCC_REQUIRE((d->L != nullptr || (d->flags & MLCC_SYNTH_L)) && d->eps != nullptr, MLCC_E_ARG,
@@ -62,7 +74,7 @@ void check_desc(const mlcc_problem_desc *d) {
                      d->n_vir_ccsd <= d->n_vir_act,
                  MLCC_E_ARG, "CCSD space not inside the active space");
   MLCC_REQUIRE(d->precision == MLCC_FP64 || d->precision == MLCC_FP32 ||
-                   d->precision == MLCC_BF16X3,
+                   d->precision == MLCC_BF16X3 || d->precision == MLCC_BF16,
                MLCC_E_ARG, "unknown precision");
   if (d->model != MLCC_CCS) {
     MLCC_REQUIRE(d->n_occ_act >= 0 && d->n_occ_act <= d->n_occ && d->n_vir_act >= 0 &&
@@ -93,6 +105,8 @@ mlcc_status mlcc_context_create(int device, void *hip_stream, uint64_t hbm_budge
     c->al.budget = hbm_budget;
     c->ex.al = &c->al;
     c->ex.prof = &c->prof;
+    c->bf16_map = kBf16Map;
+    c->ex.bf16_map = &c->bf16_map;
     if (hip_stream) {
       c->ex.stream = static_cast<hipStream_t>(hip_stream);
     } else {
@@ -122,6 +136,29 @@ mlcc_status mlcc_context_destroy(mlcc_context *ctx) {
   if (!ctx) return MLCC_E_ARG;
   context_unref(ctx);
   return MLCC_OK;
+}
+
+mlcc_status mlcc_bf16_map(mlcc_context *ctx, const char *tags) {
+  if (!ctx) return MLCC_E_ARG;
+  return guarded(ctx, [&]() -> mlcc_status {
+    std::vector<std::string> m;
+    if (!tags) {
+      m = kBf16Map;
+    } else {
+      std::string cur;
+      for (const char *c = tags;; ++c) {
+        if (*c == ',' || *c == '\0') {
+          if (!cur.empty()) m.push_back(cur);
+          cur.clear();
+          if (*c == '\0') break;
+        } else if (*c != ' ') {
+          cur.push_back(*c);
+        }
+      }
+    }
+    ctx->bf16_map.swap(m);
+    return MLCC_OK;
+  });
 }
 
 const char *mlcc_last_error(mlcc_context *ctx) {

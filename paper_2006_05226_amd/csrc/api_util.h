@@ -77,8 +77,8 @@ inline void check_engine_args(int32_t prec, int64_t M, int64_t N, int64_t K, int
                               int64_t Z, const void *A, const int64_t *sA, const void *B,
                               const int64_t *sB, void *C, const int64_t *sC, const int64_t *lvl,
                               const char *who) {
-  MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32 || prec == MLCC_BF16X3, MLCC_E_ARG,
-               "bad precision");
+  MLCC_REQUIRE(prec == MLCC_FP64 || prec == MLCC_FP32 || prec == MLCC_BF16X3 || prec == MLCC_BF16,
+               MLCC_E_ARG, "bad precision");
   MLCC_REQUIRE(M >= 0 && N >= 0 && K >= 0 && R >= 1 && Z >= 1, MLCC_E_ARG, "bad sizes");
   MLCC_REQUIRE(A && B && C && sA && sB && sC, MLCC_E_ARG, "NULL argument");
   MLCC_REQUIRE(!lvl || (lvl[0] >= 0 && lvl[3] >= 0), MLCC_E_ARG, "bad two-level sizes");
@@ -87,7 +87,10 @@ inline void check_engine_args(int32_t prec, int64_t M, int64_t N, int64_t K, int
 }
 
 inline Prec engine_prec(int32_t prec) {
-  return prec == MLCC_FP64 ? Prec::F64 : prec == MLCC_FP32 ? Prec::F32 : Prec::BF16X3;
+  return prec == MLCC_FP64   ? Prec::F64
+         : prec == MLCC_FP32 ? Prec::F32
+         : prec == MLCC_BF16 ? Prec::BF16
+                             : Prec::BF16X3;
 }
 
 // Address of the no-allocation scratch array on the current device (noalloc.hip).

@@ -350,7 +350,8 @@ mlcc_status mlcc_mo_cholesky(mlcc_context *ctx, int32_t precision, int32_t n_ao,
                              double *L_out) {
   if (!ctx) return MLCC_E_ARG;
   return guarded(ctx, [&]() -> mlcc_status {
-    MLCC_REQUIRE(precision == MLCC_FP64 || precision == MLCC_FP32 || precision == MLCC_BF16X3,
+    MLCC_REQUIRE(precision == MLCC_FP64 || precision == MLCC_FP32 || precision == MLCC_BF16X3 ||
+                     precision == MLCC_BF16,
                  MLCC_E_ARG, "unknown precision");
     MLCC_REQUIRE(n_ao >= 1 && n_ao <= 4096 && n_mo >= 1 && n_mo <= n_ao, MLCC_E_ARG,
                  "bad orbital counts");

@@ -551,9 +551,10 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm(KParams kp) {
 }
 
 
-// The split-BF16 kernel (FP32 operands on the BF16 matrix cores); defined in
-// gemm_split.h, which the FP32 instantiation units include.
-template <typename TC, int BM, int BN>
+// The split-BF16 kernel (FP32 operands on the BF16 matrix cores; PLAIN: one
+// product of the operands rounded to BF16); defined in gemm_split.h, which
+// the FP32 instantiation units include.
+template <typename TC, int BM, int BN, bool PLAIN>
 __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams kp);
 
 template <typename TA, typename TC>
@@ -611,7 +612,8 @@ inline bool gemm_split_ok(const GemmArgs &a) {
   return a.bf16x3 && !akm && !bkn && gemm_vonly(a, Tr<float>::VEC);
 }
 
-template <typename T, typename TC, int BM, int BN, bool VONLY, bool SPLIT = false>
+// SPLIT: 0 the FP64 / FP32 MFMA kernel, 1 split BF16 products, 2 plain BF16
+template <typename T, typename TC, int BM, int BN, bool VONLY, int SPLIT = 0>
 void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   constexpr int BK = Tr<T>::BK, VEC = Tr<T>::VEC;
   KParams kp;
@@ -650,7 +652,7 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
   if constexpr (SPLIT) {
     static_assert(sizeof(T) == 4, "split products take FP32 operands");
     MLCC_REQUIRE(!akm && !bkn, MLCC_E_ARG, "gemm: split products need k-contiguous operands");
-    hipLaunchKernelGGL((k_gemm_split<TC, BM, BN>), grid, block, 0, ex.stream, kp);
+    hipLaunchKernelGGL((k_gemm_split<TC, BM, BN, SPLIT == 2>), grid, block, 0, ex.stream, kp);
   } else if (akm && bkn)
     hipLaunchKernelGGL((k_gemm<T, TC, BM, BN, true, true, VONLY>), grid, block, 0, ex.stream, kp);
   else if (akm)
@@ -675,7 +677,7 @@ void launch_tile(Exec &ex, const GemmArgs &a, int splits) {
 
 // Resident blocks per CU of the kernel launch_tile runs for this layout (the
 // compiled register and LDS use decide it), queried once per variant.
-template <typename T, typename TC, int BM, int BN, bool VONLY, bool SPLIT = false>
+template <typename T, typename TC, int BM, int BN, bool VONLY, int SPLIT = 0>
 int tile_occupancy(const GemmArgs &a) {
   static std::atomic<int> cache[4];
   const bool akm = std::llabs(a.sAm) < std::llabs(a.sAk);
@@ -684,7 +686,7 @@ int tile_occupancy(const GemmArgs &a) {
   int nb = cache[v].load(std::memory_order_relaxed);
   if (nb > 0) return nb;
   const void *f;
-  if constexpr (SPLIT) f = reinterpret_cast<const void *>(&k_gemm_split<TC, BM, BN>);
+  if constexpr (SPLIT) f = reinterpret_cast<const void *>(&k_gemm_split<TC, BM, BN, SPLIT == 2>);
   else if (akm && bkn) f = reinterpret_cast<const void *>(&k_gemm<T, TC, BM, BN, true, true, VONLY>);
   else if (akm) f = reinterpret_cast<const void *>(&k_gemm<T, TC, BM, BN, true, false, VONLY>);
   else if (bkn) f = reinterpret_cast<const void *>(&k_gemm<T, TC, BM, BN, false, true, VONLY>);

@@ -18,7 +18,7 @@ namespace gk {
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf4v __attribute__((ext_vector_type(4)));
 
-template <typename TC, int BM, int BN>
+template <typename TC, int BM, int BN, bool PLAIN>
 __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams kp) {
   typedef WaveGrid<BM, BN> WG;
   constexpr int BK = Tr<float>::BK, VEC = Tr<float>::VEC, LEN = BK + 8;  // 80-byte rows
@@ -27,11 +27,13 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams k
   typedef Stage<float, BM, false, true, WG::NT> SA;
   typedef Stage<float, BN, false, true, WG::NT> SB;
   __shared__ __attribute__((aligned(16))) __bf16 Ah[2][BM][LEN];
-  __shared__ __attribute__((aligned(16))) __bf16 Al[2][BM][LEN];
+  __shared__ __attribute__((aligned(16))) __bf16 Al[2][PLAIN ? 1 : BM][LEN];
   __shared__ __attribute__((aligned(16))) __bf16 Bh[2][BN][LEN];
-  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][BN][LEN];
+  __shared__ __attribute__((aligned(16))) __bf16 Bl[2][PLAIN ? 1 : BN][LEN];
 
   const GemmArgs &p = kp.a;
+  // plain BF16: hi products only, no lo planes
+  constexpr bool plain = PLAIN;
   const int64_t L = blockIdx.x;
   const int64_t w = (L % kXcd) * kp.per_xcd + L / kXcd;
   if (w >= kp.nwork) return;
@@ -79,17 +81,17 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams k
       l[q] = (__bf16)(x[q] - (float)h[q]);
     }
     *reinterpret_cast<bf4v *>(hi) = h;
-    *reinterpret_cast<bf4v *>(lo) = l;
+    if constexpr (!plain) *reinterpret_cast<bf4v *>(lo) = l;
   };
   auto store = [&](int buf) {
     sa.mask(ra);
     sb.mask(rb);
 #pragma unroll
     for (int e = 0; e < SA::U; ++e)
-      split_store(ra[e], &Ah[buf][sa.row[e]][sa.col[e]], &Al[buf][sa.row[e]][sa.col[e]]);
+      split_store(ra[e], &Ah[buf][sa.row[e]][sa.col[e]], plain ? nullptr : &Al[buf][sa.row[e]][sa.col[e]]);
 #pragma unroll
     for (int e = 0; e < SB::U; ++e)
-      split_store(rb[e], &Bh[buf][sb.row[e]][sb.col[e]], &Bl[buf][sb.row[e]][sb.col[e]]);
+      split_store(rb[e], &Bh[buf][sb.row[e]][sb.col[e]], plain ? nullptr : &Bl[buf][sb.row[e]][sb.col[e]]);
   };
 
   int cur = 0;
@@ -106,29 +108,31 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams k
     for (int i = 0; i < FM; ++i) {
       const int r = wm * WTM + i * 16 + l16;
       ah[i] = *reinterpret_cast<const bf8v *>(&Ah[cur][r][g * 8]);
-      al[i] = *reinterpret_cast<const bf8v *>(&Al[cur][r][g * 8]);
+      if constexpr (!plain) al[i] = *reinterpret_cast<const bf8v *>(&Al[cur][r][g * 8]);
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
       const int r = wn * WTN + j * 16 + l16;
       bh[j] = *reinterpret_cast<const bf8v *>(&Bh[cur][r][g * 8]);
-      bl[j] = *reinterpret_cast<const bf8v *>(&Bl[cur][r][g * 8]);
+      if constexpr (!plain) bl[j] = *reinterpret_cast<const bf8v *>(&Bl[cur][r][g * 8]);
     }
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
       for (int j = 0; j < FN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    if constexpr (!plain) {
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+    }
     if (more) store(cur ^ 1);
     __syncthreads();
     cur ^= 1;
@@ -139,7 +143,9 @@ __global__ __launch_bounds__((WaveGrid<BM, BN>::NT)) void k_gemm_split(KParams k
 }  // namespace gk
 }  // namespace mlcc
 
-// Tile menu of the split products.
+// Tile menus of the split products and of the plain BF16 products.
+#define MLCC_GEMM_TILES_PLAIN(X) \
+  X(128, 128) X(128, 64) X(64, 128) X(96, 160) X(160, 96) X(64, 64) X(128, 32) X(32, 128) X(32, 32)
 #define MLCC_GEMM_TILES_SPLIT(X) \
   X(128, 128) X(128, 96) X(96, 128) X(128, 64) X(64, 128) X(96, 96) X(64, 64) X(128, 32) X(32, 128) \
   X(64, 32) X(32, 64) X(32, 32) X(96, 160) X(160, 96)

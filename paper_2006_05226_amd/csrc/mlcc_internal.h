@@ -144,6 +144,9 @@ struct Exec {
   // tuning): a forced bm x bn is used by every call whose menu has it; the
   // tile of the lane's last dispatched call is kept.
   int force_bm = 0, force_bn = 0, last_bm = 0, last_bn = 0;
+  // contraction tags that run plain BF16 products under Prec::BF16 (the
+  // context's map; set before problems or servers are created)
+  const std::vector<std::string> *bf16_map = nullptr;
   void *scratch(size_t bytes) {
     work.ensure(al, bytes);
     return work.p;
@@ -156,7 +159,9 @@ struct Exec {
 // F32: FP32 operands on FP32 MFMA; BF16X3: FP32 operands on the BF16 matrix
 // cores as hi*hi + hi*lo + lo*hi where the operand layout allows it, FP32
 // MFMA elsewhere.
-enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2 };
+// BF16: as BF16X3, except the contractions named in the lane's BF16 map,
+// which run one BF16 product of operands rounded to BF16 (FP32 accumulation).
+enum class Prec : int { F64 = 0, F32 = 1, BF16X3 = 2, BF16 = 3 };
 
 struct GemmArgs {
   int64_t M = 0, N = 0, K = 0, R = 1, Z = 1;
@@ -180,6 +185,8 @@ struct GemmArgs {
   bool slack = false;
   // set by gemm(): FP32 operands may run on the BF16 matrix cores (split products)
   bool bf16x3 = false;
+  // set by gemm(): a plain BF16 product (Prec::BF16 and a tag of the BF16 map)
+  bool bf16_plain = false;
   // Optional orbital-energy denominator applied in FP64 by the epilogue:
   //   C[m][n] = (alpha * acc + beta * Cin[m][n]) / (den_row[m] + den_col[n] + den_shift)
   // (m, n: output row and column indices, before any two-level mapping).

@@ -8,6 +8,8 @@
 #include "mlcc_internal.h"
 
 struct mlcc_context {
+  // contractions that run plain BF16 products in MLCC_BF16 (mlcc_bf16_map)
+  std::vector<std::string> bf16_map;
   // references: the creator's, one per problem created on it and one per
   // server; the context is freed when the last one is dropped, so that
   // destroying it before its problems is safe
@@ -151,7 +153,9 @@ struct mlcc_problem {
   // BF16 products)
   template <typename T> mlcc::Prec gemm_prec() const {
     return sizeof(T) == 8 ? mlcc::Prec::F64
-                          : (prec == MLCC_BF16X3 ? mlcc::Prec::BF16X3 : mlcc::Prec::F32);
+                          : prec == MLCC_BF16X3 ? mlcc::Prec::BF16X3
+                          : prec == MLCC_BF16   ? mlcc::Prec::BF16
+                                                : mlcc::Prec::F32;
   }
   double *t1() const { return amp.as<double>(); }
   // doubles amplitudes and residual: MLCCSD t2 after t1; MLCC2 s2 in its own

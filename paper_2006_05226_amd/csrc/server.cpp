@@ -229,6 +229,7 @@ mlcc_status mlcc_server_create(mlcc_context *ctx, const mlcc_server_opts *opts,
     lane->al.root = &ctx->al;
     lane->al.device = ctx->device;
     lane->ex.al = &lane->al;
+    lane->ex.bf16_map = &ctx->bf16_map;
     const bool ok =
         hipStreamCreateWithFlags(&lane->ex.stream, hipStreamNonBlocking) == hipSuccess &&
         hipHostMalloc((void **)&lane->ex.pinned, 512 * sizeof(double), hipHostMallocDefault) ==

@@ -21,8 +21,8 @@ E_ARG, E_OOM, E_NOCONV, E_NUMERIC, E_DEVICE, E_BUSY, E_STATE = -1, -2, -3, -4, -
 CCS, MLCC2, MLCCSD, MLCCSD3 = 0, 1, 2, 3
 FP64, FP32 = 0, 1
 MODEL = {"ccs": CCS, "mlcc2": MLCC2, "mlccsd": MLCCSD, "mlccsd3": MLCCSD3}
-BF16X3 = 2
-PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+BF16X3, BF16 = 2, 3
+PREC = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16": BF16}
 
 _STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_ARG", -2: "E_OOM", -3: "E_NOCONV",
                  -4: "E_NUMERIC", -5: "E_DEVICE", -6: "E_BUSY", -7: "E_STATE"}
@@ -73,7 +73,7 @@ EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "ml
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
            "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_gemm_noalloc",
            "mlcc_debug_get", "mlcc_profile_enable", "mlcc_profile_get", "mlcc_gemm_tile", "mlcc_cnto",
-           "mlcc_pair_block_occ", "mlcc_cholesky_basis", "mlcc_mo_cholesky"]
+           "mlcc_pair_block_occ", "mlcc_cholesky_basis", "mlcc_mo_cholesky", "mlcc_bf16_map"]
 
 NOALLOC_SCRATCH_BYTES = 16 << 20
 
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH):
         "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
         "mlcc_gemm_tile": (i32, [vp, i32, i32, P(i32)]),
         "mlcc_pair_block_occ": (i32, [vp, i32]),
+        "mlcc_bf16_map": (i32, [vp, C.c_char_p]),
         "mlcc_cholesky_basis": (i32, [vp, i32, vp, vp, dbl, i32, vp, P(i32), vp]),
         "mlcc_mo_cholesky": (i32, [vp, i32, i32, i32, vp, i32, vp, vp, vp, i32, vp]),
         "mlcc_cnto": (i32, [vp, i32, vp, vp, i32, i32, vp, vp, vp, vp, vp, vp]),
@@ -214,6 +215,13 @@ class Context:
         self.check(self.lib.mlcc_gemm_tile(self.h, bm, bn, last))
         return (last[0], last[1])
 
+    def bf16_map(self, tags=None):
+        """Contractions that run plain BF16 products in precision "bf16" on
+        problems created afterwards: a list of names, [] for none, None for
+        the built-in map."""
+        arg = None if tags is None else ",".join(tags).encode()
+        self.check(self.lib.mlcc_bf16_map(self.h, arg))
+
     def pair_block_occ(self, occ=0):
         """Occupied indices per pair block of the MLCC2 doubles on this
         context's problems (0: the memory rule)."""
@@ -221,7 +229,9 @@ class Context:
 
     def cholesky_basis(self, n_ao, G, tau, nu=None, max_vectors=None):
         """Pivots and Q^-T of the Cholesky basis of the AO pair matrix G
-        (mlcc_cholesky_basis); nu: MO screening weights or None."""
+        (mlcc_cholesky_basis); nu: MO screening weights or None.  Q^-T is
+        returned only when max_vectors^2 doubles (default max_vectors: every
+        pair) fit in 1 GiB; otherwise None (pivots only): pass max_vectors."""
         npair = n_ao * (n_ao + 1) // 2
         cap = npair if max_vectors is None else max_vectors
         piv = np.empty(cap, dtype=np.int32)

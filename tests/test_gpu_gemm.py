@@ -258,3 +258,41 @@ def test_every_tile(ctx, prec, vector):
     finally:
         ctx.gemm_tile(0, 0)
     assert applied == set(menu), sorted(set(menu) - applied)
+
+
+def bf16_round(x):
+    """float32 values rounded to BF16 (nearest, ties to even), as float64."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c[5] == "k" and c[6] == "k"])
+def test_plain_bf16_product(case):
+    """MLCC_BF16 with the engine's own calls ("gemm") on the plain-BF16 map:
+    the product of the operands rounded to BF16 (exact in FP32) accumulated
+    in FP32; with an empty map the same call is bit-identical to split BF16."""
+    M, N, K, R, Z, _, _ = case
+    ctx = mlcc.Context(0)  # the map belongs to the context
+    rng = np.random.default_rng(hash(case) % 2**32)
+    sA = [K, 1, M * K, M * K * R]
+    sB = [1, K, K * N, K * N * R]
+    A = rng.standard_normal(M * K * R * Z).astype(np.float32)
+    B = rng.standard_normal(K * N * R * Z).astype(np.float32)
+    ref = ref_gemm(bf16_round(A), sA, bf16_round(B), sB, M, N, K, R, Z)
+    Ad = torch.tensor(A, device="cuda")
+    Bd = torch.tensor(B, device="cuda")
+
+    def run(p):
+        Cd = torch.zeros(Z * M * N, dtype=torch.float32, device="cuda")
+        ctx.gemm(mlcc.PREC[p], M, N, K, R, Z, 1.0, Ad, sA, Bd, sB, 0.0, Cd, [N, 1, M * N])
+        return Cd.cpu().numpy().astype(np.float64).reshape(Z, M, N)
+
+    ctx.bf16_map(["gemm"])
+    got = run("bf16")
+    assert np.abs(got - ref).max() <= TOL["fp32"] * (np.sqrt(K * R) + 1.0)
+    split = run("bf16x3")
+    assert np.abs(got - split).max() > 0  # one product, not three
+    ctx.bf16_map([])
+    assert np.array_equal(run("bf16"), split)
+    ctx.close()
