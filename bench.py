@@ -159,8 +159,8 @@ def _profiled_traffic(tag: str, config: str, precision: str):
             fields[k] = v.strip()
     h = hashlib.sha256()
     srcs = ("gemm_kernel.h", "gemm_f64.hip", "gemm_f64g.hip") if precision == "fp64" else \
-        ("gemm_kernel.h", "gemm_split.h", "gemm_f32.hip", "gemm_f32d.hip", "gemm_f32g.hip",
-         "gemm_f32dg.hip")
+        ("gemm_kernel.h", "gemm_split.h", "gemm_planes.h", "gemm_f32.hip", "gemm_f32d.hip",
+         "gemm_f32g.hip", "gemm_f32dg.hip")
     for f in srcs:
         with open(os.path.join(ROOT, "paper_2006_05226_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())

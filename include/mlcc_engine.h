@@ -95,6 +95,20 @@ mlcc_status mlcc_gemm_noalloc(mlcc_context *ctx, int32_t prec, int64_t M, int64_
  * context or negative sizes. */
 mlcc_status mlcc_gemm_tile(mlcc_context *ctx, int32_t bm, int32_t bn, int32_t last[2]);
 
+/* Packed BF16 planes on this context, for parity tests and tuning.  Large
+ * split- and plain-BF16 products first convert both operands into BF16
+ * planes (hi, and lo for split products; rows padded to 256, the flattened
+ * reduction index to 64) in an engine buffer of at most 3 GiB, then run a
+ * kernel that streams the planes into LDS with direct loads.  mode 0: where
+ * a cost rule says the conversion pays (the default), 1: wherever the product
+ * allows it (no caller workspace, planes within the cap), -1: never.  The
+ * products are the same BF16 products either way (same rounding, same
+ * accumulation order within a k-step); results differ from the unpacked
+ * kernel's only by the order of the FP32 sums across k-steps and splits.
+ * Server lanes are not affected.  MLCC_E_ARG for a NULL context or a mode
+ * outside -1..1. */
+mlcc_status mlcc_gemm_planes(mlcc_context *ctx, int32_t mode);
+
 /* Occupied indices per pair block of the MLCC2 doubles (the ground state
  * with the analytic s2 and the effective transformation build g~ and c2 per
  * occupied-pair block (I, J), I <= J) on problems of this context: occ > 0

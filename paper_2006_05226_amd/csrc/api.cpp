@@ -176,6 +176,7 @@ void context_unref(mlcc_context *ctx) {
   (void)hipStreamSynchronize(ctx->ex.stream);
   ctx->ex.work.release();
   ctx->ex.red.release();
+  ctx->ex.planes.release();
   ctx->al.release_all();
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->ex.stream);
   if (ctx->ex.pinned) (void)hipHostFree(ctx->ex.pinned);
@@ -552,6 +553,12 @@ mlcc_status mlcc_gemm_tile(mlcc_context *ctx, int32_t bm, int32_t bn, int32_t la
   }
   ctx->ex.force_bm = bm;
   ctx->ex.force_bn = bn;
+  return MLCC_OK;
+}
+
+mlcc_status mlcc_gemm_planes(mlcc_context *ctx, int32_t mode) {
+  if (!ctx || mode < -1 || mode > 1) return MLCC_E_ARG;
+  ctx->ex.planes_mode = mode;
   return MLCC_OK;
 }
 

@@ -1,0 +1,396 @@
+// Split and plain BF16 products on packed operand planes.  Included by the
+// FP32 instantiation units after gemm_kernel.h and gemm_split.h.
+//
+// For large contractions the FP32 operands are first converted once into
+// BF16 planes, hi = bf16(x) and lo = bf16(x - hi) (hi only for plain
+// products), laid out [batch][row][k'] with k' = r * K + k the flattened
+// reduction index: rows padded to a multiple of kPlaneRowPad, k' padded to a
+// multiple of kPlaneKPad, padding zero.  The product kernel then streams
+// the planes into LDS with direct global-to-LDS loads (global_load_lds_dwordx4):
+// no VGPR staging, no per-step conversion, no bounds checks inside the
+// k-loop.  The conversion is the same as the split kernel's (round to
+// nearest even, twice), so both kernels multiply the same BF16 values.
+//
+// LDS layout: per operand, plane and stage, rows of 32 BF16 (64 bytes, four
+// 16-byte chunks).  One load instruction of a wave fills 1 KB of LDS, 16
+// rows, lane c writing bytes 16c..16c+15; the lane therefore loads logical
+// chunk (c % 4) ^ swz(row) of row c / 4, so that chunk g of row r sits at
+// physical chunk g ^ swz(r), swz(r) = (r / 2) % 4.  With it the 16-byte
+// fragment reads (16 rows, one chunk) run free of bank conflicts: measured
+// with SQ_LDS_BANK_CONFLICT on the 256 x 256 tile, 0 against 0.16 of the busy
+// cycles without a swizzle, with (r / 4) % 4, or with a variant that also
+// flips on bit 3 of r, and 0.71 against 0.65 matrix-core busy.
+#pragma once
+
+#include "gemm_kernel.h"
+#include "gemm_split.h"
+
+namespace mlcc {
+namespace gk {
+
+constexpr int kPlaneBK = 32;       // k per step: one v_mfma_f32_16x16x32_bf16
+constexpr int kPlaneRowPad = 256;  // the largest tile dimension of the menu
+constexpr int kPlaneKPad = 64;
+
+// One operand seen as Z batches of `rows` rows, each row R slices of K
+// contiguous elements (unit stride along k, the condition of the split
+// products), with an optional two-level row index.
+struct PackArgs {
+  const float *X;
+  int64_t rows, K, R, Z;
+  int64_t s_row, s_r, s_z;
+  int64_t lo, s_hi;        // two-level row index (lo <= 0: one level)
+  int64_t rows_p, kp;      // padded plane extents
+  __bf16 *hi, *lo_plane;   // [Z][rows_p][kp]; lo_plane unused for plain products
+};
+
+// One thread per 8 consecutive k' of one row (one 16-byte group of each
+// plane); consecutive threads walk along k', so the FP32 reads of a wave are
+// contiguous within a slice.  Padding rows and k' >= R K are written as zero.
+template <bool PLAIN> __global__ __launch_bounds__(256) void k_pack_planes(PackArgs a) {
+  const int64_t chunks = a.kp / 8;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.Z * a.rows_p * chunks) return;
+  const int64_t rz = t / chunks, ch = t - rz * chunks;
+  const int64_t z = rz / a.rows_p, m = rz - z * a.rows_p;
+  const int64_t k0 = ch * 8, KK = a.R * a.K;
+  bf8v h, l;
+  if (m < a.rows) {
+    const float *X = a.X + z * a.s_z + two_level(m, a.lo, a.s_row, a.s_hi);
+    int64_t r = k0 / a.K, k = k0 - r * a.K;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const float x = k0 + q < KK ? X[r * a.s_r + k] : 0.0f;
+      h[q] = (__bf16)x;
+      l[q] = (__bf16)(x - (float)h[q]);
+      if (++k == a.K) {
+        k = 0;
+        ++r;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) h[q] = l[q] = (__bf16)0.0f;
+  }
+  const int64_t o = rz * a.kp + k0;
+  *reinterpret_cast<bf8v *>(a.hi + o) = h;
+  if constexpr (!PLAIN) *reinterpret_cast<bf8v *>(a.lo_plane + o) = l;
+}
+
+struct PlaneOps {
+  const __bf16 *ah, *al, *bh, *bl;  // al, bl null for plain products
+  int64_t a_zs, b_zs;               // plane batch strides (0: one plane for every batch)
+};
+
+__device__ __forceinline__ int plane_swz(int r) { return (r >> 1) & 3; }
+
+// Fragments of one k-step of a wave, read from a stage of LDS (A planes at
+// As, B planes at Bs, each plane rows x 32 BF16 with swizzled chunks).
+template <int FM, int FN, int WTM, int WTN, bool PLAIN> struct PlaneFrags {
+  bf8v ah[FM], al[PLAIN ? 1 : FM], bh[FN], bl[PLAIN ? 1 : FN];
+  __device__ __forceinline__ void read(const __bf16 *As, int plane_a, const __bf16 *Bs, int plane_b,
+                                       int wm, int wn, int l16, int chunk) {
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+      const int o = (wn * WTN + j * 16 + l16) * kPlaneBK + chunk * 8;
+      bh[j] = *reinterpret_cast<const bf8v *>(Bs + o);
+      if constexpr (!PLAIN) bl[j] = *reinterpret_cast<const bf8v *>(Bs + plane_b + o);
+    }
+#pragma unroll
+    for (int i = 0; i < FM; ++i) {
+      const int o = (wm * WTM + i * 16 + l16) * kPlaneBK + chunk * 8;
+      ah[i] = *reinterpret_cast<const bf8v *>(As + o);
+      if constexpr (!PLAIN) al[i] = *reinterpret_cast<const bf8v *>(As + plane_a + o);
+    }
+  }
+  // the products: all hi*hi first, then hi*lo, then lo*hi, so that
+  // consecutive MFMAs never accumulate into the same registers
+  __device__ __forceinline__ void mma(f4 (&acc)[FM][FN]) const {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+    if constexpr (!PLAIN) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+    }
+  }
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// 16 bytes per lane from global memory straight into LDS: lane l's bytes
+// land at dst + 16 l (dst uniform over the wave).
+__device__ __forceinline__ void load_lds16(const __bf16 *src, __bf16 *dst) {
+  __builtin_amdgcn_global_load_lds(src, (lds_void *)dst, 16, 0, 0);
+}
+
+// Product kernel on packed planes: BM x BN output tile, WM x WN waves, two
+// LDS stages.
+template <int WM, int WN> struct PlaneWaves {
+  static constexpr int NT = 64 * WM * WN;
+};
+
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN>
+__global__ __launch_bounds__((PlaneWaves<WM, WN>::NT)) void k_gemm_planes(KParams kp, PlaneOps po) {
+  constexpr int NW = WM * WN, WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
+  constexpr int PL = PLAIN ? 1 : 2;
+  constexpr int RA = BM * kPlaneBK, RB = BN * kPlaneBK;  // elements of one plane of a stage
+  constexpr int QA = PL * BM / 16, QB = PL * BN / 16;     // 1 KB loads per stage
+  constexpr int EA = QA / NW, EB = QB / NW;
+  static_assert(QA % NW == 0 && QB % NW == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile");
+  static_assert(BM <= kPlaneRowPad && BN <= kPlaneRowPad && kPlaneRowPad % BM == 0 &&
+                kPlaneRowPad % BN == 0, "plane padding");
+  constexpr int STAGE = PL * (RA + RB);  // elements of one stage
+  __shared__ __attribute__((aligned(1024))) __bf16 lds[2 * STAGE];
+
+  const int64_t L = blockIdx.x;
+  const int64_t w = (L % kXcd) * kp.per_xcd + L / kXcd;
+  if (w >= kp.nwork) return;
+  int64_t tm, tn, zs;
+  tile_of(kp, w, tm, tn, zs);
+  const int64_t z = zs / kp.splits;
+  const int split = (int)(zs % kp.splits);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform over the wave
+  const int wm = wave / WN, wn = wave % WN, l16 = lane & 15;
+  const int chunk = (lane >> 4) ^ plane_swz(l16);  // this lane's fragment chunk
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  const int64_t kpad = kp.ktiles * kPlaneBK;
+  const int64_t s_begin = split * kp.steps_per_split;
+  const int64_t s_end = min(kp.ktiles, s_begin + kp.steps_per_split);
+
+  // Load q of a stage covers plane q / (rows / 16), tile rows 16 (q % (rows
+  // / 16)) .. +15; its source is a wave-uniform offset plus this lane's
+  // offset (row lane / 4 of the 16, logical chunk (lane % 4) ^ swz).
+  const int64_t lane_off = (int64_t)(lane >> 2) * kpad + 8 * ((lane & 3) ^ plane_swz(lane >> 2));
+  const __bf16 *a_base = po.ah + z * po.a_zs + lane_off, *b_base = po.bh + z * po.b_zs + lane_off;
+  const int64_t a_lo = PLAIN ? 0 : po.al - po.ah, b_lo = PLAIN ? 0 : po.bl - po.bh;
+  auto issue = [&](int stage, int64_t step) {
+    __bf16 *As = lds + stage * STAGE, *Bs = As + PL * RA;
+    const int64_t k0 = step * kPlaneBK;
+#pragma unroll
+    for (int e = 0; e < EA; ++e) {
+      const int q = wave + NW * e, pl = q / (BM / 16), rq = q % (BM / 16);
+      load_lds16(a_base + ((pl ? a_lo : 0) + (m0 + rq * 16) * kpad + k0), As + pl * RA + rq * 512);
+    }
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+      const int q = wave + NW * e, pl = q / (BN / 16), rq = q % (BN / 16);
+      load_lds16(b_base + ((pl ? b_lo : 0) + (n0 + rq * 16) * kpad + k0), Bs + pl * RB + rq * 512);
+    }
+  };
+
+  f4 acc[FM][FN];
+#pragma unroll
+  for (int i = 0; i < FM; ++i)
+#pragma unroll
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+  // Per k-step: wait for this wave's loads of the stage, a barrier (every
+  // wave's loads have landed, and every wave has finished reading the other
+  // stage), all fragment reads of the step, then the loads of the next step
+  // into the other stage, then the products.
+  if (s_begin < s_end) issue(0, s_begin);
+  int cur = 0;
+  for (int64_t step = s_begin; step < s_end; ++step) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    PlaneFrags<FM, FN, WTM, WTN, PLAIN> fr;
+    const __bf16 *As = lds + cur * STAGE;
+    fr.read(As, RA, As + PL * RA, RB, wm, wn, l16, chunk);
+    if (step + 1 < s_end) issue(cur ^ 1, step + 1);
+    fr.mma(acc);
+    cur ^= 1;
+  }
+  epilogue<float, TC, FM, FN, WTM, WTN, false>(kp, acc, m0, n0, z, split, lane, wm, wn);
+}
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Plane geometry of a product: extents, batch counts and bytes.
+struct PlaneGeom {
+  int64_t mp, np, kp, za, zb;
+  int pl;
+  size_t bytes_a, bytes_b;  // per plane
+  size_t total() const { return (size_t)pl * (bytes_a + bytes_b); }
+};
+inline PlaneGeom plane_geom(const GemmArgs &a, bool plain) {
+  PlaneGeom g;
+  g.mp = round_up(a.M, kPlaneRowPad);
+  g.np = round_up(a.N, kPlaneRowPad);
+  g.kp = round_up(a.R * a.K, kPlaneKPad);
+  g.za = a.sAz ? a.Z : 1;
+  g.zb = a.sBz ? a.Z : 1;
+  g.pl = plain ? 1 : 2;
+  g.bytes_a = sizeof(__bf16) * (size_t)g.za * g.mp * g.kp;
+  g.bytes_b = sizeof(__bf16) * (size_t)g.zb * g.np * g.kp;
+  return g;
+}
+
+inline void pack_planes(Exec &ex, const PackArgs &pa) {
+  const int64_t blocks = cdiv(pa.Z * pa.rows_p * (pa.kp / 8), 256);
+  MLCC_REQUIRE(blocks < ((int64_t)1 << 31), MLCC_E_ARG, "gemm: operand planes too large");
+  if (pa.lo_plane) hipLaunchKernelGGL(k_pack_planes<false>, dim3((unsigned)blocks), dim3(256), 0, ex.stream, pa);
+  else hipLaunchKernelGGL(k_pack_planes<true>, dim3((unsigned)blocks), dim3(256), 0, ex.stream, pa);
+  MLCC_HIP(hipGetLastError());
+}
+
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN>
+void launch_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad, int splits) {
+  KParams kp;
+  kp.a = a;
+  kp.splits = splits;
+  kp.ktiles = kpad / kPlaneBK;
+  kp.steps_per_split = cdiv(kp.ktiles, splits);
+  kp.tiles_m = (int)cdiv(a.M, BM);
+  kp.tiles_n = (int)cdiv(a.N, BN);
+  kp.nwork = (int64_t)kp.tiles_m * kp.tiles_n * a.Z * splits;
+  kp.per_xcd = cdiv(kp.nwork, kXcd);
+  kp.vec_a = kp.vec_b = 1;
+  MLCC_REQUIRE(kp.per_xcd * kXcd < (int64_t)1 << 31, MLCC_E_ARG, "gemm: grid too large");
+  kp.work = nullptr;
+  if (splits > 1) kp.work = ex.scratch(sizeof(float) * (size_t)splits * a.Z * a.M * a.N);
+  hipLaunchKernelGGL((k_gemm_planes<TC, BM, BN, WM, WN, PLAIN>), dim3((unsigned)(kp.per_xcd * kXcd)),
+                     dim3(64 * WM * WN), 0, ex.stream, kp, po);
+  MLCC_HIP(hipGetLastError());
+  if (splits > 1) {
+    const int64_t n = a.Z * a.M * a.N;
+    const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL((k_split_reduce<float, TC>), dim3(blocks), dim3(256), 0, ex.stream, kp);
+    MLCC_HIP(hipGetLastError());
+  }
+}
+
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN> int planes_occupancy(const GemmArgs &) {
+  static std::atomic<int> cache{0};
+  int nb = cache.load(std::memory_order_relaxed);
+  if (nb > 0) return nb;
+  const void *f = reinterpret_cast<const void *>(&k_gemm_planes<TC, BM, BN, WM, WN, PLAIN>);
+  MLCC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * WM * WN, 0));
+  nb = std::max(nb, 1);
+  cache.store(nb, std::memory_order_relaxed);
+  return nb;
+}
+
+typedef void (*PlaneLaunchFn)(Exec &, const GemmArgs &, const PlaneOps &, int64_t, int);
+struct PlaneTile {
+  int bm, bn, waves;
+  PlaneLaunchFn fn;
+  OccFn occ;
+};
+
+// Whether a split-eligible product runs on packed planes: never with a
+// caller workspace (the planes are allocated) or planes beyond the lane's
+// cap; otherwise as the lane's mode says, by default where the packing pass
+// (read 4 bytes, write 2 per plane per operand element, ~3.3 TB/s measured)
+// costs less than the planes kernel saves: on the 3601 x 5000 x 5000 (x 5)
+// product the split kernel runs ~240 TFLOP/s unpacked and ~370 on planes,
+// plain BF16 ~370 and ~640, so packing pays above ~210 (split) and ~270
+// (plain) flops per packed byte; 250 is the rule, with at least 4 GFLOP so
+// that the two extra launches stay negligible.
+inline bool use_planes(const Exec &ex, const GemmArgs &a, bool plain) {
+  if (a.work || ex.planes_mode < 0) return false;
+  const PlaneGeom g = plane_geom(a, plain);
+  if (g.total() > ex.planes_cap) return false;
+  if (ex.planes_mode > 0) return true;
+  const double flops = 2.0 * (double)a.M * a.N * a.K * a.R * a.Z;
+  const double pack_bytes = (4.0 / (2.0 * g.pl) + 1.0) * (double)g.total();
+  return flops >= 4e9 && flops >= 250.0 * pack_bytes;
+}
+
+// Pack both operands and run the product with the tile of the lowest
+// modelled cost: rounds of resident blocks (the kernel's occupancy per CU)
+// times each block's k-steps and outputs over its per-CU rate (rate: the
+// 8-wave 256 x 256 tile, one block per CU, measured 1.13 times the rate of
+// two 128 x 128 blocks per CU on the 3601 x 5000 x 5000 (x 5) product and
+// on 4096^3), plus the split reduction's traffic.
+template <typename TC>
+void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles, int ntiles) {
+  const PlaneGeom g = plane_geom(a, plain);
+  ex.planes.ensure(ex.al, g.total());
+  __bf16 *base = static_cast<__bf16 *>(ex.planes.p);
+  const size_t ea = g.bytes_a / sizeof(__bf16), eb = g.bytes_b / sizeof(__bf16);
+  PlaneOps po;
+  po.ah = base;
+  po.bh = base + ea;
+  po.al = plain ? nullptr : base + ea + eb;
+  po.bl = plain ? nullptr : base + 2 * ea + eb;
+  po.a_zs = a.sAz ? g.mp * g.kp : 0;
+  po.b_zs = a.sBz ? g.np * g.kp : 0;
+
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (ex.prof && ex.prof->on) {
+    ev = ex.prof->next();
+    MLCC_HIP(hipEventRecord(ev.first, ex.stream));
+  }
+  MLCC_REQUIRE(a.sAk == 1 && a.sBk == 1, MLCC_E_ARG, "gemm: packed planes need k-contiguous operands");
+  PackArgs pa;
+  pa.X = static_cast<const float *>(a.A);
+  pa.rows = a.M; pa.K = a.K; pa.R = a.R; pa.Z = g.za;
+  pa.s_row = a.sAm; pa.s_r = a.sAr; pa.s_z = a.sAz;
+  pa.lo = a.Mlo; pa.s_hi = a.sAm_hi;
+  pa.rows_p = g.mp; pa.kp = g.kp;
+  pa.hi = const_cast<__bf16 *>(po.ah); pa.lo_plane = const_cast<__bf16 *>(po.al);
+  pack_planes(ex, pa);
+  pa.X = static_cast<const float *>(a.B);
+  pa.rows = a.N; pa.Z = g.zb;
+  pa.s_row = a.sBn; pa.s_r = a.sBr; pa.s_z = a.sBz;
+  pa.lo = a.Nlo; pa.s_hi = a.sBn_hi;
+  pa.rows_p = g.np;
+  pa.hi = const_cast<__bf16 *>(po.bh); pa.lo_plane = const_cast<__bf16 *>(po.bl);
+  pack_planes(ex, pa);
+
+  const int64_t steps = g.kp / kPlaneBK, ncu = cu_count();
+  int forced = -1;
+  for (int t = 0; t < ntiles; ++t)
+    if (tiles[t].bm == ex.force_bm && tiles[t].bn == ex.force_bn) forced = t;
+  int best = -1, best_s = 1;
+  double best_cost = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    if (forced >= 0 && t != forced) continue;
+    const int bm = tiles[t].bm, bn = tiles[t].bn;
+    const int64_t occ = tiles[t].occ(a);
+    const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
+    int64_t s = 1;
+    if (blocks < occ * ncu && steps >= 8)
+      s = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(occ * ncu / blocks, steps / 4), 128));
+    const int64_t rounds = cdiv(blocks * s, occ * ncu);
+    const double rate = tiles[t].waves == 8 ? 1.13 : 1.0;
+    double cost = (double)rounds * (double)cdiv(steps, s) * bm * bn * occ / rate;
+    if (s > 1) cost += 2.0 * (double)s * a.Z * a.M * a.N;
+    if (best < 0 || cost < best_cost) {
+      best = t;
+      best_s = (int)s;
+      best_cost = cost;
+    }
+  }
+  ex.last_bm = tiles[best].bm;
+  ex.last_bn = tiles[best].bn;
+  tiles[best].fn(ex, a, po, g.kp, best_s);
+  if (ev.first) {
+    MLCC_HIP(hipEventRecord(ev.second, ex.stream));
+    ex.prof->recs.push_back({a.tag, ev.first, ev.second, 2.0 * (double)a.M * a.N * a.K * a.R * a.Z});
+  }
+}
+
+}  // namespace gk
+}  // namespace mlcc
+
+// Tile menu of the planes kernel: (BM, BN, WM, WN).  Measured on the
+// 3601 x 5000 x 5000 (x 5) split product: 256 x 256 with 8 waves (one block
+// per CU, two waves per SIMD) 344 TFLOP/s, 128 x 128 with 4 waves (two
+// blocks per CU) 305, 256 x 128 and 128 x 256 with 4 waves (one block per
+// CU) 269 and 256, 256 x 256 with 4 waves spills.
+#ifndef MLCC_GEMM_TILES_PLANES
+#define MLCC_GEMM_TILES_PLANES(X) X(256, 256, 2, 4) X(128, 128, 2, 2)
+#endif

@@ -133,12 +133,21 @@ struct Profiler {
 };
 
 // An execution lane: a stream plus its scratch for split reductions.
+// Largest packed operand planes of one BF16 product (larger ones run
+// without packing).
+constexpr size_t kPlaneBytesMax = (size_t)3 << 30;
+
 struct Exec {
   Profiler *prof = nullptr;
   Alloc *al = nullptr;
   hipStream_t stream = nullptr;
   DBuf work;      // split-K partials
   DBuf red;       // reduction partials (dot products)
+  DBuf planes;    // packed BF16 operand planes of the large split / plain BF16 products
+  // Packed planes: 0 where the cost rule says they pay, 1 wherever the
+  // product allows them, -1 never (tests and tuning); at most planes_cap bytes.
+  int planes_mode = 0;
+  size_t planes_cap = kPlaneBytesMax;
   double *pinned = nullptr;    // pinned host scalars (512 doubles) for results
   // Tile override of the contraction engine on this lane (parity tests,
   // tuning): a forced bm x bn is used by every call whose menu has it; the

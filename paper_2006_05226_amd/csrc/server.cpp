@@ -73,16 +73,46 @@ struct mlcc_server {
   void work(Lane *lane);
 };
 
+namespace {
+// Device bytes of a request's solve peak (L, L~, packed blocks, the
+// ground-state u that the Jacobian reads, the pair blocks of the MLCC2
+// doubles, the per-vector scratch of a Jacobian batch, the Davidson subspace
+// and the DIIS history) before the packed BF16 planes of its large products;
+// *setup_out receives the set-up peak (L, plus its FP64 staging copy in FP32
+// mode).  0 for invalid input.
+double solve_bytes(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_solver_opts *es,
+                   double *setup_out);
+
+// The packed BF16 planes a split- or plain-BF16 request may hold at once:
+// half its solve peak (the planes of a product are about its FP32 operands'
+// bytes, and the largest operands are a fraction of the solve peak), at
+// most the engine's cap; 0 for the FP64 and FP32 tiers.  A lane runs the
+// request with this cap, so a product whose planes need more runs unpacked.
+uint64_t planes_share(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_solver_opts *es) {
+  if (!d || (d->precision != MLCC_BF16X3 && d->precision != MLCC_BF16)) return 0;
+  double setup = 0.0;
+  const double run = solve_bytes(d, n_roots, es, &setup);
+  return (uint64_t)std::min<double>((double)mlcc::kPlaneBytesMax, 0.5 * run);
+}
+}  // namespace
+
 // Device bytes one request needs at its peak, with a 15% margin: the larger
-// of the set-up peak (L, plus its FP64 staging copy in FP32 mode) and the
-// solve peak (L, L~, packed blocks, the ground-state u that the Jacobian
-// reads, the pair blocks of the MLCC2 doubles, the per-vector scratch of a
-// Jacobian batch, the Davidson subspace and the DIIS history), plus the
-// lane's split-K partial sums (at most ~67 MB: resident blocks x compute
-// units x the largest FP64 tile) and reduction buffers.
+// of the set-up peak and the solve peak (solve_bytes plus the packed planes
+// of planes_share), plus the lane's split-K partial sums (at most ~67 MB:
+// resident blocks x compute units x the largest FP64 tile) and reduction
+// buffers.
 extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n_roots,
                                            const mlcc_solver_opts *es) {
   if (!d || n_roots < 1) return 0;
+  double setup = 0.0;
+  const double run = solve_bytes(d, n_roots, es, &setup) + (double)planes_share(d, n_roots, es);
+  return (uint64_t)(std::max(setup, run) * 1.15) + (160ull << 20);
+}
+
+namespace {
+double solve_bytes(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_solver_opts *es,
+                   double *setup_out) {
+  if (!d || n_roots < 1) return 0.0;
   const double O = d->n_occ, V = d->n_vir, J = d->n_chol, n = O + V;
   const bool dbl = d->model != MLCC_CCS && d->n_occ_act > 0 && d->n_vir_act > 0;
   const double o = dbl ? d->n_occ_act : 0.0, v = dbl ? d->n_vir_act : 0.0;
@@ -121,8 +151,10 @@ extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n
   const double space = es && es->max_subspace > 0 ? es->max_subspace : 20.0 * n_roots;
   run += dim * 8.0 * (2.0 * space + 3.0 * (n_roots + 2));  // Davidson
   run += 2.0 * 8.0 * (n1 + (ccsd ? MM : 0.0)) * 8;         // DIIS
-  return (uint64_t)(std::max(setup, run) * 1.15) + (160ull << 20);
+  *setup_out = setup;
+  return run;
 }
+}  // namespace
 
 void mlcc_server::work(Lane *lane) {
   (void)hipSetDevice(ctx->device);
@@ -157,6 +189,7 @@ void mlcc_server::work(Lane *lane) {
       if (!(d.flags & MLCC_SYNTH_L)) d.L = r->L.data();
       d.eps = r->eps.data();
       d.fock = r->fock.empty() ? nullptr : r->fock.data();
+      lane->ex.planes_cap = planes_share(&d, r->n_roots, &r->es);
       std::unique_ptr<mlcc_problem> P(problem_new(ctx, &lane->ex, &d));
       drop_host();  // the problem holds its own device copies now
       mlcc_info gi{};
@@ -181,6 +214,7 @@ void mlcc_server::work(Lane *lane) {
     (void)hipStreamSynchronize(lane->ex.stream);
     lane->ex.work.release();
     lane->ex.red.release();
+    lane->ex.planes.release();
     lane->al.quiesce();
     drop_host();
     {
@@ -268,6 +302,7 @@ mlcc_status mlcc_server_destroy(mlcc_server *s) {
     if (l->ex.stream) (void)hipStreamSynchronize(l->ex.stream);
     l->ex.work.release();
     l->ex.red.release();
+    l->ex.planes.release();
     l->al.quiesce();
     if (l->ex.stream) (void)hipStreamDestroy(l->ex.stream);
     if (l->ex.pinned) (void)hipHostFree(l->ex.pinned);

@@ -73,7 +73,8 @@ EXPORTS = ["mlcc_context_create", "mlcc_context_destroy", "mlcc_last_error", "ml
            "mlcc_server_create", "mlcc_server_destroy", "mlcc_submit", "mlcc_poll",
            "mlcc_request_footprint", "mlcc_gemm", "mlcc_gemm2", "mlcc_gemm_noalloc",
            "mlcc_debug_get", "mlcc_profile_enable", "mlcc_profile_get", "mlcc_gemm_tile", "mlcc_cnto",
-           "mlcc_pair_block_occ", "mlcc_cholesky_basis", "mlcc_mo_cholesky", "mlcc_bf16_map"]
+           "mlcc_pair_block_occ", "mlcc_cholesky_basis", "mlcc_mo_cholesky", "mlcc_bf16_map",
+           "mlcc_gemm_planes"]
 
 NOALLOC_SCRATCH_BYTES = 16 << 20
 
@@ -119,6 +120,7 @@ def load(path: str = LIB_PATH):
         "mlcc_profile_enable": (i32, [vp, i32]),
         "mlcc_profile_get": (i32, [vp, P(KernelStat), i32]),
         "mlcc_gemm_tile": (i32, [vp, i32, i32, P(i32)]),
+        "mlcc_gemm_planes": (i32, [vp, i32]),
         "mlcc_pair_block_occ": (i32, [vp, i32]),
         "mlcc_bf16_map": (i32, [vp, C.c_char_p]),
         "mlcc_cholesky_basis": (i32, [vp, i32, vp, vp, dbl, i32, vp, P(i32), vp]),
@@ -214,6 +216,12 @@ class Context:
         last = (C.c_int32 * 2)()
         self.check(self.lib.mlcc_gemm_tile(self.h, bm, bn, last))
         return (last[0], last[1])
+
+    def gemm_planes(self, mode=0):
+        """Packed BF16 planes for the split and plain BF16 products of this
+        context: 0 where the cost rule picks them, 1 wherever allowed, -1
+        never."""
+        self.check(self.lib.mlcc_gemm_planes(self.h, mode))
 
     def bf16_map(self, tags=None):
         """Contractions that run plain BF16 products in precision "bf16" on
