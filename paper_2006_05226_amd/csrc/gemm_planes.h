@@ -42,6 +42,7 @@ struct PackArgs {
   int64_t lo, s_hi;        // two-level row index (lo <= 0: one level)
   int64_t rows_p, kp;      // padded plane extents
   __bf16 *hi, *lo_plane;   // [Z][rows_p][kp]; lo_plane unused for plain products
+  int vec4;                // every group of 4 elements (k % 4 == 0) is one aligned 16-byte load
 };
 
 // One thread per 8 consecutive k' of one row (one 16-byte group of each
@@ -55,7 +56,22 @@ template <bool PLAIN> __global__ __launch_bounds__(256) void k_pack_planes(PackA
   const int64_t z = rz / a.rows_p, m = rz - z * a.rows_p;
   const int64_t k0 = ch * 8, KK = a.R * a.K;
   bf8v h, l;
-  if (m < a.rows) {
+  if (m < a.rows && a.vec4) {
+    // K and KK are multiples of 4: each half of the chunk is one 16-byte
+    // group inside one slice, wholly inside or wholly past the reduction
+    const float *X = a.X + z * a.s_z + two_level(m, a.lo, a.s_row, a.s_hi);
+#pragma unroll
+    for (int g = 0; g < 2; ++g) {
+      const int64_t kk = k0 + 4 * g, r = kk / a.K, k = kk - r * a.K;
+      f4 v = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      if (kk < KK) v = *reinterpret_cast<const f4 *>(X + r * a.s_r + k);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        h[4 * g + q] = (__bf16)v[q];
+        l[4 * g + q] = (__bf16)(v[q] - (float)h[4 * g + q]);
+      }
+    }
+  } else if (m < a.rows) {
     const float *X = a.X + z * a.s_z + two_level(m, a.lo, a.s_row, a.s_hi);
     int64_t r = k0 / a.K, k = k0 - r * a.K;
 #pragma unroll
@@ -237,7 +253,11 @@ inline PlaneGeom plane_geom(const GemmArgs &a, bool plain) {
   return g;
 }
 
-inline void pack_planes(Exec &ex, const PackArgs &pa) {
+inline void pack_planes(Exec &ex, PackArgs pa) {
+  // 16-byte groups: K a multiple of 4 and every group start 16-byte aligned
+  const bool lo_ok = pa.lo <= 0 || pa.s_hi % 4 == 0;
+  pa.vec4 = pa.K % 4 == 0 && pa.s_row % 4 == 0 && pa.s_r % 4 == 0 && pa.s_z % 4 == 0 && lo_ok &&
+            reinterpret_cast<uintptr_t>(pa.X) % 16 == 0;
   const int64_t blocks = cdiv(pa.Z * pa.rows_p * (pa.kp / 8), 256);
   MLCC_REQUIRE(blocks < ((int64_t)1 << 31), MLCC_E_ARG, "gemm: operand planes too large");
   if (pa.lo_plane) hipLaunchKernelGGL(k_pack_planes<false>, dim3((unsigned)blocks), dim3(256), 0, ex.stream, pa);
@@ -271,7 +291,8 @@ void launch_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad
   }
 }
 
-template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN> int planes_occupancy(const GemmArgs &) {
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN>
+int planes_occupancy(const GemmArgs &) {
   static std::atomic<int> cache{0};
   int nb = cache.load(std::memory_order_relaxed);
   if (nb > 0) return nb;
@@ -292,11 +313,11 @@ struct PlaneTile {
 // Whether a split-eligible product runs on packed planes: never with a
 // caller workspace (the planes are allocated) or planes beyond the lane's
 // cap; otherwise as the lane's mode says, by default where the packing pass
-// (read 4 bytes, write 2 per plane per operand element, ~3.3 TB/s measured)
+// (read 4 bytes, write 2 per plane per operand element, ~6 TB/s measured)
 // costs less than the planes kernel saves: on the 3601 x 5000 x 5000 (x 5)
-// product the split kernel runs ~240 TFLOP/s unpacked and ~370 on planes,
-// plain BF16 ~370 and ~640, so packing pays above ~210 (split) and ~270
-// (plain) flops per packed byte; 250 is the rule, with at least 4 GFLOP so
+// product the split kernel runs ~240 TFLOP/s unpacked and ~390 on planes,
+// plain BF16 ~370 and ~700, so packing pays above ~130 (split) and ~130
+// (plain) flops per packed byte; 150 is the rule, with at least 4 GFLOP so
 // that the two extra launches stay negligible.
 inline bool use_planes(const Exec &ex, const GemmArgs &a, bool plain) {
   if (a.work || ex.planes_mode < 0) return false;
@@ -305,7 +326,7 @@ inline bool use_planes(const Exec &ex, const GemmArgs &a, bool plain) {
   if (ex.planes_mode > 0) return true;
   const double flops = 2.0 * (double)a.M * a.N * a.K * a.R * a.Z;
   const double pack_bytes = (4.0 / (2.0 * g.pl) + 1.0) * (double)g.total();
-  return flops >= 4e9 && flops >= 250.0 * pack_bytes;
+  return flops >= 4e9 && flops >= 150.0 * pack_bytes;
 }
 
 // Pack both operands and run the product with the tile of the lowest
@@ -390,7 +411,9 @@ void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles
 // 3601 x 5000 x 5000 (x 5) split product: 256 x 256 with 8 waves (one block
 // per CU, two waves per SIMD) 344 TFLOP/s, 128 x 128 with 4 waves (two
 // blocks per CU) 305, 256 x 128 and 128 x 256 with 4 waves (one block per
-// CU) 269 and 256, 256 x 256 with 4 waves spills.
+// CU) 269 and 256, 256 x 256 with 4 waves spills.  A three-stage variant
+// (loads two steps ahead, the next step's fragments read during the current
+// products; 8-wave 256 x 128, 144 KB of LDS) ran 278.
 #ifndef MLCC_GEMM_TILES_PLANES
 #define MLCC_GEMM_TILES_PLANES(X) X(256, 256, 2, 4) X(128, 128, 2, 2)
 #endif

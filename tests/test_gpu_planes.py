@@ -215,3 +215,33 @@ def test_planes_large_product_default_rule():
         ref = ah @ bh + ah @ bl + al @ bh
         assert abs(got[z, m, n] - ref) <= TOL_ACC * (np.sqrt(K) + 1.0), (z, m, n)
     ctx.close()
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_planes_unaligned_operands(plain):
+    """Operands that start off a 16-byte boundary (A shifted by 1 element, B
+    by 3): the packing pass gathers them element by element."""
+    M, N, K, R, Z = 290, 270, 84, 2, 2
+    ctx = mlcc.Context(0)
+    rng = np.random.default_rng(41 + plain)
+    sA = [K, 1, M * K, M * K * R]
+    sB = [1, K, K * N, K * N * R]
+    A = rng.standard_normal(1 + M * K * R * Z).astype(np.float32)
+    B = rng.standard_normal(3 + K * N * R * Z).astype(np.float32)
+    ah, al = split_planes(A[1:])
+    bh, bl = split_planes(B[3:])
+    ref = batched(ah, sA, bh, sB, M, N, K, R, Z)
+    if not plain:
+        ref += batched(ah, sA, bl, sB, M, N, K, R, Z) + batched(al, sA, bh, sB, M, N, K, R, Z)
+    Ad = torch.tensor(A, device="cuda")[1:]
+    Bd = torch.tensor(B, device="cuda")[3:]
+    prec = "bf16" if plain else "bf16x3"
+    if plain:
+        ctx.bf16_map(["gemm"])
+    ctx.gemm_planes(1)
+    Cd = torch.zeros(Z * M * N, device="cuda")
+    ctx.gemm(mlcc.PREC[prec], M, N, K, R, Z, 1.0, Ad, sA, Bd, sB, 0.0, Cd, [N, 1, M * N])
+    assert ctx.bytes() >= plane_bytes(M, N, K, R, Z, False, 1 if plain else 2)
+    got = Cd.cpu().numpy().astype(np.float64).reshape(Z, M, N)
+    assert np.abs(got - ref).max() <= TOL_ACC * (np.sqrt(K * R) + 1.0)
+    ctx.close()
