@@ -237,7 +237,9 @@ mlcc_status mlcc_davidson_solve(mlcc_problem *prob, int32_t n_roots,
 typedef struct {
   int32_t max_slots;        /* requests on the device at once (0 -> 8) */
   int32_t max_queue;        /* waiting requests before MLCC_E_BUSY (0 -> 1024) */
-  uint64_t hbm_budget;      /* bytes for admitted requests (0 -> context budget) */
+  uint64_t hbm_budget;      /* bytes for admitted requests (0 -> the context's
+                               budget, else 90% of the device memory that is
+                               free or held idle by the context) */
   uint64_t host_budget;     /* host bytes that the input copies of waiting (and
                                admitted, until staged on the device) requests may
                                hold (0 -> a quarter of the host's physical memory) */

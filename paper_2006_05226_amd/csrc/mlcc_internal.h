@@ -69,12 +69,30 @@ struct Alloc {
   std::map<uintptr_t, size_t> live;         // root: base -> capacity
   std::multimap<size_t, void *> cache;      // capacity -> block, released on this stream
   std::multimap<size_t, void *> idle;       // root: capacity -> block no pending work uses
+  std::vector<Alloc *> lanes;               // root: the attached lanes' allocators
   void *get(size_t bytes);
   void put(void *p, size_t bytes);
   bool owns(const void *p);
   void quiesce();  // this allocator's stream is idle: cached blocks become idle in the root
-  void trim();     // root: idle blocks back to the device
-  void reclaim();  // under memory pressure: wait for this stream, then quiesce and trim
+  // root: idle blocks back to the device, the largest first, until at least
+  // need bytes are freed (0: all of them)
+  void trim(size_t need = 0);
+  // under memory pressure: wait for this stream, then quiesce and trim
+  void reclaim(size_t need = 0);
+  // root, when reclaim() did not free enough: every attached lane's cached
+  // blocks (and the root's own), each after its stream has finished the work
+  // enqueued before, become idle; then trim
+  void reclaim_all(size_t need = 0);
+  // a block that this allocator's stream no longer needs and that nothing
+  // later on this stream is expected to reuse (a one-off staging copy):
+  // idle in the root at once, after the stream has finished the work
+  // enqueued before, so that every lane may reuse it (or trim free it)
+  void put_idle(void *p);
+  // root: bytes of its idle blocks and of the blocks cached on its own stream
+  // (device memory that reclaim returns on demand)
+  size_t reusable();
+  void attach(Alloc *lane);  // root: a lane whose cache reclaim_all may empty
+  void detach(Alloc *lane);  // root: before the lane's stream is destroyed
   void release_all();  // root, at the end: every cached and idle block back to the device
   Alloc() = default;
   Alloc(const Alloc &) = delete;
@@ -111,6 +129,11 @@ struct DBuf {
   }
   void release() {
     if (p && al) al->put(p, bytes);
+    p = nullptr;
+    bytes = 0;
+  }
+  void release_idle() {
+    if (p && al) al->put_idle(p);
     p = nullptr;
     bytes = 0;
   }

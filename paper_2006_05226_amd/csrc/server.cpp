@@ -16,6 +16,7 @@
 //   the result and the submit / admit / done times go to the ticket table that
 //   mlcc_poll reads.  The kernels and reductions are deterministic, so a
 //   request gives the same result alone and in a mix.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -80,19 +81,20 @@ namespace {
 // and the DIIS history) before the packed BF16 planes of its large products;
 // *setup_out receives the set-up peak (L, plus its FP64 staging copy in FP32
 // mode).  0 for invalid input.
+// *planes_out receives the packed BF16 planes a split- or plain-BF16 request
+// may hold at once (0 for the other tiers and without doubles): those of its
+// largest products, the doubles-to-singles products of a pair block or of
+// the full doubles (R rows of pairs, b trial vectors, J Cholesky vectors):
+// 2 planes x 2 bytes x (1 + b) R x max(J + 1, R), rows and reduction padded,
+// at most the engine's cap.  A lane runs the request with this cap, so a
+// product whose planes need more runs unpacked.
 double solve_bytes(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_solver_opts *es,
-                   double *setup_out);
+                   double *setup_out, double *planes_out);
 
-// The packed BF16 planes a split- or plain-BF16 request may hold at once:
-// half its solve peak (the planes of a product are about its FP32 operands'
-// bytes, and the largest operands are a fraction of the solve peak), at
-// most the engine's cap; 0 for the FP64 and FP32 tiers.  A lane runs the
-// request with this cap, so a product whose planes need more runs unpacked.
 uint64_t planes_share(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_solver_opts *es) {
-  if (!d || (d->precision != MLCC_BF16X3 && d->precision != MLCC_BF16)) return 0;
-  double setup = 0.0;
-  const double run = solve_bytes(d, n_roots, es, &setup);
-  return (uint64_t)std::min<double>((double)mlcc::kPlaneBytesMax, 0.5 * run);
+  double setup = 0.0, planes = 0.0;
+  solve_bytes(d, n_roots, es, &setup, &planes);
+  return (uint64_t)planes;
 }
 }  // namespace
 
@@ -104,14 +106,15 @@ uint64_t planes_share(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_so
 extern "C" uint64_t mlcc_request_footprint(const mlcc_problem_desc *d, int32_t n_roots,
                                            const mlcc_solver_opts *es) {
   if (!d || n_roots < 1) return 0;
-  double setup = 0.0;
-  const double run = solve_bytes(d, n_roots, es, &setup) + (double)planes_share(d, n_roots, es);
+  double setup = 0.0, planes = 0.0;
+  const double run = solve_bytes(d, n_roots, es, &setup, &planes) + planes;
   return (uint64_t)(std::max(setup, run) * 1.15) + (160ull << 20);
 }
 
 namespace {
 double solve_bytes(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_solver_opts *es,
-                   double *setup_out) {
+                   double *setup_out, double *planes_out) {
+  *setup_out = *planes_out = 0.0;
   if (!d || n_roots < 1) return 0.0;
   const double O = d->n_occ, V = d->n_vir, J = d->n_chol, n = O + V;
   const bool dbl = d->model != MLCC_CCS && d->n_occ_act > 0 && d->n_vir_act > 0;
@@ -137,14 +140,28 @@ double solve_bytes(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_solve
   run += 5.0 * (J + 1.0) * M * ts;            // packed L_ai (two orders), L~_ai, Z, dot scratch
   run += J * O * O * ts;                      // L~_oo transposed
   run += b * (per_v + 3.0 * n1 * ts);         // transform batch: W, dL~, Zc, P, trial singles
+  // packed planes of a product: 2 planes x 2 bytes per element of a shared
+  // operand (ra rows) and z batched ones (rb rows), reduction k
+  auto plane_bytes = [](double ra, double rb, double k, double z) {
+    auto up = [](double x, double m) { return std::ceil(x / m) * m; };
+    return 4.0 * up(k, 64.0) * (up(ra, 256.0) + z * up(rb, 256.0));
+  };
+  double planes = 0.0;
   if (mlcc2 && dbl) {
     run += MM * ts;                           // ground-state u kept for the Jacobian
     const int nz = eff ? (int)b : 1;
     const double R = std::min((double)mlcc::pair_block_occ((int)o, (int)v, nz, (int)ts), o) * v;
     run += nz * R * R * (16.0 + 2.0 * ts);    // pair blocks of the doubles
     if (!eff) run += MM * b * (8.0 + ts);     // G and u(c2) of full-space batches
+    // ground state: g~ and Z of single pair blocks; effective transformation:
+    // the same for b vectors; full space: G of the batch
+    const double R1 = std::min((double)mlcc::pair_block_occ((int)o, (int)v, 1, (int)ts), o) * v;
+    planes = std::max(plane_bytes(R1, R1, J, 1.0), plane_bytes(J + 1.0, R1, R1, 1.0));
+    if (eff) planes = std::max({planes, plane_bytes(R, R, J, b), plane_bytes(J + 1.0, R, R, b)});
+    else planes = std::max(planes, plane_bytes(M, b * M, J, 1.0));
   }
   if (ccsd && dbl) {
+    planes = std::max(plane_bytes(M, M, J, 1.0), plane_bytes(M, b * M, J, 1.0));
     run += MM * (8.0 * 2 + ts * 4) + MM * b * (ts + 8.0);  // t2, Omega_2, u, copies; G, u(c2)
     run += (vt * v * vt * v + O * v * vt * v + O * o * M) * ts + 16.0 * MM * ts;  // integral blocks
   }
@@ -152,6 +169,8 @@ double solve_bytes(const mlcc_problem_desc *d, int32_t n_roots, const mlcc_solve
   run += dim * 8.0 * (2.0 * space + 3.0 * (n_roots + 2));  // Davidson
   run += 2.0 * 8.0 * (n1 + (ccsd ? MM : 0.0)) * 8;         // DIIS
   *setup_out = setup;
+  if (d->precision == MLCC_BF16X3 || d->precision == MLCC_BF16)
+    *planes_out = std::min((double)mlcc::kPlaneBytesMax, planes);
   return run;
 }
 }  // namespace
@@ -251,7 +270,9 @@ mlcc_status mlcc_server_create(mlcc_context *ctx, const mlcc_server_opts *opts,
       delete s;
       return MLCC_E_DEVICE;
     }
-    budget = (uint64_t)(fr * 0.9);
+    // blocks the context holds idle or cached count as free: they are
+    // returned to the device when the lanes need the memory
+    budget = (uint64_t)((fr + ctx->al.reusable()) * 0.9);
   }
   if (host_budget == 0) {
     const long pages = sysconf(_SC_PHYS_PAGES), page = sysconf(_SC_PAGE_SIZE);
@@ -280,6 +301,7 @@ mlcc_status mlcc_server_create(mlcc_context *ctx, const mlcc_server_opts *opts,
       return MLCC_E_DEVICE;
     }
   }
+  for (auto &l : s->lanes) ctx->al.attach(&l->al);
   for (auto &l : s->lanes) s->workers.emplace_back(&mlcc_server::work, s, l.get());
   ctx->refs.fetch_add(1);  // dropped by mlcc_server_destroy
   *out = s;
@@ -304,6 +326,7 @@ mlcc_status mlcc_server_destroy(mlcc_server *s) {
     l->ex.red.release();
     l->ex.planes.release();
     l->al.quiesce();
+    s->ctx->al.detach(&l->al);
     if (l->ex.stream) (void)hipStreamDestroy(l->ex.stream);
     if (l->ex.pinned) (void)hipHostFree(l->ex.pinned);
   }
