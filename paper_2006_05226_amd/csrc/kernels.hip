@@ -391,22 +391,68 @@ __global__ void k_energy_singles(int64_t n, int O, const T *Lt, const T *L, doub
   if (threadIdx.x == 0) part[K] = 2.0 * trs * trs - qqs;
 }
 
+// Tile geometry of k_permute4_tiled: extents of dst dimension 3 and d (the
+// one along which src is contiguous) and of the outer pair (a, b), their
+// src strides (s*) and dst strides (d*), tile counts along 3 and d.
+struct P4 {
+  int64_t n3, nd, nb, t3, td;
+  int64_t s3, sd, sa, sb;
+  int64_t dd, da, db;
+};
+
 // dst[j0][j1][j2][j3] (contiguous, dims n0..n3) = a * src[sum j_k s_k] + b * dst
-template <typename TD, typename TS>
-__global__ void k_permute4(TD *dst, const TS *src, int64_t n0, int64_t n1, int64_t n2, int64_t n3,
-                           int64_t s0, int64_t s1, int64_t s2, int64_t s3, double a, double b) {
-  const int64_t total = n0 * n1 * n2 * n3;
-  GRID_STRIDE(t, total) {
-    int64_t r = t;
-    const int64_t j3 = r % n3;
+// Element by element in dst order (IT: the index type, 32-bit when the
+// array allows it); coalesced on both sides when s3 is 1.
+template <typename TD, typename TS, typename IT>
+__global__ void k_permute4(TD *dst, const TS *src, IT n0, IT n1, IT n2, IT n3, int64_t s0,
+                           int64_t s1, int64_t s2, int64_t s3, double a, double b) {
+  const IT total = n0 * n1 * n2 * n3;
+  for (IT t = (IT)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += (IT)gridDim.x * blockDim.x) {
+    IT r = t;
+    const IT j3 = r % n3;
     r /= n3;
-    const int64_t j2 = r % n2;
+    const IT j2 = r % n2;
     r /= n2;
-    const int64_t j1 = r % n1;
-    const int64_t j0 = r / n1;
+    const IT j1 = r % n1;
+    const IT j0 = r / n1;
     double v = a * (double)src[j0 * s0 + j1 * s1 + j2 * s2 + j3 * s3];
     if (b != 0.0) v += b * (double)dst[t];
     dst[t] = (TD)v;
+  }
+}
+
+// The same when src is contiguous along dst dimension d < 3 instead: 32 x 32
+// tiles over (j_d, j3) through LDS, read along j_d and written along j3, so
+// that both sides are coalesced.  Block q: tile (q3, qd) of the pair of
+// indices (ja, jb) over the other two dimensions (a < b).
+template <typename TD, typename TS>
+__global__ __launch_bounds__(256) void k_permute4_tiled(TD *dst, const TS *src, P4 p, double a,
+                                                          double b) {
+  __shared__ double tile[32][33];
+  int64_t q = blockIdx.x;
+  const int64_t q3 = q % p.t3;
+  q /= p.t3;
+  const int64_t qd = q % p.td;
+  q /= p.td;
+  const int64_t jb = q % p.nb, ja = q / p.nb;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const int64_t sbase = ja * p.sa + jb * p.sb, dbase = ja * p.da + jb * p.db;
+  const int64_t jd0 = qd * 32, j30 = q3 * 32;
+#pragma unroll
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t j3 = j30 + k, jd = jd0 + tx;
+    if (j3 < p.n3 && jd < p.nd) tile[k][tx] = (double)src[sbase + jd * p.sd + j3 * p.s3];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t jd = jd0 + k, j3 = j30 + tx;
+    if (j3 < p.n3 && jd < p.nd) {
+      const int64_t o = dbase + jd * p.dd + j3;
+      double v = a * tile[tx][k];
+      if (b != 0.0) v += b * (double)dst[o];
+      dst[o] = (TD)v;
+    }
   }
 }
 
@@ -648,8 +694,44 @@ void permute4(Exec &ex, TD *dst, const TS *src, const int64_t n[4], const int64_
               double b) {
   const int64_t total = n[0] * n[1] * n[2] * n[3];
   if (total <= 0) return;
-  hipLaunchKernelGGL((k_permute4<TD, TS>), dim3(blocks_for(total)), dim3(TPB), 0, ex.stream, dst,
-                     src, n[0], n[1], n[2], n[3], s[0], s[1], s[2], s[3], a, b);
+  // the dst dimension along which src is contiguous, if not the last one
+  int d = -1;
+  if (std::llabs(s[3]) != 1 && n[3] > 1)
+    for (int k = 2; k >= 0; --k)
+      if (std::llabs(s[k]) == 1 && n[k] > 1) {
+        d = k;
+        break;
+      }
+  if (d >= 0) {
+    const int64_t dstride[4] = {n[1] * n[2] * n[3], n[2] * n[3], n[3], 1};
+    int o2[2], m = 0;
+    for (int k = 0; k < 3; ++k)
+      if (k != d) o2[m++] = k;
+    P4 p;
+    p.n3 = n[3];
+    p.nd = n[d];
+    p.nb = n[o2[1]];
+    p.t3 = (n[3] + 31) / 32;
+    p.td = (n[d] + 31) / 32;
+    p.s3 = s[3];
+    p.sd = s[d];
+    p.sa = s[o2[0]];
+    p.sb = s[o2[1]];
+    p.dd = dstride[d];
+    p.da = dstride[o2[0]];
+    p.db = dstride[o2[1]];
+    const int64_t blocks = p.t3 * p.td * n[o2[0]] * n[o2[1]];
+    MLCC_REQUIRE(blocks < ((int64_t)1 << 31), MLCC_E_ARG, "permute4: array too large");
+    hipLaunchKernelGGL((k_permute4_tiled<TD, TS>), dim3((unsigned)blocks), dim3(256), 0, ex.stream,
+                       dst, src, p, a, b);
+  } else if (total < ((int64_t)1 << 30)) {  // t + grid stride stays below 2^31
+    hipLaunchKernelGGL((k_permute4<TD, TS, int32_t>), dim3(blocks_for(total)), dim3(TPB), 0,
+                       ex.stream, dst, src, (int32_t)n[0], (int32_t)n[1], (int32_t)n[2],
+                       (int32_t)n[3], s[0], s[1], s[2], s[3], a, b);
+  } else {
+    hipLaunchKernelGGL((k_permute4<TD, TS, int64_t>), dim3(blocks_for(total)), dim3(TPB), 0,
+                       ex.stream, dst, src, n[0], n[1], n[2], n[3], s[0], s[1], s[2], s[3], a, b);
+  }
   MLCC_HIP(hipGetLastError());
 }
 template void permute4<double, double>(Exec &, double *, const double *, const int64_t *,
