@@ -35,6 +35,8 @@ void gemm_f32(Exec &ex, const GemmArgs &a) {
     } else {
       gk::dispatch_load<float, float>(ex, a, kSplitTiles, count(kSplitTiles), 48.0);
     }
+  } else if (gk::planes_any_layout(ex, a)) {
+    gk::gemm_planes<float>(ex, a, false, kSplitPlanes, count(kSplitPlanes));
   } else if (a.K > 0 && a.R > 0 && gk::gemm_vonly(a, gk::Tr<float>::VEC)) {
     gk::dispatch_load<float, float>(ex, a, kTiles, count(kTiles), 16.0);
   } else {

@@ -33,12 +33,12 @@ constexpr int kPlaneRowPad = 256;  // the largest tile dimension of the menu
 constexpr int kPlaneKPad = 64;
 
 // One operand seen as Z batches of `rows` rows, each row R slices of K
-// contiguous elements (unit stride along k, the condition of the split
-// products), with an optional two-level row index.
+// elements, with an optional two-level row index: contiguous along k
+// (s_k = 1, k_pack_planes) or along the rows (k_pack_planes_t).
 struct PackArgs {
   const float *X;
   int64_t rows, K, R, Z;
-  int64_t s_row, s_r, s_z;
+  int64_t s_row, s_r, s_z, s_k;
   int64_t lo, s_hi;        // two-level row index (lo <= 0: one level)
   int64_t rows_p, kp;      // padded plane extents
   __bf16 *hi, *lo_plane;   // [Z][rows_p][kp]; lo_plane unused for plain products
@@ -91,6 +91,45 @@ template <bool PLAIN> __global__ __launch_bounds__(256) void k_pack_planes(PackA
   const int64_t o = rz * a.kp + k0;
   *reinterpret_cast<bf8v *>(a.hi + o) = h;
   if constexpr (!PLAIN) *reinterpret_cast<bf8v *>(a.lo_plane + o) = l;
+}
+
+// Operands contiguous along the rows: 64 rows x 64 k' per block, read along
+// the rows into an LDS tile, written as 16-byte groups of each plane.
+template <bool PLAIN> __global__ __launch_bounds__(256) void k_pack_planes_t(PackArgs a) {
+  __shared__ float t[64][65];
+  const int64_t tk_n = a.kp / 64, tm_n = a.rows_p / 64;
+  int64_t q = blockIdx.x;
+  const int64_t tk = q % tk_n;
+  q /= tk_n;
+  const int64_t tm = q % tm_n, z = q / tm_n;
+  const int64_t m0 = tm * 64, k0 = tk * 64, KK = a.R * a.K;
+  const float *X = a.X + z * a.s_z;
+  const int tid = threadIdx.x;
+  for (int e = 0; e < 16; ++e) {
+    const int u = tid + e * 256, dm = u & 63, dk = u >> 6;
+    const int64_t m = m0 + dm, kk = k0 + dk;
+    float x = 0.0f;
+    if (m < a.rows && kk < KK) {
+      const int64_t r = kk / a.K, k = kk - r * a.K;
+      x = X[two_level(m, a.lo, a.s_row, a.s_hi) + r * a.s_r + k * a.s_k];
+    }
+    t[dm][dk] = x;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int c = tid + e * 256, dm = c >> 3, ch = c & 7;
+    bf8v h, l;
+#pragma unroll
+    for (int qq = 0; qq < 8; ++qq) {
+      const float x = t[dm][ch * 8 + qq];
+      h[qq] = (__bf16)x;
+      l[qq] = (__bf16)(x - (float)h[qq]);
+    }
+    const int64_t o = (z * a.rows_p + m0 + dm) * a.kp + k0 + ch * 8;
+    *reinterpret_cast<bf8v *>(a.hi + o) = h;
+    if constexpr (!PLAIN) *reinterpret_cast<bf8v *>(a.lo_plane + o) = l;
+  }
 }
 
 struct PlaneOps {
@@ -254,6 +293,16 @@ inline PlaneGeom plane_geom(const GemmArgs &a, bool plain) {
 }
 
 inline void pack_planes(Exec &ex, PackArgs pa) {
+  if (pa.s_k != 1) {  // contiguous along the rows: through LDS tiles
+    const int64_t blocks = pa.Z * (pa.rows_p / 64) * (pa.kp / 64);
+    MLCC_REQUIRE(blocks < ((int64_t)1 << 31), MLCC_E_ARG, "gemm: operand planes too large");
+    if (pa.lo_plane)
+      hipLaunchKernelGGL(k_pack_planes_t<false>, dim3((unsigned)blocks), dim3(256), 0, ex.stream, pa);
+    else
+      hipLaunchKernelGGL(k_pack_planes_t<true>, dim3((unsigned)blocks), dim3(256), 0, ex.stream, pa);
+    MLCC_HIP(hipGetLastError());
+    return;
+  }
   // 16-byte groups: K a multiple of 4 and every group start 16-byte aligned
   const bool lo_ok = pa.lo <= 0 || pa.s_hi % 4 == 0;
   pa.vec4 = pa.K % 4 == 0 && pa.s_row % 4 == 0 && pa.s_r % 4 == 0 && pa.s_z % 4 == 0 && lo_ok &&
@@ -319,14 +368,25 @@ struct PlaneTile {
 // plain BF16 ~370 and ~700, so packing pays above ~130 (split) and ~130
 // (plain) flops per packed byte; 150 is the rule, with at least 4 GFLOP so
 // that the two extra launches stay negligible.
-inline bool use_planes(const Exec &ex, const GemmArgs &a, bool plain) {
+// ratio: the flops per packed byte above which packing pays (150 against the
+// unpacked split kernel; 40 for split products whose operand layout leaves
+// only FP32 MFMA, ~100 TFLOP/s, as the alternative).
+inline bool use_planes(const Exec &ex, const GemmArgs &a, bool plain, double ratio = 150.0) {
   if (a.work || ex.planes_mode < 0) return false;
   const PlaneGeom g = plane_geom(a, plain);
   if (g.total() > ex.planes_cap) return false;
   if (ex.planes_mode > 0) return true;
   const double flops = 2.0 * (double)a.M * a.N * a.K * a.R * a.Z;
   const double pack_bytes = (4.0 / (2.0 * g.pl) + 1.0) * (double)g.total();
-  return flops >= 4e9 && flops >= 150.0 * pack_bytes;
+  return flops >= 4e9 && flops >= ratio * pack_bytes;
+}
+
+// Split products on packed planes for operands the split kernel cannot read
+// (contiguous along m or n, or unaligned groups): any FP32 layout once
+// packed; not for contractions on the plain-BF16 map, which keep FP32 MFMA
+// there as their accuracy study measured.
+inline bool planes_any_layout(const Exec &ex, const GemmArgs &a) {
+  return a.bf16x3 && !a.bf16_plain && a.K > 0 && a.R > 0 && use_planes(ex, a, false, 40.0);
 }
 
 // Pack both operands and run the product with the tile of the lowest
@@ -354,18 +414,17 @@ void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles
     ev = ex.prof->next();
     MLCC_HIP(hipEventRecord(ev.first, ex.stream));
   }
-  MLCC_REQUIRE(a.sAk == 1 && a.sBk == 1, MLCC_E_ARG, "gemm: packed planes need k-contiguous operands");
   PackArgs pa;
   pa.X = static_cast<const float *>(a.A);
   pa.rows = a.M; pa.K = a.K; pa.R = a.R; pa.Z = g.za;
-  pa.s_row = a.sAm; pa.s_r = a.sAr; pa.s_z = a.sAz;
+  pa.s_row = a.sAm; pa.s_r = a.sAr; pa.s_z = a.sAz; pa.s_k = a.sAk;
   pa.lo = a.Mlo; pa.s_hi = a.sAm_hi;
   pa.rows_p = g.mp; pa.kp = g.kp;
   pa.hi = const_cast<__bf16 *>(po.ah); pa.lo_plane = const_cast<__bf16 *>(po.al);
   pack_planes(ex, pa);
   pa.X = static_cast<const float *>(a.B);
   pa.rows = a.N; pa.Z = g.zb;
-  pa.s_row = a.sBn; pa.s_r = a.sBr; pa.s_z = a.sBz;
+  pa.s_row = a.sBn; pa.s_r = a.sBr; pa.s_z = a.sBz; pa.s_k = a.sBk;
   pa.lo = a.Nlo; pa.s_hi = a.sBn_hi;
   pa.rows_p = g.np;
   pa.hi = const_cast<__bf16 *>(po.bh); pa.lo_plane = const_cast<__bf16 *>(po.bl);

@@ -245,3 +245,60 @@ def test_planes_unaligned_operands(plain):
     got = Cd.cpu().numpy().astype(np.float64).reshape(Z, M, N)
     assert np.abs(got - ref).max() <= TOL_ACC * (np.sqrt(K * R) + 1.0)
     ctx.close()
+
+
+# operand layouts the unpacked split kernel cannot read: A contiguous along m,
+# B contiguous along n, k groups cut by a K that is not a multiple of 4
+LAYOUTS = [("m", "n", 84), ("m", "k", 84), ("k", "n", 84), ("k", "k", 83), ("m", "n", 83)]
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_planes_any_operand_layout(layout):
+    """Split products of any operand layout run on packed planes (the packing
+    pass transposes operands contiguous along m or n through LDS tiles)."""
+    al_, bl_, K = layout
+    M, N, R, Z = 290, 270, 2, 2
+    ctx = mlcc.Context(0)
+    rng = np.random.default_rng(abs(hash(layout)) % 2**32)
+    sAm, sAk = (K, 1) if al_ == "k" else (1, M)
+    sBk, sBn = (N, 1) if bl_ == "n" else (1, K)
+    sA = [sAm, sAk, M * K, M * K * R]
+    sB = [sBk, sBn, K * N, K * N * R]
+    A = rng.standard_normal(M * K * R * Z).astype(np.float32)
+    B = rng.standard_normal(K * N * R * Z).astype(np.float32)
+    ah, al = split_planes(A)
+    bh, bl = split_planes(B)
+    ref = (batched(ah, sA, bh, sB, M, N, K, R, Z) + batched(ah, sA, bl, sB, M, N, K, R, Z)
+           + batched(al, sA, bh, sB, M, N, K, R, Z))
+    Ad = torch.tensor(A, device="cuda")
+    Bd = torch.tensor(B, device="cuda")
+    ctx.gemm_planes(1)
+    Cd = torch.zeros(Z * M * N, device="cuda")
+    ctx.gemm(mlcc.BF16X3, M, N, K, R, Z, 1.0, Ad, sA, Bd, sB, 0.0, Cd, [N, 1, M * N])
+    assert ctx.bytes() >= plane_bytes(M, N, K, R, Z, False, 2)
+    got = Cd.cpu().numpy().astype(np.float64).reshape(Z, M, N)
+    assert np.abs(got - ref).max() <= TOL_ACC * (np.sqrt(K * R) + 1.0)
+    ctx.close()
+
+
+def test_plain_map_keeps_fp32_for_other_layouts():
+    """A contraction on the plain-BF16 map whose operands the split kernel
+    cannot read keeps FP32 MFMA (as the map's accuracy study measured it),
+    also when packing is forced: bitwise the FP32 result."""
+    M, N, K, R = 200, 180, 96, 2
+    ctx = mlcc.Context(0)
+    rng = np.random.default_rng(51)
+    sA = [1, M, M * K, 0]   # A contiguous along m
+    sB = [N, 1, K * N, 0]   # B contiguous along n
+    Ad = torch.tensor(rng.standard_normal(M * K * R).astype(np.float32), device="cuda")
+    Bd = torch.tensor(rng.standard_normal(K * N * R).astype(np.float32), device="cuda")
+
+    def run(prec):
+        Cd = torch.zeros(M * N, device="cuda")
+        ctx.gemm(mlcc.PREC[prec], M, N, K, R, 1, 1.0, Ad, sA, Bd, sB, 0.0, Cd, [N, 1, 0])
+        return Cd.cpu().numpy()
+
+    ctx.bf16_map(["gemm"])
+    ctx.gemm_planes(1)
+    assert np.array_equal(run("bf16"), run("fp32"))
+    ctx.close()
