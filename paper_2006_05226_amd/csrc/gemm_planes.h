@@ -28,7 +28,7 @@
 namespace mlcc {
 namespace gk {
 
-constexpr int kPlaneBK = 32;       // k per step: one v_mfma_f32_16x16x32_bf16
+constexpr int kPlaneBK = 32;       // k of one v_mfma_f32_16x16x32_bf16
 constexpr int kPlaneRowPad = 256;  // the largest tile dimension of the menu
 constexpr int kPlaneKPad = 64;
 
@@ -137,46 +137,57 @@ struct PlaneOps {
   int64_t a_zs, b_zs;               // plane batch strides (0: one plane for every batch)
 };
 
-__device__ __forceinline__ int plane_swz(int r) { return (r >> 1) & 3; }
+// Chunk swizzle of a row of CH 16-byte chunks: chunk g of row r sits at
+// g ^ plane_swz<CH>(r).
+template <int CH> __device__ __forceinline__ int plane_swz(int r) { return (r >> 1) & (CH - 1); }
 
-// Fragments of one k-step of a wave, read from a stage of LDS (A planes at
-// As, B planes at Bs, each plane rows x 32 BF16 with swizzled chunks).
-template <int FM, int FN, int WTM, int WTN, bool PLAIN> struct PlaneFrags {
-  bf8v ah[FM], al[PLAIN ? 1 : FM], bh[FN], bl[PLAIN ? 1 : FN];
+// Fragments of one k-step (KS = 32 or 64 BF16, one or two MFMA k-slices) of a
+// wave, read from a stage of LDS (A planes at As, B planes at Bs, each plane
+// rows x KS BF16 with swizzled chunks); sw: this lane's swizzle.
+template <int FM, int FN, int WTM, int WTN, bool PLAIN, int KS> struct PlaneFrags {
+  static constexpr int NS = KS / kPlaneBK;
+  static_assert(NS == 1 || PLAIN, "two k-slices per step for plain products only");
+  bf8v ah[NS][FM], al[PLAIN ? 1 : FM], bh[NS][FN], bl[PLAIN ? 1 : FN];
   __device__ __forceinline__ void read(const __bf16 *As, int plane_a, const __bf16 *Bs, int plane_b,
-                                       int wm, int wn, int l16, int chunk) {
+                                       int wm, int wn, int l16, int g, int sw) {
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int o = (wn * WTN + j * 16 + l16) * kPlaneBK + chunk * 8;
-      bh[j] = *reinterpret_cast<const bf8v *>(Bs + o);
-      if constexpr (!PLAIN) bl[j] = *reinterpret_cast<const bf8v *>(Bs + plane_b + o);
-    }
+    for (int u = 0; u < NS; ++u) {
+      const int ch = (4 * u + g) ^ sw;
 #pragma unroll
-    for (int i = 0; i < FM; ++i) {
-      const int o = (wm * WTM + i * 16 + l16) * kPlaneBK + chunk * 8;
-      ah[i] = *reinterpret_cast<const bf8v *>(As + o);
-      if constexpr (!PLAIN) al[i] = *reinterpret_cast<const bf8v *>(As + plane_a + o);
+      for (int j = 0; j < FN; ++j) {
+        const int o = (wn * WTN + j * 16 + l16) * KS + ch * 8;
+        bh[u][j] = *reinterpret_cast<const bf8v *>(Bs + o);
+        if constexpr (!PLAIN) bl[j] = *reinterpret_cast<const bf8v *>(Bs + plane_b + o);
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i) {
+        const int o = (wm * WTM + i * 16 + l16) * KS + ch * 8;
+        ah[u][i] = *reinterpret_cast<const bf8v *>(As + o);
+        if constexpr (!PLAIN) al[i] = *reinterpret_cast<const bf8v *>(As + plane_a + o);
+      }
     }
   }
   // the products: all hi*hi first, then hi*lo, then lo*hi, so that
   // consecutive MFMAs never accumulate into the same registers
   __device__ __forceinline__ void mma(f4 (&acc)[FM][FN]) const {
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+    for (int u = 0; u < NS; ++u)
 #pragma unroll
-      for (int j = 0; j < FN; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][i], bh[u][j], acc[i][j], 0, 0, 0);
     if constexpr (!PLAIN) {
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[0][i], bl[j], acc[i][j], 0, 0, 0);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[0][j], acc[i][j], 0, 0, 0);
     }
   }
 };
@@ -195,12 +206,13 @@ template <int WM, int WN> struct PlaneWaves {
   static constexpr int NT = 64 * WM * WN;
 };
 
-template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN>
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS>
 __global__ __launch_bounds__((PlaneWaves<WM, WN>::NT)) void k_gemm_planes(KParams kp, PlaneOps po) {
   constexpr int NW = WM * WN, WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
   constexpr int PL = PLAIN ? 1 : 2;
-  constexpr int RA = BM * kPlaneBK, RB = BN * kPlaneBK;  // elements of one plane of a stage
-  constexpr int QA = PL * BM / 16, QB = PL * BN / 16;     // 1 KB loads per stage
+  constexpr int CH = KS / 8, RPL = 512 / KS;  // 16-byte chunks per row, rows per 1 KB load
+  constexpr int RA = BM * KS, RB = BN * KS;   // elements of one plane of a stage
+  constexpr int QA = PL * BM / RPL, QB = PL * BN / RPL;  // 1 KB loads per stage
   constexpr int EA = QA / NW, EB = QB / NW;
   static_assert(QA % NW == 0 && QB % NW == 0 && WTM % 16 == 0 && WTN % 16 == 0, "tile");
   static_assert(BM <= kPlaneRowPad && BN <= kPlaneRowPad && kPlaneRowPad % BM == 0 &&
@@ -218,30 +230,35 @@ __global__ __launch_bounds__((PlaneWaves<WM, WN>::NT)) void k_gemm_planes(KParam
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform over the wave
   const int wm = wave / WN, wn = wave % WN, l16 = lane & 15;
-  const int chunk = (lane >> 4) ^ plane_swz(l16);  // this lane's fragment chunk
+  const int sw = plane_swz<CH>(l16), g = lane >> 4;  // this lane's fragment chunk: (4u + g) ^ sw
   const int64_t m0 = tm * BM, n0 = tn * BN;
-  const int64_t kpad = kp.ktiles * kPlaneBK;
+  const int64_t kpad = kp.ktiles * KS;
   const int64_t s_begin = split * kp.steps_per_split;
   const int64_t s_end = min(kp.ktiles, s_begin + kp.steps_per_split);
 
-  // Load q of a stage covers plane q / (rows / 16), tile rows 16 (q % (rows
-  // / 16)) .. +15; its source is a wave-uniform offset plus this lane's
-  // offset (row lane / 4 of the 16, logical chunk (lane % 4) ^ swz).
-  const int64_t lane_off = (int64_t)(lane >> 2) * kpad + 8 * ((lane & 3) ^ plane_swz(lane >> 2));
-  const __bf16 *a_base = po.ah + z * po.a_zs + lane_off, *b_base = po.bh + z * po.b_zs + lane_off;
+  // Load q of a stage covers plane q / (rows / RPL), tile rows RPL (q % (rows
+  // / RPL)) .. +RPL-1; its source is a wave-uniform offset plus this lane's
+  // offset (row lane / CH of the RPL, logical chunk (lane % CH) ^ swz of the
+  // row, which for RPL = 8 depends on the parity of the load's row block).
+  const int dr = lane / CH, dc = lane % CH;
+  const int64_t lane_off0 = (int64_t)dr * kpad + 8 * (dc ^ plane_swz<CH>(dr));
+  const int64_t lane_off1 = (int64_t)dr * kpad + 8 * (dc ^ plane_swz<CH>(dr + RPL));
+  const __bf16 *a_base = po.ah + z * po.a_zs, *b_base = po.bh + z * po.b_zs;
   const int64_t a_lo = PLAIN ? 0 : po.al - po.ah, b_lo = PLAIN ? 0 : po.bl - po.bh;
   auto issue = [&](int stage, int64_t step) {
     __bf16 *As = lds + stage * STAGE, *Bs = As + PL * RA;
-    const int64_t k0 = step * kPlaneBK;
+    const int64_t k0 = step * KS;
 #pragma unroll
     for (int e = 0; e < EA; ++e) {
-      const int q = wave + NW * e, pl = q / (BM / 16), rq = q % (BM / 16);
-      load_lds16(a_base + ((pl ? a_lo : 0) + (m0 + rq * 16) * kpad + k0), As + pl * RA + rq * 512);
+      const int q = wave + NW * e, pl = q / (BM / RPL), rq = q % (BM / RPL);
+      const int64_t lo = (RPL == 16 || (rq & 1) == 0) ? lane_off0 : lane_off1;
+      load_lds16(a_base + ((pl ? a_lo : 0) + (m0 + rq * RPL) * kpad + k0 + lo), As + pl * RA + rq * 512);
     }
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
-      const int q = wave + NW * e, pl = q / (BN / 16), rq = q % (BN / 16);
-      load_lds16(b_base + ((pl ? b_lo : 0) + (n0 + rq * 16) * kpad + k0), Bs + pl * RB + rq * 512);
+      const int q = wave + NW * e, pl = q / (BN / RPL), rq = q % (BN / RPL);
+      const int64_t lo = (RPL == 16 || (rq & 1) == 0) ? lane_off0 : lane_off1;
+      load_lds16(b_base + ((pl ? b_lo : 0) + (n0 + rq * RPL) * kpad + k0 + lo), Bs + pl * RB + rq * 512);
     }
   };
 
@@ -260,9 +277,9 @@ __global__ __launch_bounds__((PlaneWaves<WM, WN>::NT)) void k_gemm_planes(KParam
   for (int64_t step = s_begin; step < s_end; ++step) {
     asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
-    PlaneFrags<FM, FN, WTM, WTN, PLAIN> fr;
+    PlaneFrags<FM, FN, WTM, WTN, PLAIN, KS> fr;
     const __bf16 *As = lds + cur * STAGE;
-    fr.read(As, RA, As + PL * RA, RB, wm, wn, l16, chunk);
+    fr.read(As, RA, As + PL * RA, RB, wm, wn, l16, g, sw);
     if (step + 1 < s_end) issue(cur ^ 1, step + 1);
     fr.mma(acc);
     cur ^= 1;
@@ -314,12 +331,12 @@ inline void pack_planes(Exec &ex, PackArgs pa) {
   MLCC_HIP(hipGetLastError());
 }
 
-template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN>
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS>
 void launch_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad, int splits) {
   KParams kp;
   kp.a = a;
   kp.splits = splits;
-  kp.ktiles = kpad / kPlaneBK;
+  kp.ktiles = kpad / KS;
   kp.steps_per_split = cdiv(kp.ktiles, splits);
   kp.tiles_m = (int)cdiv(a.M, BM);
   kp.tiles_n = (int)cdiv(a.N, BN);
@@ -329,7 +346,7 @@ void launch_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad
   MLCC_REQUIRE(kp.per_xcd * kXcd < (int64_t)1 << 31, MLCC_E_ARG, "gemm: grid too large");
   kp.work = nullptr;
   if (splits > 1) kp.work = ex.scratch(sizeof(float) * (size_t)splits * a.Z * a.M * a.N);
-  hipLaunchKernelGGL((k_gemm_planes<TC, BM, BN, WM, WN, PLAIN>), dim3((unsigned)(kp.per_xcd * kXcd)),
+  hipLaunchKernelGGL((k_gemm_planes<TC, BM, BN, WM, WN, PLAIN, KS>), dim3((unsigned)(kp.per_xcd * kXcd)),
                      dim3(64 * WM * WN), 0, ex.stream, kp, po);
   MLCC_HIP(hipGetLastError());
   if (splits > 1) {
@@ -340,12 +357,12 @@ void launch_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad
   }
 }
 
-template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN>
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS>
 int planes_occupancy(const GemmArgs &) {
   static std::atomic<int> cache{0};
   int nb = cache.load(std::memory_order_relaxed);
   if (nb > 0) return nb;
-  const void *f = reinterpret_cast<const void *>(&k_gemm_planes<TC, BM, BN, WM, WN, PLAIN>);
+  const void *f = reinterpret_cast<const void *>(&k_gemm_planes<TC, BM, BN, WM, WN, PLAIN, KS>);
   MLCC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * WM * WN, 0));
   nb = std::max(nb, 1);
   cache.store(nb, std::memory_order_relaxed);
@@ -354,7 +371,7 @@ int planes_occupancy(const GemmArgs &) {
 
 typedef void (*PlaneLaunchFn)(Exec &, const GemmArgs &, const PlaneOps &, int64_t, int);
 struct PlaneTile {
-  int bm, bn, waves;
+  int bm, bn, waves, ks;
   PlaneLaunchFn fn;
   OccFn occ;
 };
@@ -430,7 +447,7 @@ void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles
   pa.hi = const_cast<__bf16 *>(po.bh); pa.lo_plane = const_cast<__bf16 *>(po.bl);
   pack_planes(ex, pa);
 
-  const int64_t steps = g.kp / kPlaneBK, ncu = cu_count();
+  const int64_t ncu = cu_count();
   int forced = -1;
   for (int t = 0; t < ntiles; ++t)
     if (tiles[t].bm == ex.force_bm && tiles[t].bn == ex.force_bn) forced = t;
@@ -439,14 +456,14 @@ void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles
   for (int t = 0; t < ntiles; ++t) {
     if (forced >= 0 && t != forced) continue;
     const int bm = tiles[t].bm, bn = tiles[t].bn;
-    const int64_t occ = tiles[t].occ(a);
+    const int64_t occ = tiles[t].occ(a), steps = g.kp / tiles[t].ks;
     const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
     int64_t s = 1;
     if (blocks < occ * ncu && steps >= 8)
       s = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(occ * ncu / blocks, steps / 4), 128));
     const int64_t rounds = cdiv(blocks * s, occ * ncu);
     const double rate = tiles[t].waves == 8 ? 1.13 : 1.0;
-    double cost = (double)rounds * (double)cdiv(steps, s) * bm * bn * occ / rate;
+    double cost = (double)rounds * (double)cdiv(steps, s) * tiles[t].ks * bm * bn * occ / rate;
     if (s > 1) cost += 2.0 * (double)s * a.Z * a.M * a.N;
     if (best < 0 || cost < best_cost) {
       best = t;
@@ -466,7 +483,7 @@ void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles
 }  // namespace gk
 }  // namespace mlcc
 
-// Tile menu of the planes kernel: (BM, BN, WM, WN).  Measured on the
+// Tile menus of the planes kernel: (BM, BN, WM, WN, k per step).  Measured on the
 // 3601 x 5000 x 5000 (x 5) split product: 256 x 256 with 8 waves (one block
 // per CU, two waves per SIMD) 344 TFLOP/s, 128 x 128 with 4 waves (two
 // blocks per CU) 305, 256 x 128 and 128 x 256 with 4 waves (one block per
@@ -474,5 +491,9 @@ void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles
 // (loads two steps ahead, the next step's fragments read during the current
 // products; 8-wave 256 x 128, 144 KB of LDS) ran 278.
 #ifndef MLCC_GEMM_TILES_PLANES
-#define MLCC_GEMM_TILES_PLANES(X) X(256, 256, 2, 4) X(128, 128, 2, 2)
+#define MLCC_GEMM_TILES_PLANES(X) X(256, 256, 2, 4, 32) X(128, 128, 2, 2, 32)
+#endif
+// Plain products (one plane): k-steps of 64, two MFMA k-slices per barrier.
+#ifndef MLCC_GEMM_TILES_PLANES_PLAIN
+#define MLCC_GEMM_TILES_PLANES_PLAIN(X) X(256, 256, 2, 4, 64) X(128, 128, 2, 2, 64)
 #endif
