@@ -11,15 +11,16 @@
 // k-loop.  The conversion is the same as the split kernel's (round to
 // nearest even, twice), so both kernels multiply the same BF16 values.
 //
-// LDS layout: per operand, plane and stage, rows of 32 BF16 (64 bytes, four
-// 16-byte chunks).  One load instruction of a wave fills 1 KB of LDS, 16
-// rows, lane c writing bytes 16c..16c+15; the lane therefore loads logical
-// chunk (c % 4) ^ swz(row) of row c / 4, so that chunk g of row r sits at
-// physical chunk g ^ swz(r), swz(r) = (r / 2) % 4.  With it the 16-byte
-// fragment reads (16 rows, one chunk) run free of bank conflicts: measured
-// with SQ_LDS_BANK_CONFLICT on the 256 x 256 tile, 0 against 0.16 of the busy
-// cycles without a swizzle, with (r / 4) % 4, or with a variant that also
-// flips on bit 3 of r, and 0.71 against 0.65 matrix-core busy.
+// LDS layout: per operand, plane and stage, rows of KS BF16 (KS = 32 or 64
+// per k-step: CH = KS / 8 chunks of 16 bytes).  One load instruction of a
+// wave fills 1 KB of LDS (512 / KS rows), lane c writing bytes 16c..16c+15;
+// the lane therefore loads logical chunk (c % CH) ^ swz(row) of row c / CH,
+// so that chunk g of row r sits at physical chunk g ^ swz(r), swz(r) =
+// (r / 2) % CH.  With it the 16-byte fragment reads (16 rows, one chunk) run
+// free of bank conflicts: measured with SQ_LDS_BANK_CONFLICT on the 256 x 256
+// split tile, 0 against 0.16 of the busy cycles without a swizzle, with
+// (r / 4) % 4, or with a variant that also flips on bit 3 of r, and 0.71
+// against 0.65 matrix-core busy.
 #pragma once
 
 #include "gemm_kernel.h"
@@ -146,8 +147,7 @@ template <int CH> __device__ __forceinline__ int plane_swz(int r) { return (r >>
 // rows x KS BF16 with swizzled chunks); sw: this lane's swizzle.
 template <int FM, int FN, int WTM, int WTN, bool PLAIN, int KS> struct PlaneFrags {
   static constexpr int NS = KS / kPlaneBK;
-  static_assert(NS == 1 || PLAIN, "two k-slices per step for plain products only");
-  bf8v ah[NS][FM], al[PLAIN ? 1 : FM], bh[NS][FN], bl[PLAIN ? 1 : FN];
+  bf8v ah[NS][FM], al[NS][PLAIN ? 1 : FM], bh[NS][FN], bl[NS][PLAIN ? 1 : FN];
   __device__ __forceinline__ void read(const __bf16 *As, int plane_a, const __bf16 *Bs, int plane_b,
                                        int wm, int wn, int l16, int g, int sw) {
 #pragma unroll
@@ -157,13 +157,13 @@ template <int FM, int FN, int WTM, int WTN, bool PLAIN, int KS> struct PlaneFrag
       for (int j = 0; j < FN; ++j) {
         const int o = (wn * WTN + j * 16 + l16) * KS + ch * 8;
         bh[u][j] = *reinterpret_cast<const bf8v *>(Bs + o);
-        if constexpr (!PLAIN) bl[j] = *reinterpret_cast<const bf8v *>(Bs + plane_b + o);
+        if constexpr (!PLAIN) bl[u][j] = *reinterpret_cast<const bf8v *>(Bs + plane_b + o);
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
         const int o = (wm * WTM + i * 16 + l16) * KS + ch * 8;
         ah[u][i] = *reinterpret_cast<const bf8v *>(As + o);
-        if constexpr (!PLAIN) al[i] = *reinterpret_cast<const bf8v *>(As + plane_a + o);
+        if constexpr (!PLAIN) al[u][i] = *reinterpret_cast<const bf8v *>(As + plane_a + o);
       }
     }
   }
@@ -179,15 +179,19 @@ template <int FM, int FN, int WTM, int WTN, bool PLAIN, int KS> struct PlaneFrag
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][i], bh[u][j], acc[i][j], 0, 0, 0);
     if constexpr (!PLAIN) {
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+      for (int u = 0; u < NS; ++u)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[0][i], bl[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-      for (int i = 0; i < FM; ++i)
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u][i], bl[u][j], acc[i][j], 0, 0, 0);
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[0][j], acc[i][j], 0, 0, 0);
+      for (int u = 0; u < NS; ++u)
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int j = 0; j < FN; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u][i], bh[u][j], acc[i][j], 0, 0, 0);
     }
   }
 };
