@@ -154,3 +154,27 @@ def test_synthetic_request_alone_equals_served(ctx):
     assert r["status"] == mlcc.OK
     assert r["e_corr"] == g["energy"]
     assert np.array_equal(np.array(r["omega"][:3]), w)
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp64"])
+def test_request_runs_within_its_footprint(precision):
+    """Admission trusts the footprint estimate: a serving-stream request (the
+    size class of its largest members, n_occ 60) solves on a context whose
+    allocator may hold no more than that estimate."""
+    from paper_2006_05226_amd.synth import gen_eps
+    no = 60
+    nv, o = 10 * no, int(round(0.375 * no))
+    q = dict(n_occ=no, n_vir=nv, n_chol=3 * nv, n_occ_act=o, n_vir_act=10 * o, seed=77)
+    eps = gen_eps(q["n_occ"], q["n_vir"], q["n_occ_act"], q["seed"])
+    d, keep = mlcc.Server.desc(None, eps, q["n_occ"], q["n_vir"], q["n_occ_act"], q["n_vir_act"],
+                               "mlcc2", precision, n_chol=q["n_chol"], seed=q["seed"])
+    fp = mlcc.footprint(d, 3, True)
+    c = mlcc.Context(0, hbm_budget=fp)
+    P = mlcc.Problem(c, None, eps, q["n_occ"], q["n_vir"], q["n_occ_act"], q["n_vir_act"],
+                     model="mlcc2", precision=precision, n_chol=q["n_chol"], seed=q["seed"])
+    g = P.ground_state(tol=1e-6)
+    w = P.davidson(3, tol=1e-5, effective=True)
+    assert g["converged"] and w["converged"]
+    assert c.bytes() <= fp
+    P.close()
+    c.close()
