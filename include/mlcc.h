@@ -264,7 +264,10 @@ mlcc_status mlcc_server_destroy(mlcc_server *srv);
  * or its inputs alone the host budget (it could never be admitted);
  * MLCC_E_ARG for invalid descriptors.  The host copy of the Cholesky vectors
  * is dropped as soon as the admitted request has staged them on the device;
- * requests with MLCC_SYNTH_L hold none. */
+ * requests with MLCC_SYNTH_L hold none.  A request whose lane finds device
+ * memory exhausted first frees the idle and cached blocks of every lane of
+ * the server, then waits up to about a minute for other requests to return
+ * memory; only then does its result carry MLCC_E_OOM. */
 mlcc_status mlcc_submit(mlcc_server *srv, const mlcc_problem_desc *desc, int32_t n_roots,
                         const mlcc_solver_opts *gs_opts, const mlcc_solver_opts *es_opts,
                         uint64_t *ticket);
