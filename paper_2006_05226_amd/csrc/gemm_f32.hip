@@ -15,10 +15,10 @@ const gk::Tile kSplitTiles[] = {MLCC_GEMM_TILES_SPLIT(MLCC_TILE_ENTRY)};
 #define MLCC_TILE_ENTRY(BMv, BNv) {BMv, BNv, &gk::launch_tile<float, float, BMv, BNv, true, 2>, &gk::tile_occupancy<float, float, BMv, BNv, true, 2>},
 const gk::Tile kPlainTiles[] = {MLCC_GEMM_TILES_PLAIN(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
-#define MLCC_TILE_ENTRY(BMv, BNv, WMv, WNv, KSv) {BMv, BNv, WMv * WNv, KSv, &gk::launch_planes<float, BMv, BNv, WMv, WNv, false, KSv>, &gk::planes_occupancy<float, BMv, BNv, WMv, WNv, false, KSv>},
+#define MLCC_TILE_ENTRY(BMv, BNv, WMv, WNv, KSv, NSv) {BMv, BNv, WMv * WNv, KSv, &gk::launch_planes<float, BMv, BNv, WMv, WNv, false, KSv, NSv>, &gk::planes_occupancy<float, BMv, BNv, WMv, WNv, false, KSv, NSv>},
 const gk::PlaneTile kSplitPlanes[] = {MLCC_GEMM_TILES_PLANES(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
-#define MLCC_TILE_ENTRY(BMv, BNv, WMv, WNv, KSv) {BMv, BNv, WMv * WNv, KSv, &gk::launch_planes<float, BMv, BNv, WMv, WNv, true, KSv>, &gk::planes_occupancy<float, BMv, BNv, WMv, WNv, true, KSv>},
+#define MLCC_TILE_ENTRY(BMv, BNv, WMv, WNv, KSv, NSv) {BMv, BNv, WMv * WNv, KSv, &gk::launch_planes<float, BMv, BNv, WMv, WNv, true, KSv, NSv>, &gk::planes_occupancy<float, BMv, BNv, WMv, WNv, true, KSv, NSv>},
 const gk::PlaneTile kPlainPlanes[] = {MLCC_GEMM_TILES_PLANES_PLAIN(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
 template <typename T, int N> constexpr int count(const T (&)[N]) { return N; }
