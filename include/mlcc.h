@@ -31,7 +31,9 @@
  *   space): singles block followed by the doubles block.  Several vectors are
  *   stored back to back, [n_vec][dim].
  * Pointers.  Every array argument may be host memory or device memory on the
- *   context's GPU; the library tells them apart with hipPointerGetAttributes.
+ *   context's GPU; the library tells them apart with hipPointerGetAttributes
+ *   (with MLCC_INPUT_ON_DEVICE a problem descriptor's inputs must be device
+ *   memory).
  *   The caller owns every pointer it passes; inputs are copied before a call
  *   returns, outputs are written only into the caller's buffers and only when
  *   the call returns MLCC_OK (MLCC_E_NOCONV also fills best-so-far values).
@@ -113,7 +115,8 @@ typedef struct {
   int32_t precision;              /* MLCC_FP64 | MLCC_FP32 | MLCC_BF16X3 | MLCC_BF16 */
   const double *L;                /* [n_chol][n][n], symmetric in the last two */
   const double *eps;              /* [n] orbital energies in the order above */
-  uint32_t flags;                 /* MLCC_SYNTH_L, or 0 */
+  uint32_t flags;                 /* MLCC_SYNTH_L | MLCC_INPUT_ON_DEVICE |
+                                     MLCC_DETERMINISTIC, or 0 */
   uint64_t seed;                  /* seed of MLCC_SYNTH_L */
   const double *fock;             /* [n][n] symmetric Fock matrix (host or device), or
                                      NULL for diag(eps).  For a semicanonical basis
@@ -136,6 +139,21 @@ typedef struct {
  * benchmark and serving workloads too large to stage from the host; eps is
  * still read. */
 #define MLCC_SYNTH_L 1u
+/* flags: the caller states that L (unless MLCC_SYNTH_L), eps and fock (when
+ * not NULL) are device memory; the library checks each pointer and fails with
+ * MLCC_E_ARG for one that is not.  Without the flag each of them may be host
+ * or device memory (the library classifies them itself).  The server copies
+ * a submitted request's inputs in either case. */
+#define MLCC_INPUT_ON_DEVICE 2u
+/* flags: bitwise-reproducible results.  Residuals, transformations, ground
+ * states, Davidson roots and served results of a problem run on this
+ * library's kernels only, and every reduction among them has a fixed order
+ * (split-K partial sums are added by a separate pass in split order; no
+ * floating-point atomics), so for equal inputs, model, precision, context
+ * settings and device the results are bitwise equal, with or without this
+ * flag; it is accepted so that a caller can state the requirement.  Not
+ * covered: mlcc_cnto's eigenvectors, computed by rocSOLVER. */
+#define MLCC_DETERMINISTIC 4u
 
 typedef struct {
   double tol;             /* ground state: ||Omega||_2; Davidson: residual norm */

@@ -63,7 +63,15 @@ void check_desc(const mlcc_problem_desc *d) {
   MLCC_REQUIRE(d != nullptr, MLCC_E_ARG, "NULL problem descriptor");
   MLCC_REQUIRE((d->L != nullptr || (d->flags & MLCC_SYNTH_L)) && d->eps != nullptr, MLCC_E_ARG,
                "NULL L or eps");
-  MLCC_REQUIRE((d->flags & ~MLCC_SYNTH_L) == 0, MLCC_E_ARG, "unknown flags");
+  MLCC_REQUIRE((d->flags & ~(MLCC_SYNTH_L | MLCC_INPUT_ON_DEVICE | MLCC_DETERMINISTIC)) == 0,
+               MLCC_E_ARG, "unknown flags");
+  if (d->flags & MLCC_INPUT_ON_DEVICE) {
+    MLCC_REQUIRE((d->flags & MLCC_SYNTH_L) || is_device_ptr(d->L), MLCC_E_ARG,
+                 "MLCC_INPUT_ON_DEVICE: L is not device memory");
+    MLCC_REQUIRE(is_device_ptr(d->eps), MLCC_E_ARG, "MLCC_INPUT_ON_DEVICE: eps is not device memory");
+    MLCC_REQUIRE(!d->fock || is_device_ptr(d->fock), MLCC_E_ARG,
+                 "MLCC_INPUT_ON_DEVICE: fock is not device memory");
+  }
   MLCC_REQUIRE(d->n_occ >= 1 && d->n_vir >= 1 && d->n_chol >= 1, MLCC_E_ARG,
                "n_occ, n_vir and n_chol must be >= 1");
   MLCC_REQUIRE(d->model == MLCC_CCS || d->model == MLCC_MLCC2 || d->model == MLCC_MLCCSD ||

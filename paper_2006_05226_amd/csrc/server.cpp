@@ -205,6 +205,7 @@ void mlcc_server::work(Lane *lane) {
     out.n_roots = r->n_roots;
     try {
       mlcc_problem_desc d = r->desc;
+      d.flags &= ~MLCC_INPUT_ON_DEVICE;  // the inputs are the request's host copies now
       if (!(d.flags & MLCC_SYNTH_L)) d.L = r->L.data();
       d.eps = r->eps.data();
       d.fock = r->fock.empty() ? nullptr : r->fock.data();

@@ -37,6 +37,8 @@ class ProblemDesc(C.Structure):
 
 
 SYNTH_L = 1
+INPUT_ON_DEVICE = 2
+DETERMINISTIC = 4
 
 
 class SolverOpts(C.Structure):
@@ -291,11 +293,12 @@ class Problem:
 
     def __init__(self, ctx: Context, L, eps, n_occ, n_vir, n_occ_act=None, n_vir_act=None,
                  model="mlcc2", precision="fp64", n_chol=None, seed=None, fock=None,
-                 ccsd_space=None):
+                 ccsd_space=None, flags=0):
         """L=None with n_chol and seed: Cholesky vectors drawn on the device
         (MLCC_SYNTH_L).  fock: the full [n][n] Fock matrix of a semicanonical
         basis (eps its diagonal), or None for diag(eps).  ccsd_space:
-        (n_occ_ccsd, n_vir_ccsd) of model "mlccsd3" (three-level MLCCSD)."""
+        (n_occ_ccsd, n_vir_ccsd) of model "mlccsd3" (three-level MLCCSD).
+        flags: INPUT_ON_DEVICE and/or DETERMINISTIC, added to the descriptor."""
         self.ctx = ctx
         L = _f64(L)
         eps = _f64(eps)
@@ -307,7 +310,7 @@ class Problem:
                         n_occ if n_occ_act is None else n_occ_act,
                         n_vir if n_vir_act is None else n_vir_act,
                         MODEL[model], PREC[precision], _ptr(L), _ptr(eps),
-                        SYNTH_L if synth else 0, int(seed or 0), _ptr(fock),
+                        (SYNTH_L if synth else 0) | int(flags), int(seed or 0), _ptr(fock),
                         *(ccsd_space or (0, 0)))
         h = C.c_void_p()
         ctx.check(ctx.lib.mlcc_problem_create(ctx.h, C.byref(d), C.byref(h)))

@@ -97,6 +97,11 @@ def test_problem_descriptor_layout_matches_header():
     assert [n for n, _ in members] == [f[0] for f in fields]
     assert all(ct[t] is f[1] for (_, t), f in zip(members, fields))
     assert mlcc.MODEL["mlccsd3"] == int(re.search(r"#define MLCC_MLCCSD3 (\d+)", text).group(1))
+    for name in ("SYNTH_L", "INPUT_ON_DEVICE", "DETERMINISTIC"):
+        value = int(re.search(r"#define MLCC_%s (\d+)u" % name, text).group(1))
+        assert getattr(mlcc, name) == value, name
+    flags = [getattr(mlcc, n) for n in ("SYNTH_L", "INPUT_ON_DEVICE", "DETERMINISTIC")]
+    assert all(f & (f - 1) == 0 for f in flags) and len(set(flags)) == 3  # distinct bits
 
 
 def test_plain_c_client(tmp_path):
