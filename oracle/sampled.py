@@ -165,7 +165,7 @@ def s_analytic_rule(g, den):
     return -g / den
 
 
-def omega1_samples(Lsrc, eps, d: Dims, t1, pairs, s_rule=s_analytic_rule, act=None):
+def omega1_samples(Lsrc, eps, d: Dims, t1, pairs, s_rule=s_analytic_rule, act=None, x2=None):
     """Omega_AI (App. A, MLCC2 Omega vector) at the given (A, I):
 
       Omega_AI = F~_AI + [I act] sum_bcj u_bicj g~_Abjc - [A act] sum_jkb u_ajbk g~_kbjI
@@ -173,7 +173,8 @@ def omega1_samples(Lsrc, eps, d: Dims, t1, pairs, s_rule=s_analytic_rule, act=No
 
     with the doubles s given by s_rule(g~, eps) on the rows of g~ each term
     needs (all active pairs against (b, I) for fixed I, or against (a, j) for
-    fixed a)."""
+    fixed a), or, when x2 (v, o, v, o) is given, s = x2 (the singles of the
+    MLCCSD models, App. A, MLCCSD Omega vector)."""
     pairs = [(int(A), int(I)) for A, I in pairs]
     act = act or Active(Lsrc, t1, d)
     J = Lsrc.n_chol
@@ -192,8 +193,11 @@ def omega1_samples(Lsrc, eps, d: Dims, t1, pairs, s_rule=s_analytic_rule, act=No
     for I in Is:
         if I >= d.o:
             continue
-        g = _einsum("Kb,Kcj->bcj", act.vo[:, :, I], act.vo)               # g~_bI,cj
-        s = s_rule(g, D[:, I][:, None, None] + D[None, :, :])
+        if x2 is None:
+            g = _einsum("Kb,Kcj->bcj", act.vo[:, :, I], act.vo)           # g~_bI,cj
+            s = s_rule(g, D[:, I][:, None, None] + D[None, :, :])
+        else:
+            s = x2[:, I, :, :]                                             # x_bI,cj
         u = 2.0 * s - s.transpose(1, 0, 2)                                 # u_bIcj
         Z = _einsum("bcj,Kjc->Kb", u, act.ov)                              # Z^K_bI
         A1 = _ksum(lambda Ks: lt_block(Lsrc, t1, d, Ks, d.O + np.asarray(As), av),
@@ -212,8 +216,11 @@ def omega1_samples(Lsrc, eps, d: Dims, t1, pairs, s_rule=s_analytic_rule, act=No
     for A in As:
         if A >= d.v:
             continue
-        g = _einsum("Kj,Kbk->jbk", act.vo[:, A, :], act.vo)                # g~_aj,bk
-        s = s_rule(g, D[A, :][:, None, None] + D[None, :, :])
+        if x2 is None:
+            g = _einsum("Kj,Kbk->jbk", act.vo[:, A, :], act.vo)            # g~_aj,bk
+            s = s_rule(g, D[A, :][:, None, None] + D[None, :, :])
+        else:
+            s = x2[A]                                                      # x_aj,bk
         u = 2.0 * s - s.transpose(2, 1, 0)                                 # u_ajbk
         Z = _einsum("jbk,Kkb->Kj", u, act.ov)                              # Z^K_aj
         B1 = _ksum(lambda Ks: Z[Ks], lambda Ks: lt_block(Lsrc, t1, d, Ks, ao, np.asarray(Is)),

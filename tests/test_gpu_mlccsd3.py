@@ -3,6 +3,10 @@ FP64 oracle: residual and Jacobian transformation with CCSD-space outputs
 restricted inside a larger CC2 space (ragged multi-tile sizes, an empty and a
 one-sided CCSD space), the two-level limits, the ground state and the
 Davidson roots."""
+import hashlib
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -150,3 +154,61 @@ def test_fullsize_properties(ctx):
     assert dav["converged"] and dav["complex_roots"] == 0
     assert np.all(np.asarray(dav["omega"]) > 0)
     P.close()
+
+
+GOLD3 = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                     "samples_mlccsd3_60_600_2000.json")
+
+
+@pytest.fixture(scope="module")
+def gold3():
+    with open(GOLD3) as f:
+        return json.load(f)
+
+
+def _digest(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()[:16]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_fullsize_sampled_parity(ctx, gold3, precision):
+    """The three-level residual at full size (60/600/2000, CC2 space 30/300,
+    CCSD space 12/120, Cholesky vectors drawn on the device) element by
+    element against the sampled oracle (tests/golden/make_mlccsd3_samples.py:
+    doubles inside, across and outside the CCSD space, singles across every
+    orbital space), at sparse singles and doubles over the whole CC2 space."""
+    from paper_2006_05226_amd.synth import CONFIGS, device_cholesky_block, gen_eps
+    print(f"mlccsd3 full-size sampled parity {precision}", flush=True)
+    c = CONFIGS[gold3["config"]]
+    O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
+    ot, vt = c["n_occ_ccsd"], c["n_vir_ccsd"]
+    eps = gen_eps(O, V, o, seed=gold3["seed"])
+    assert _digest(eps) == gold3["eps_sha256"]
+    probe = device_cholesky_block([0, 1, 37, 1999], [0, 59, 60, 359], [1, 77, 300, 659], O, V,
+                                  gold3["seed"])
+    assert _digest(probe) == gold3["probe_sha256"]
+    t1 = np.zeros((V, O))
+    tt = gold3["t1"]
+    t1[np.ix_(tt["rows"], tt["cols"])] = np.array(tt["values"]).reshape(len(tt["rows"]),
+                                                                        len(tt["cols"]))
+    _, x2 = gen_amplitudes(O, V, o, v, seed=gold3["x2_seed"], scale1=0.0,
+                           scale2=gold3["x2_scale"])
+    assert _digest(x2) == gold3["x2_sha256"]
+    M = o * v
+    P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlccsd3", precision=precision,
+                     n_chol=J, seed=gold3["seed"], ccsd_space=(ot, vt))
+    P.set_amplitudes(t1, x2.reshape(M, M))
+    del x2
+    om1, om2, _, _ = P.residual()
+    P.close()
+    q = np.array(gold3["quads"])
+    got2 = om2[q[:, 0] * o + q[:, 1], q[:, 2] * o + q[:, 3]]
+    want2 = np.array(gold3["omega2"])
+    pr = np.array(gold3["pairs"])
+    got1 = om1[pr[:, 0], pr[:, 1]]
+    want1 = np.array(gold3["omega1"])
+    # longest reductions: J, the pair count and the ladder's v^2; about eight
+    # chained contractions from L to the doubles
+    tol = 1e-10 if precision == "fp64" else tol_chain(precision, max(J, M, v * v), 8)
+    assert np.abs(got2 - want2).max() <= tol * np.abs(want2).max()
+    assert np.abs(got1 - want1).max() <= tol * np.abs(want1).max()

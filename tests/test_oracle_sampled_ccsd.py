@@ -1,0 +1,124 @@
+"""Pins of the sampled three-level MLCCSD residual (oracle/sampled_ccsd.py)
+against the dense oracle (mlcc.mlccsd3_omega) on small problems: every
+doubles element and every singles element, for several CCSD spaces inside the
+CC2 space, with singles amplitudes of small support and dense ones; planted
+mistakes in the sampled terms fail (CPU only)."""
+import numpy as np
+import pytest
+
+from oracle import mlcc as om
+from oracle import sampled as sm
+from oracle import sampled_ccsd as sc
+from paper_2006_05226_amd.synth import gen_amplitudes, gen_inputs
+
+# (O, V, J, o, v, o_t, v_t)
+SHAPES = [(6, 16, 24, 4, 7, 2, 3), (5, 12, 20, 5, 6, 5, 6), (6, 14, 22, 4, 6, 1, 6),
+          (5, 12, 20, 3, 5, 0, 0)]
+
+
+def setup(shape, kind, seed=3):
+    O, V, J, o, v, ot, vt = shape
+    inp = gen_inputs(O, V, J, o, v, seed=seed)
+    d = om.Dims(O, V, o, v)
+    t1_dense, x2 = gen_amplitudes(O, V, o, v, seed=seed + 1, scale1=0.05, scale2=0.05)
+    if kind == "sparse":
+        t1 = np.zeros((V, O))
+        rows, cols = [0, 2, V - 3], [1, O - 1]
+        t1[np.ix_(rows, cols)] = t1_dense[np.ix_(rows, cols)]
+    else:
+        t1 = t1_dense
+    return inp, d, sm.DenseSource(inp.L), t1, x2
+
+
+def all_quads(d):
+    return [(a, i, b, j) for a in range(d.v) for i in range(d.o) for b in range(d.v)
+            for j in range(d.o)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("kind", ["sparse", "dense"])
+def test_doubles_and_singles_equal_dense(shape, kind):
+    inp, d, src, t1, x2 = setup(shape, kind)
+    ot, vt = shape[5], shape[6]
+    ref1, ref2 = om.mlccsd3_omega(inp.L, inp.eps, d, ot, vt, t1, x2)
+    quads = all_quads(d)
+    got2 = sc.mlccsd3_omega2_samples(src, inp.eps, d, ot, vt, t1, x2, quads)
+    want2 = np.array([ref2[q] for q in quads])
+    assert np.abs(got2 - want2).max() <= 1e-12 * np.abs(want2).max()
+    pairs = [(A, I) for A in range(d.V) for I in range(d.O)]
+    got1 = sc.mlccsd3_omega1_samples(src, inp.eps, d, t1, x2, pairs)
+    want1 = np.array([ref1[p] for p in pairs])
+    assert np.abs(got1 - want1).max() <= 1e-12 * np.abs(want1).max()
+
+
+def _plant(monkeypatch, which):
+    """Replace one sampled term by a plausible mistake."""
+    if which == "ladder":      # the ladder sum dropped
+        orig = sc.Blocks.omega2
+
+        def omega2(self, a, i, b, j, ccsd):
+            v = orig(self, a, i, b, j, ccsd)
+            if ccsd:
+                g = self.vv[:, a, :].T @ self.vv[:, b, :]
+                v = v - np.sum(self.t[:, i, :, j] * g)
+            return v
+        monkeypatch.setattr(sc.Blocks, "omega2", omega2)
+    elif which == "exchange":  # C2's second term with i and j not exchanged
+        def _R(self, a, i, b, j):
+            t, u = self.t, self.u
+            C2 = (-0.5 * np.sum(t[b, :, :, j].T * self._Y(a, i))
+                  - np.sum(t[b, :, :, j].T * self._Y(a, j)))
+            D2 = 0.5 * np.sum(u[b, j].T * self._Z(a, i))
+            E2 = t[a, i, :, j] @ self.Wvv[b, :] - t[a, i, b, :] @ self.Woo[:, j]
+            return C2 + D2 + E2
+        monkeypatch.setattr(sc.Blocks, "_R", _R)
+    elif which == "sign":      # the occupied E2 intermediate added, not subtracted
+        def _R(self, a, i, b, j):
+            t, u = self.t, self.u
+            C2 = (-0.5 * np.sum(t[b, :, :, j].T * self._Y(a, i))
+                  - np.sum(t[b, :, :, i].T * self._Y(a, j)))
+            D2 = 0.5 * np.sum(u[b, j].T * self._Z(a, i))
+            E2 = t[a, i, :, j] @ self.Wvv[b, :] + t[a, i, b, :] @ self.Woo[:, j]
+            return C2 + D2 + E2
+        monkeypatch.setattr(sc.Blocks, "_R", _R)
+
+
+@pytest.mark.parametrize("which", ["ladder", "exchange", "sign"])
+def test_planted_mistakes_fail(monkeypatch, which):
+    shape = SHAPES[0]
+    inp, d, src, t1, x2 = setup(shape, "dense")
+    ot, vt = shape[5], shape[6]
+    _, ref2 = om.mlccsd3_omega(inp.L, inp.eps, d, ot, vt, t1, x2)
+    quads = [q for q in all_quads(d) if q[0] < vt and q[2] < vt and q[1] < ot and q[3] < ot]
+    _plant(monkeypatch, which)
+    got = sc.mlccsd3_omega2_samples(src, inp.eps, d, ot, vt, t1, x2, quads)
+    want = np.array([ref2[q] for q in quads])
+    assert np.abs(got - want).max() > 1e-6 * np.abs(want).max()
+
+
+def test_fullsize_golden_inputs_match_generator():
+    """The stored full-size samples were made from the inputs the generator
+    gives now (eps, a probe of the device-drawn Cholesky vectors, the doubles)."""
+    import hashlib
+    import json
+    import os
+    from paper_2006_05226_amd.synth import CONFIGS, device_cholesky_block, gen_eps
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "samples_mlccsd3_60_600_2000.json")
+    with open(path) as f:
+        gold = json.load(f)
+    c = CONFIGS[gold["config"]]
+    O, V, o, v = c["n_occ"], c["n_vir"], c["n_occ_act"], c["n_vir_act"]
+
+    def digest(a):
+        return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()[:16]
+    assert digest(gen_eps(O, V, o, seed=gold["seed"])) == gold["eps_sha256"]
+    probe = device_cholesky_block([0, 1, 37, 1999], [0, 59, 60, 359], [1, 77, 300, 659], O, V,
+                                  gold["seed"])
+    assert digest(probe) == gold["probe_sha256"]
+    _, x2 = gen_amplitudes(O, V, o, v, seed=gold["x2_seed"], scale1=0.0, scale2=gold["x2_scale"])
+    assert digest(x2) == gold["x2_sha256"]
+    q = np.array(gold["quads"])
+    inner = (q[:, 0] < c["n_vir_ccsd"]) & (q[:, 2] < c["n_vir_ccsd"]) & \
+        (q[:, 1] < c["n_occ_ccsd"]) & (q[:, 3] < c["n_occ_ccsd"])
+    assert inner.sum() >= 60 and (~inner).sum() >= 30
