@@ -16,7 +16,8 @@ evaluated at the sample:
   Omega_aibj = A2 + B2 + R_aibj + R_bjai,  R = C2 + D2 + E2   (CCSD space)
   Omega_aibj = g~_aibj + eps_aibj x_aibj                      (elsewhere)
 
-and the singles are sampled.omega1_samples with the given doubles x2.
+and the singles are sampled.omega1_samples with the given doubles x2.  The
+Jacobian transformation follows by complex step on the same evaluation.
 
 Pinned by tests/test_oracle_sampled_ccsd.py against mlcc.mlccsd3_omega.
 """
@@ -111,3 +112,17 @@ def mlccsd3_omega1_samples(Lsrc, eps, d: Dims, t1, x2, pairs, act=None):
     """Omega_AI of the three-level model at (A, I): the singles of
     exp(-X) H exp(X) with the doubles x2 of the whole active space."""
     return sm.omega1_samples(Lsrc, eps, d, t1, pairs, act=act, x2=x2)
+
+
+def mlccsd3_sigma_samples(Lsrc, eps, d: Dims, o_t, v_t, t1, x2, c1, c2, quads, pairs, h=1e-30):
+    """Jacobian transformation sigma = A c of the three-level model (the
+    derivative of the residual, Sec. 2.1) at sampled doubles and singles, by
+    complex step: sigma = Im Omega(t1 + i h c1, x2 + i h c2) / h, every step
+    of the residual above being analytic in the amplitudes.  c1 (V, O),
+    c2 (v, o, v, o) symmetric."""
+    tc = t1.astype(complex) + 1j * h * c1
+    xc = x2.astype(complex) + 1j * h * c2
+    B = Blocks(Lsrc, eps, d, tc, xc)
+    s2 = mlccsd3_omega2_samples(Lsrc, eps, d, o_t, v_t, tc, xc, quads, blocks=B).imag / h
+    s1 = mlccsd3_omega1_samples(Lsrc, eps, d, tc, xc, pairs).imag / h
+    return s1, s2

@@ -170,6 +170,37 @@ def _digest(a):
     return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()[:16]
 
 
+def _inputs3(gold):
+    """The inputs the stored samples were made from, checked by digest."""
+    from paper_2006_05226_amd.synth import CONFIGS, gen_eps
+    c = CONFIGS[gold["config"]]
+    O, V, o, v = c["n_occ"], c["n_vir"], c["n_occ_act"], c["n_vir_act"]
+    eps = gen_eps(O, V, o, seed=gold["seed"])
+    assert _digest(eps) == gold["eps_sha256"]
+    t1 = np.zeros((V, O))
+    tt = gold["t1"]
+    t1[np.ix_(tt["rows"], tt["cols"])] = np.array(tt["values"]).reshape(len(tt["rows"]),
+                                                                        len(tt["cols"]))
+    _, x2 = gen_amplitudes(O, V, o, v, seed=gold["x2_seed"], scale1=0.0, scale2=gold["x2_scale"])
+    assert _digest(x2) == gold["x2_sha256"]
+    return c, eps, t1, x2
+
+
+def _problem3(ctx, c, eps, t1, x2, seed, precision):
+    O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
+    P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlccsd3", precision=precision,
+                     n_chol=J, seed=seed, ccsd_space=(c["n_occ_ccsd"], c["n_vir_ccsd"]))
+    P.set_amplitudes(t1, x2.reshape(o * v, o * v))
+    return P
+
+
+def _tol3(c, precision):
+    # longest reductions: J, the pair count and the ladder's v^2; about eight
+    # chained contractions from L to the doubles
+    o, v = c["n_occ_act"], c["n_vir_act"]
+    return 1e-10 if precision == "fp64" else tol_chain(precision, max(c["n_chol"], o * v, v * v), 8)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
 def test_fullsize_sampled_parity(ctx, gold3, precision):
     """The three-level residual at full size (60/600/2000, CC2 space 30/300,
@@ -177,27 +208,14 @@ def test_fullsize_sampled_parity(ctx, gold3, precision):
     element against the sampled oracle (tests/golden/make_mlccsd3_samples.py:
     doubles inside, across and outside the CCSD space, singles across every
     orbital space), at sparse singles and doubles over the whole CC2 space."""
-    from paper_2006_05226_amd.synth import CONFIGS, device_cholesky_block, gen_eps
+    from paper_2006_05226_amd.synth import device_cholesky_block
     print(f"mlccsd3 full-size sampled parity {precision}", flush=True)
-    c = CONFIGS[gold3["config"]]
-    O, V, J, o, v = c["n_occ"], c["n_vir"], c["n_chol"], c["n_occ_act"], c["n_vir_act"]
-    ot, vt = c["n_occ_ccsd"], c["n_vir_ccsd"]
-    eps = gen_eps(O, V, o, seed=gold3["seed"])
-    assert _digest(eps) == gold3["eps_sha256"]
-    probe = device_cholesky_block([0, 1, 37, 1999], [0, 59, 60, 359], [1, 77, 300, 659], O, V,
-                                  gold3["seed"])
+    c, eps, t1, x2 = _inputs3(gold3)
+    probe = device_cholesky_block([0, 1, 37, 1999], [0, 59, 60, 359], [1, 77, 300, 659],
+                                  c["n_occ"], c["n_vir"], gold3["seed"])
     assert _digest(probe) == gold3["probe_sha256"]
-    t1 = np.zeros((V, O))
-    tt = gold3["t1"]
-    t1[np.ix_(tt["rows"], tt["cols"])] = np.array(tt["values"]).reshape(len(tt["rows"]),
-                                                                        len(tt["cols"]))
-    _, x2 = gen_amplitudes(O, V, o, v, seed=gold3["x2_seed"], scale1=0.0,
-                           scale2=gold3["x2_scale"])
-    assert _digest(x2) == gold3["x2_sha256"]
-    M = o * v
-    P = mlcc.Problem(ctx, None, eps, O, V, o, v, model="mlccsd3", precision=precision,
-                     n_chol=J, seed=gold3["seed"], ccsd_space=(ot, vt))
-    P.set_amplitudes(t1, x2.reshape(M, M))
+    o = c["n_occ_act"]
+    P = _problem3(ctx, c, eps, t1, x2, gold3["seed"], precision)
     del x2
     om1, om2, _, _ = P.residual()
     P.close()
@@ -207,8 +225,48 @@ def test_fullsize_sampled_parity(ctx, gold3, precision):
     pr = np.array(gold3["pairs"])
     got1 = om1[pr[:, 0], pr[:, 1]]
     want1 = np.array(gold3["omega1"])
-    # longest reductions: J, the pair count and the ladder's v^2; about eight
-    # chained contractions from L to the doubles
-    tol = 1e-10 if precision == "fp64" else tol_chain(precision, max(J, M, v * v), 8)
+    tol = _tol3(c, precision)
+    assert np.abs(got2 - want2).max() <= tol * np.abs(want2).max()
+    assert np.abs(got1 - want1).max() <= tol * np.abs(want1).max()
+
+
+GOLD3J = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "samples_mlccsd3_60_600_2000_jacobian.json")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+def test_fullsize_sampled_jacobian_parity(ctx, precision):
+    """The three-level Jacobian transformation at full size element by element
+    against the sampled oracle's complex step (make_mlccsd3_samples.py
+    --jacobian), for a trial vector with sparse singles and doubles over the
+    whole CC2 space, at the amplitudes of the residual test."""
+    from paper_2006_05226_amd.synth import gen_vectors
+    print(f"mlccsd3 full-size sampled Jacobian parity {precision}", flush=True)
+    with open(GOLD3J) as f:
+        gold = json.load(f)
+    c, eps, t1, x2 = _inputs3(gold)
+    O, V, o, v = c["n_occ"], c["n_vir"], c["n_occ_act"], c["n_vir_act"]
+    M = o * v
+    c1 = np.zeros((V, O))
+    cc = gold["c1"]
+    c1[np.ix_(cc["rows"], cc["cols"])] = np.array(cc["values"]).reshape(len(cc["rows"]),
+                                                                        len(cc["cols"]))
+    _, c2 = gen_vectors(1, O, V, M, seed=gold["c2_seed"])
+    c2 = c2[0]
+    assert _digest(c2) == gold["c2_sha256"]
+    P = _problem3(ctx, c, eps, t1, x2, gold["seed"], precision)
+    del x2
+    sig = P.jacobian_transform(np.concatenate([c1.ravel(), c2.ravel()])[None])
+    P.close()
+    n1 = V * O
+    s1 = sig[0, :n1].reshape(V, O)
+    s2 = sig[0, n1:].reshape(M, M)
+    q = np.array(gold["quads"])
+    got2 = s2[q[:, 0] * o + q[:, 1], q[:, 2] * o + q[:, 3]]
+    want2 = np.array(gold["sigma2"])
+    pr = np.array(gold["pairs"])
+    got1 = s1[pr[:, 0], pr[:, 1]]
+    want1 = np.array(gold["sigma1"])
+    tol = _tol3(c, precision)
     assert np.abs(got2 - want2).max() <= tol * np.abs(want2).max()
     assert np.abs(got1 - want1).max() <= tol * np.abs(want1).max()
