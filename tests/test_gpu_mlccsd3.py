@@ -201,7 +201,7 @@ def _tol3(c, precision):
     return 1e-10 if precision == "fp64" else tol_chain(precision, max(c["n_chol"], o * v, v * v), 8)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_fullsize_sampled_parity(ctx, gold3, precision):
     """The three-level residual at full size (60/600/2000, CC2 space 30/300,
     CCSD space 12/120, Cholesky vectors drawn on the device) element by
@@ -234,7 +234,7 @@ GOLD3J = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
                       "samples_mlccsd3_60_600_2000_jacobian.json")
 
 
-@pytest.mark.parametrize("precision", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_fullsize_sampled_jacobian_parity(ctx, precision):
     """The three-level Jacobian transformation at full size element by element
     against the sampled oracle's complex step (make_mlccsd3_samples.py
