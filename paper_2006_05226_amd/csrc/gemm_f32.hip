@@ -21,6 +21,9 @@ const gk::PlaneTile kSplitPlanes[] = {MLCC_GEMM_TILES_PLANES(MLCC_TILE_ENTRY)};
 #define MLCC_TILE_ENTRY(BMv, BNv, WMv, WNv, KSv, NSv) {BMv, BNv, WMv * WNv, KSv, &gk::launch_planes<float, BMv, BNv, WMv, WNv, true, KSv, NSv>, &gk::planes_occupancy<float, BMv, BNv, WMv, WNv, true, KSv, NSv>},
 const gk::PlaneTile kPlainPlanes[] = {MLCC_GEMM_TILES_PLANES_PLAIN(MLCC_TILE_ENTRY)};
 #undef MLCC_TILE_ENTRY
+#define MLCC_TILE_ENTRY(BMv, BNv, WMv, WNv, KSv, NSv) {BMv, BNv, WMv * WNv, KSv, &gk::launch_planes<float, BMv, BNv, WMv, WNv, true, KSv, NSv, true>, &gk::planes_occupancy<float, BMv, BNv, WMv, WNv, true, KSv, NSv, true>},
+const gk::PlaneTile kF32Planes[] = {MLCC_GEMM_TILES_PLANES_F32(MLCC_TILE_ENTRY)};
+#undef MLCC_TILE_ENTRY
 template <typename T, int N> constexpr int count(const T (&)[N]) { return N; }
 }  // namespace
 
@@ -37,6 +40,8 @@ void gemm_f32(Exec &ex, const GemmArgs &a) {
     }
   } else if (gk::planes_any_layout(ex, a)) {
     gk::gemm_planes<float>(ex, a, false, kSplitPlanes, count(kSplitPlanes));
+  } else if (!a.bf16x3 && gk::use_planes_f32(ex, a)) {
+    gk::gemm_planes_f32<float>(ex, a, kF32Planes, count(kF32Planes));
   } else if (a.K > 0 && a.R > 0 && gk::gemm_vonly(a, gk::Tr<float>::VEC)) {
     gk::dispatch_load<float, float>(ex, a, kTiles, count(kTiles), 16.0);
   } else {

@@ -145,7 +145,11 @@ template <int CH> __device__ __forceinline__ int plane_swz(int r) { return (r >>
 // Fragments of one k-step (KS = 32 or 64 BF16, one or two MFMA k-slices) of a
 // wave, read from a stage of LDS (A planes at As, B planes at Bs, each plane
 // rows x KS BF16 with swizzled chunks); sw: this lane's swizzle.
-template <int FM, int FN, int WTM, int WTN, bool PLAIN, int KS> struct PlaneFrags {
+// F32: the plane holds FP32 values (a plain plane of 4-byte elements, each
+// 16-byte chunk four consecutive k); a chunk then feeds four
+// v_mfma_f32_16x16x4f32, lane group g taking k = 4 g + s in the s-th (the
+// same order in A and B, so the sum over a k-step is only reordered).
+template <int FM, int FN, int WTM, int WTN, bool PLAIN, int KS, bool F32 = false> struct PlaneFrags {
   static constexpr int NS = KS / kPlaneBK;
   bf8v ah[NS][FM], al[NS][PLAIN ? 1 : FM], bh[NS][FN], bl[NS][PLAIN ? 1 : FN];
   __device__ __forceinline__ void read(const __bf16 *As, int plane_a, const __bf16 *Bs, int plane_b,
@@ -170,6 +174,20 @@ template <int FM, int FN, int WTM, int WTN, bool PLAIN, int KS> struct PlaneFrag
   // the products: all hi*hi first, then hi*lo, then lo*hi, so that
   // consecutive MFMAs never accumulate into the same registers
   __device__ __forceinline__ void mma(f4 (&acc)[FM][FN]) const {
+    if constexpr (F32) {
+#pragma unroll
+      for (int u = 0; u < NS; ++u)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(__builtin_bit_cast(f4, ah[u][i])[s],
+                                                              __builtin_bit_cast(f4, bh[u][j])[s],
+                                                              acc[i][j], 0, 0, 0);
+      return;
+    }
 #pragma unroll
     for (int u = 0; u < NS; ++u)
 #pragma unroll
@@ -211,8 +229,9 @@ template <int WM, int WN> struct PlaneWaves {
   static constexpr int NT = 64 * WM * WN;
 };
 
-template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS, int NSTG>
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS, int NSTG, bool F32 = false>
 __global__ __launch_bounds__((PlaneWaves<WM, WN>::NT)) void k_gemm_planes(KParams kp, PlaneOps po) {
+  static_assert(!F32 || PLAIN, "FP32 planes are one plane");
   constexpr int NW = WM * WN, WTM = BM / WM, WTN = BN / WN, FM = WTM / 16, FN = WTN / 16;
   constexpr int PL = PLAIN ? 1 : 2;
   constexpr int CH = KS / 8, RPL = 512 / KS;  // 16-byte chunks per row, rows per 1 KB load
@@ -335,7 +354,7 @@ __global__ __launch_bounds__((PlaneWaves<WM, WN>::NT)) void k_gemm_planes(KParam
       if (half == 0) wait_stage(step);
       barrier();
       if (half == 0 && step + NSTG - 1 < s_end) issue(cur == 0 ? NSTG - 1 : cur - 1, step + NSTG - 1);
-      PlaneFrags<FM, FN, WTM, WTN, PLAIN, KS> fr;
+      PlaneFrags<FM, FN, WTM, WTN, PLAIN, KS, F32> fr;
       const __bf16 *As = lds + cur * STAGE;
       fr.read(As, RA, As + PL * RA, RB, wm, wn, l16, g, sw);
       asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
@@ -358,7 +377,7 @@ __global__ __launch_bounds__((PlaneWaves<WM, WN>::NT)) void k_gemm_planes(KParam
       __builtin_amdgcn_sched_barrier(0);
       asm volatile("s_barrier" ::: "memory");
       __builtin_amdgcn_sched_barrier(0);
-      PlaneFrags<FM, FN, WTM, WTN, PLAIN, KS> fr;
+      PlaneFrags<FM, FN, WTM, WTN, PLAIN, KS, F32> fr;
       const __bf16 *As = lds + cur * STAGE;
       fr.read(As, RA, As + PL * RA, RB, wm, wn, l16, g, sw);
       if (step + NSTG - 1 < s_end) issue(cur == 0 ? NSTG - 1 : cur - 1, step + NSTG - 1);
@@ -413,7 +432,7 @@ inline void pack_planes(Exec &ex, PackArgs pa) {
   MLCC_HIP(hipGetLastError());
 }
 
-template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS, int NSTG>
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS, int NSTG, bool F32 = false>
 void launch_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad, int splits) {
   KParams kp;
   kp.a = a;
@@ -428,7 +447,7 @@ void launch_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad
   MLCC_REQUIRE(kp.per_xcd * kXcd < (int64_t)1 << 31, MLCC_E_ARG, "gemm: grid too large");
   kp.work = nullptr;
   if (splits > 1) kp.work = ex.scratch(sizeof(float) * (size_t)splits * a.Z * a.M * a.N);
-  hipLaunchKernelGGL((k_gemm_planes<TC, BM, BN, WM, WN, PLAIN, KS, NSTG>), dim3((unsigned)(kp.per_xcd * kXcd)),
+  hipLaunchKernelGGL((k_gemm_planes<TC, BM, BN, WM, WN, PLAIN, KS, NSTG, F32>), dim3((unsigned)(kp.per_xcd * kXcd)),
                      dim3(64 * WM * WN), 0, ex.stream, kp, po);
   MLCC_HIP(hipGetLastError());
   if (splits > 1) {
@@ -439,12 +458,12 @@ void launch_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad
   }
 }
 
-template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS, int NSTG>
+template <typename TC, int BM, int BN, int WM, int WN, bool PLAIN, int KS, int NSTG, bool F32 = false>
 int planes_occupancy(const GemmArgs &) {
   static std::atomic<int> cache{0};
   int nb = cache.load(std::memory_order_relaxed);
   if (nb > 0) return nb;
-  const void *f = reinterpret_cast<const void *>(&k_gemm_planes<TC, BM, BN, WM, WN, PLAIN, KS, NSTG>);
+  const void *f = reinterpret_cast<const void *>(&k_gemm_planes<TC, BM, BN, WM, WN, PLAIN, KS, NSTG, F32>);
   MLCC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, 64 * WM * WN, 0));
   nb = std::max(nb, 1);
   cache.store(nb, std::memory_order_relaxed);
@@ -486,6 +505,39 @@ inline bool use_planes(const Exec &ex, const GemmArgs &a, bool plain, double rat
 // there as their accuracy study measured.
 inline bool planes_any_layout(const Exec &ex, const GemmArgs &a) {
   return a.bf16x3 && !a.bf16_plain && a.K > 0 && a.R > 0 && use_planes(ex, a, false, 40.0);
+}
+
+// Run the product on packed planes (kpad: the plane row length in 2-byte
+// units) with the tile of the lowest modelled cost.
+inline void run_planes(Exec &ex, const GemmArgs &a, const PlaneOps &po, int64_t kpad,
+                       const PlaneTile *tiles, int ntiles) {
+  const int64_t ncu = cu_count();
+  int forced = -1;
+  for (int t = 0; t < ntiles; ++t)
+    if (tiles[t].bm == ex.force_bm && tiles[t].bn == ex.force_bn) forced = t;
+  int best = -1, best_s = 1;
+  double best_cost = 0.0;
+  for (int t = 0; t < ntiles; ++t) {
+    if (forced >= 0 && t != forced) continue;
+    const int bm = tiles[t].bm, bn = tiles[t].bn;
+    const int64_t occ = tiles[t].occ(a), steps = kpad / tiles[t].ks;
+    const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
+    int64_t s = 1;
+    if (blocks < occ * ncu && steps >= 8)
+      s = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(occ * ncu / blocks, steps / 4), 128));
+    const int64_t rounds = cdiv(blocks * s, occ * ncu);
+    const double rate = tiles[t].waves == 8 ? 1.13 : 1.0;
+    double cost = (double)rounds * (double)cdiv(steps, s) * tiles[t].ks * bm * bn * occ / rate;
+    if (s > 1) cost += 2.0 * (double)s * a.Z * a.M * a.N;
+    if (best < 0 || cost < best_cost) {
+      best = t;
+      best_s = (int)s;
+      best_cost = cost;
+    }
+  }
+  ex.last_bm = tiles[best].bm;
+  ex.last_bn = tiles[best].bn;
+  tiles[best].fn(ex, a, po, kpad, best_s);
 }
 
 // Pack both operands and run the product with the tile of the lowest
@@ -531,33 +583,132 @@ void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles
   pa.hi = const_cast<__bf16 *>(po.bh); pa.lo_plane = const_cast<__bf16 *>(po.bl);
   pack_planes(ex, pa);
 
-  const int64_t ncu = cu_count();
-  int forced = -1;
-  for (int t = 0; t < ntiles; ++t)
-    if (tiles[t].bm == ex.force_bm && tiles[t].bn == ex.force_bn) forced = t;
-  int best = -1, best_s = 1;
-  double best_cost = 0.0;
-  for (int t = 0; t < ntiles; ++t) {
-    if (forced >= 0 && t != forced) continue;
-    const int bm = tiles[t].bm, bn = tiles[t].bn;
-    const int64_t occ = tiles[t].occ(a), steps = g.kp / tiles[t].ks;
-    const int64_t blocks = cdiv(a.M, bm) * cdiv(a.N, bn) * a.Z;
-    int64_t s = 1;
-    if (blocks < occ * ncu && steps >= 8)
-      s = std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(occ * ncu / blocks, steps / 4), 128));
-    const int64_t rounds = cdiv(blocks * s, occ * ncu);
-    const double rate = tiles[t].waves == 8 ? 1.13 : 1.0;
-    double cost = (double)rounds * (double)cdiv(steps, s) * tiles[t].ks * bm * bn * occ / rate;
-    if (s > 1) cost += 2.0 * (double)s * a.Z * a.M * a.N;
-    if (best < 0 || cost < best_cost) {
-      best = t;
-      best_s = (int)s;
-      best_cost = cost;
+  run_planes(ex, a, po, g.kp, tiles, ntiles);
+  if (ev.first) {
+    MLCC_HIP(hipEventRecord(ev.second, ex.stream));
+    ex.prof->recs.push_back({a.tag, ev.first, ev.second, 2.0 * (double)a.M * a.N * a.K * a.R * a.Z});
+  }
+}
+
+// FP32 products on the planes kernel: each operand copied once as
+// [batch][row][k'] FP32 (rows padded to kPlaneRowPad, k' to kPlaneKPad / 2,
+// padding zero), streamed into LDS by the same direct loads and multiplied
+// by v_mfma_f32_16x16x4f32 (the kernel's F32 mode).  Operands contiguous
+// along k only.  One thread per 8 consecutive k' of one row.
+template <typename T> __global__ __launch_bounds__(256) void k_pack_f32(PackArgs a, T *out) {
+  const int64_t chunks = a.kp / 8;
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= a.Z * a.rows_p * chunks) return;
+  const int64_t rz = t / chunks, ch = t - rz * chunks;
+  const int64_t z = rz / a.rows_p, m = rz - z * a.rows_p;
+  const int64_t k0 = ch * 8, KK = a.R * a.K;
+  f4 v0 = f4{0.0f, 0.0f, 0.0f, 0.0f}, v1 = v0;
+  if (m < a.rows) {
+    const float *X = a.X + z * a.s_z + two_level(m, a.lo, a.s_row, a.s_hi);
+    if (a.vec4) {
+      const int64_t r0 = k0 / a.K, r1 = (k0 + 4) / a.K;
+      if (k0 < KK) v0 = *reinterpret_cast<const f4 *>(X + r0 * a.s_r + (k0 - r0 * a.K));
+      if (k0 + 4 < KK) v1 = *reinterpret_cast<const f4 *>(X + r1 * a.s_r + (k0 + 4 - r1 * a.K));
+    } else {
+      int64_t r = k0 / a.K, k = k0 - r * a.K;
+      float x[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        x[q] = k0 + q < KK ? X[r * a.s_r + k] : 0.0f;
+        if (++k == a.K) {
+          k = 0;
+          ++r;
+        }
+      }
+      v0 = f4{x[0], x[1], x[2], x[3]};
+      v1 = f4{x[4], x[5], x[6], x[7]};
     }
   }
-  ex.last_bm = tiles[best].bm;
-  ex.last_bn = tiles[best].bn;
-  tiles[best].fn(ex, a, po, g.kp, best_s);
+  const int64_t o = rz * a.kp + k0;
+  *reinterpret_cast<f4 *>(out + o) = v0;
+  *reinterpret_cast<f4 *>(out + o + 4) = v1;
+}
+
+inline void pack_f32(Exec &ex, PackArgs pa, float *out) {
+  MLCC_REQUIRE(pa.s_k == 1, MLCC_E_STATE, "gemm: FP32 planes need operands contiguous along k");
+  const bool lo_ok = pa.lo <= 0 || pa.s_hi % 4 == 0;
+  pa.vec4 = pa.K % 4 == 0 && pa.s_row % 4 == 0 && pa.s_r % 4 == 0 && pa.s_z % 4 == 0 && lo_ok &&
+            reinterpret_cast<uintptr_t>(pa.X) % 16 == 0;
+  const int64_t blocks = cdiv(pa.Z * pa.rows_p * (pa.kp / 8), 256);
+  MLCC_REQUIRE(blocks < ((int64_t)1 << 31), MLCC_E_ARG, "gemm: operand planes too large");
+  hipLaunchKernelGGL(k_pack_f32<float>, dim3((unsigned)blocks), dim3(256), 0, ex.stream, pa, out);
+  MLCC_HIP(hipGetLastError());
+}
+
+struct F32Geom {
+  int64_t mp, np, kpf, za, zb;
+  size_t bytes_a, bytes_b;
+  size_t total() const { return bytes_a + bytes_b; }
+};
+inline F32Geom f32_geom(const GemmArgs &a) {
+  F32Geom g;
+  g.mp = round_up(a.M, kPlaneRowPad);
+  g.np = round_up(a.N, kPlaneRowPad);
+  g.kpf = round_up(a.R * a.K, kPlaneKPad / 2);
+  g.za = a.sAz ? a.Z : 1;
+  g.zb = a.sBz ? a.Z : 1;
+  g.bytes_a = sizeof(float) * (size_t)g.za * g.mp * g.kpf;
+  g.bytes_b = sizeof(float) * (size_t)g.zb * g.np * g.kpf;
+  return g;
+}
+
+// Whether an FP32 product runs on FP32 planes: operands contiguous along k,
+// no caller workspace, planes within the lane's cap; by default from 4 GFLOP
+// and 300 flops per byte the packing moves (it reads and writes 4 bytes per
+// operand element).  Measured: the 3601 x 5000 x 5000 (x 5) product (~750
+// flops per byte) 108.6 -> 118.0 TFLOP/s with packing; the 40/400/1200 MLCC2
+// transformation (~135) 3.6% slower on planes, so below the rule.  The
+// outputs must also fill at least 85% of the padded plane rows x columns:
+// the CCS product with 150 rows (padded to 256) ran 19.0 ms on planes
+// against 13.6 on the FP32 kernel.
+inline bool use_planes_f32(const Exec &ex, const GemmArgs &a) {
+  if (a.work || ex.planes_mode < 0 || a.K <= 0 || a.R <= 0 || a.sAk != 1 || a.sBk != 1) return false;
+  const F32Geom g = f32_geom(a);
+  if (g.total() > ex.planes_cap) return false;
+  if (ex.planes_mode > 0) return true;
+  const double flops = 2.0 * (double)a.M * a.N * a.K * a.R * a.Z;
+  const double fill = (double)a.M * a.N / ((double)g.mp * g.np);
+  return flops >= 4e9 && flops >= 300.0 * 2.0 * (double)g.total() && fill >= 0.85;
+}
+
+template <typename TC>
+void gemm_planes_f32(Exec &ex, const GemmArgs &a, const PlaneTile *tiles, int ntiles) {
+  const F32Geom g = f32_geom(a);
+  MLCC_REQUIRE(g.total() < ((size_t)1 << 32), MLCC_E_ARG, "gemm: operand planes too large");
+  ex.planes.ensure(ex.al, g.total());
+  float *fa = static_cast<float *>(ex.planes.p), *fb = fa + g.bytes_a / sizeof(float);
+  const int64_t kpad = 2 * g.kpf;  // the kernel counts the plane rows in 2-byte units
+  PlaneOps po;
+  po.ah = reinterpret_cast<const __bf16 *>(fa);
+  po.bh = reinterpret_cast<const __bf16 *>(fb);
+  po.al = po.bl = nullptr;
+  po.a_zs = a.sAz ? g.mp * kpad : 0;
+  po.b_zs = a.sBz ? g.np * kpad : 0;
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  if (ex.prof && ex.prof->on) {
+    ev = ex.prof->next();
+    MLCC_HIP(hipEventRecord(ev.first, ex.stream));
+  }
+  PackArgs pa;
+  pa.X = static_cast<const float *>(a.A);
+  pa.rows = a.M; pa.K = a.K; pa.R = a.R; pa.Z = g.za;
+  pa.s_row = a.sAm; pa.s_r = a.sAr; pa.s_z = a.sAz; pa.s_k = a.sAk;
+  pa.lo = a.Mlo; pa.s_hi = a.sAm_hi;
+  pa.rows_p = g.mp; pa.kp = g.kpf;
+  pa.hi = nullptr; pa.lo_plane = nullptr;
+  pack_f32(ex, pa, fa);
+  pa.X = static_cast<const float *>(a.B);
+  pa.rows = a.N; pa.Z = g.zb;
+  pa.s_row = a.sBn; pa.s_r = a.sBr; pa.s_z = a.sBz; pa.s_k = a.sBk;
+  pa.lo = a.Nlo; pa.s_hi = a.sBn_hi;
+  pa.rows_p = g.np;
+  pack_f32(ex, pa, fb);
+  run_planes(ex, a, po, kpad, tiles, ntiles);
   if (ev.first) {
     MLCC_HIP(hipEventRecord(ev.second, ex.stream));
     ex.prof->recs.push_back({a.tag, ev.first, ev.second, 2.0 * (double)a.M * a.N * a.K * a.R * a.Z});
@@ -584,4 +735,9 @@ void gemm_planes(Exec &ex, const GemmArgs &a, bool plain, const PlaneTile *tiles
 // Plain products (one plane): k-steps of 64, two MFMA k-slices per barrier.
 #ifndef MLCC_GEMM_TILES_PLANES_PLAIN
 #define MLCC_GEMM_TILES_PLANES_PLAIN(X) X(256, 256, 2, 4, 64, 2) X(128, 128, 2, 2, 64, 2)
+#endif
+// FP32 products on FP32 planes: the F32 mode of the plain kernel, 32 FP32
+// values (128 bytes) per row and k-step.
+#ifndef MLCC_GEMM_TILES_PLANES_F32
+#define MLCC_GEMM_TILES_PLANES_F32(X) X(256, 256, 2, 4, 64, 2) X(128, 128, 2, 2, 64, 2)
 #endif

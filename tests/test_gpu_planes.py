@@ -302,3 +302,39 @@ def test_plain_map_keeps_fp32_for_other_layouts():
     ctx.gemm_planes(1)
     assert np.array_equal(run("bf16"), run("fp32"))
     ctx.close()
+
+
+# FP32 cases: K and the batch-reduced k' of any length (the FP32 packing
+# reads element by element when a row is not 16-byte aligned)
+CASES_F32 = CASES + [(70, 90, 33, 2, 2, False), (257, 129, 7, 3, 1, True)]
+
+
+@pytest.mark.parametrize("case", CASES_F32)
+def test_f32_planes_products(case):
+    """FP32 products on FP32 planes (the planes kernel's FP32 mode, forced)
+    against the FP64 product: FP32 accumulation error only, and the same
+    result bounds as the FP32 kernel they replace."""
+    M, N, K, R, Z, a_shared = case
+    ctx = mlcc.Context(0)
+    rng = np.random.default_rng(abs(hash(("f32",) + case)) % 2**32)
+    sA = [K, 1, M * K, 0 if a_shared else M * K * R]
+    sB = [1, K, K * N, K * N * R]
+    A = rng.standard_normal(M * K * R * (1 if a_shared else Z)).astype(np.float32)
+    B = rng.standard_normal(K * N * R * Z).astype(np.float32)
+    ref = batched(A.astype(np.float64), sA, B.astype(np.float64), sB, M, N, K, R, Z)
+    Ad, Bd = torch.tensor(A, device="cuda"), torch.tensor(B, device="cuda")
+    outs = []
+    for mode in (1, -1):
+        Cd = torch.zeros(Z * M * N, device="cuda", dtype=torch.float32)
+        ctx.gemm_planes(mode)
+        ctx.gemm(mlcc.FP32, M, N, K, R, Z, 1.0, Ad, sA, Bd, sB, 0.0, Cd, [N, 1, M * N])
+        outs.append(Cd.cpu().numpy().reshape(Z, M, N).astype(np.float64))
+    ctx.gemm_planes(0)
+    # FP32 products and accumulation (the other parity tests' derived bar,
+    # one contraction over K R terms), relative to the largest output
+    from gpu_util import tol_chain
+    scale = np.abs(ref).max()
+    err_planes, err_fp32 = (np.abs(got - ref).max() for got in outs)
+    assert err_planes <= tol_chain("fp32", K * R, 1) * scale
+    assert err_fp32 <= tol_chain("fp32", K * R, 1) * scale
+    assert err_planes <= 2.0 * err_fp32 + 1e-7 * scale
